@@ -1,0 +1,278 @@
+/*
+ * CPU ORACLE for local-max matching -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg call this
+ * code. The product path (the HIP library) never links or calls it, and this
+ * file shares no code, header or constant table with it.
+ *
+ * Plain, single-threaded C99, no fast-math; weights are compared with the
+ * ordinary numeric '>' on float (so -0 == +0).
+ *
+ * What is computed (paper, Section 1, "local max" definition; Section 2,
+ * "Sequential Model"):
+ *   An edge is locally maximal if its key beats the key of every incident
+ *   remaining edge. Each iteration adds every locally maximal edge to M and
+ *   removes all edges incident to newly matched vertices, until no edge is
+ *   left. One iteration is three passes over the remaining edges:
+ *     pass 1: every endpoint x keeps its candidate C[x], the best incident
+ *             edge seen so far (C starts as a dummy edge below every key);
+ *     pass 2: an edge e with C[u] = C[v] = e joins M;
+ *     pass 3: an edge with a matched endpoint is removed; for every other
+ *             edge the candidates of both endpoints go back to the dummy.
+ *   C is initialised once, before the first iteration.
+ *
+ * Tie breaking (the paper perturbs equal weights randomly; the reading fixed
+ * here): key(e) = (w(e), H(e)) compared lexicographically, w numerically and
+ * H as an unsigned 64-bit integer, with H fixed for the whole run:
+ *     S       = mix(seed + GAMMA)              (first SplitMix64 output)
+ *     H(e)    = mix(((uint64)lo << 32 | hi) XOR S),   lo < hi the endpoints
+ * where mix is the SplitMix64 output function (Steele, Lea & Flood, OOPSLA
+ * 2014). mix and XOR with a constant are bijections, so distinct edges get
+ * distinct H and the order on edges is strict.
+ *
+ * Parity pins (checked by tests, not by this file): SplitMix64 published
+ * output vectors pin mix; a sorted greedy scan under the same key, validity,
+ * maximality, brute-force maximum weight matching (1/2 bound), closed forms
+ * for paths/stars/triangles and the Lemma 1 removal fraction pin the loop.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define LMO_GAMMA 0x9E3779B97F4A7C15ULL
+#define LMO_NONE (-1)
+
+/* SplitMix64 output function. */
+uint64_t lmo_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* Per-run seed mix: the first output of a SplitMix64 generator seeded with s. */
+uint64_t lmo_seed_mix(uint64_t seed) { return lmo_mix64(seed + LMO_GAMMA); }
+
+/* Tie-break value of the undirected edge {lo, hi}, lo < hi, local ids. */
+uint64_t lmo_edge_hash(uint64_t seed, int32_t lo, int32_t hi) {
+  uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint64_t)(uint32_t)hi;
+  return lmo_mix64(pair ^ lmo_seed_mix(seed));
+}
+
+typedef struct {
+  int32_t lo, hi;
+  float w;
+  uint64_t h;
+} lmo_edge;
+
+/* key(a) > key(b): weight first, numerically; hash on equal weight. */
+static int key_greater(const lmo_edge* a, const lmo_edge* b) {
+  if (a->w > b->w) return 1;
+  if (a->w < b->w) return 0;
+  return a->h > b->h;
+}
+
+/* Error codes of the oracle entry points. */
+#define LMO_EINVAL (-1)
+#define LMO_ENOMEM (-2)
+
+/* Builds the undirected edge list {lo < hi} from symmetric CSR. Entries with
+ * v < u define the edges; a self-loop or an id out of range is an error. */
+static int64_t edges_from_csr(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, uint64_t seed,
+                              lmo_edge** out) {
+  if (n < 0 || !row_ptr) return LMO_EINVAL;
+  int64_t nnz = row_ptr[n];
+  int64_t m = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (row_ptr[v + 1] < row_ptr[v]) return LMO_EINVAL;
+    for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+      int32_t u = col[k];
+      if (u < 0 || u >= n || u == v) return LMO_EINVAL;
+      if (v < u) ++m;
+    }
+  }
+  (void)nnz;
+  lmo_edge* E = (lmo_edge*)malloc((size_t)(m > 0 ? m : 1) * sizeof(lmo_edge));
+  if (!E) return LMO_ENOMEM;
+  int64_t j = 0;
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+      int32_t u = col[k];
+      if (v < u) {
+        E[j].lo = (int32_t)v;
+        E[j].hi = u;
+        E[j].w = w[k];
+        E[j].h = lmo_edge_hash(seed, (int32_t)v, u);
+        ++j;
+      }
+    }
+  *out = E;
+  return m;
+}
+
+/*
+ * Local-max matching of one graph given as symmetric CSR.
+ *   mate[n]: output, partner id or -1.
+ *   log (optional, log_cap rows of 3 int64): per iteration t = 1.. the number
+ *   of remaining edges |E_t| at its start, the number of vertices with at least
+ *   one remaining edge V_t, and the number of edges matched in it.
+ * Returns the number of iterations (0 for an edgeless graph) or a negative
+ * error code. Iterations beyond log_cap are still run, not logged.
+ */
+int64_t lmo_local_max(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, uint64_t seed,
+                      int32_t* mate, int64_t* log, int64_t log_cap) {
+  lmo_edge* E = NULL;
+  int64_t m = edges_from_csr(n, row_ptr, col, w, seed, &E);
+  if (m < 0) return m;
+  int64_t* C = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  int64_t* seen = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  if (!C || !seen) {
+    free(E);
+    free(C);
+    free(seen);
+    return LMO_ENOMEM;
+  }
+  for (int64_t x = 0; x < n; ++x) {
+    mate[x] = -1;
+    C[x] = LMO_NONE; /* the dummy edge, below every key; set once */
+    seen[x] = 0;
+  }
+  int64_t t = 0;
+  while (m > 0) {
+    ++t;
+    int64_t vt = 0;
+    for (int64_t j = 0; j < m; ++j) {
+      if (seen[E[j].lo] != t) {
+        seen[E[j].lo] = t;
+        ++vt;
+      }
+      if (seen[E[j].hi] != t) {
+        seen[E[j].hi] = t;
+        ++vt;
+      }
+    }
+    /* pass 1: candidates */
+    for (int64_t j = 0; j < m; ++j) {
+      const lmo_edge* e = &E[j];
+      if (C[e->lo] == LMO_NONE || key_greater(e, &E[C[e->lo]])) C[e->lo] = j;
+      if (C[e->hi] == LMO_NONE || key_greater(e, &E[C[e->hi]])) C[e->hi] = j;
+    }
+    /* pass 2: mutual candidates join the matching */
+    int64_t matched = 0;
+    for (int64_t j = 0; j < m; ++j) {
+      const lmo_edge* e = &E[j];
+      if (C[e->lo] == j && C[e->hi] == j) {
+        mate[e->lo] = e->hi;
+        mate[e->hi] = e->lo;
+        ++matched;
+      }
+    }
+    /* pass 3: remove edges at matched vertices, reset the others' candidates */
+    int64_t keep = 0;
+    for (int64_t j = 0; j < m; ++j) {
+      lmo_edge e = E[j];
+      if (mate[e.lo] != -1 || mate[e.hi] != -1) continue;
+      C[e.lo] = LMO_NONE;
+      C[e.hi] = LMO_NONE;
+      E[keep++] = e;
+    }
+    if (log && t <= log_cap) {
+      log[3 * (t - 1) + 0] = m;
+      log[3 * (t - 1) + 1] = vt;
+      log[3 * (t - 1) + 2] = matched;
+    }
+    m = keep;
+  }
+  free(E);
+  free(C);
+  free(seen);
+  return t;
+}
+
+/*
+ * Batch form: graphs g = 0..G-1 are solved one after another, each alone with
+ * its own seed (seeds[g], or seed0 for all when seeds is NULL). Inputs as in
+ * the batched library call: vtx_off[G+1], row_ptr[N+1] with global offsets,
+ * col holding local ids. mate receives local ids. phases[g] (optional) gets
+ * each graph's iteration count. Returns the largest count or an error.
+ */
+int64_t lmo_local_max_batch(int64_t G, const int64_t* vtx_off, const int64_t* row_ptr, const int32_t* col,
+                            const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate, int64_t* phases) {
+  int64_t worst = 0;
+  for (int64_t g = 0; g < G; ++g) {
+    int64_t a = vtx_off[g], b = vtx_off[g + 1];
+    int64_t n = b - a;
+    int64_t e0 = row_ptr[a];
+    int64_t* rp = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    if (!rp) return LMO_ENOMEM;
+    for (int64_t v = 0; v <= n; ++v) rp[v] = row_ptr[a + v] - e0;
+    int64_t t = lmo_local_max(n, rp, col + e0, w + e0, seeds ? seeds[g] : seed0, mate + a, NULL, 0);
+    free(rp);
+    if (t < 0) return t;
+    if (phases) phases[g] = t;
+    if (t > worst) worst = t;
+  }
+  return worst;
+}
+
+/*
+ * Greedy certificate check (test infrastructure; same key as above).
+ *
+ * The greedy matching -- scan edges by decreasing key, take an edge iff both
+ * endpoints are free (paper, Section 3, the greedy competitor) -- is the
+ * unique matching M such that every edge outside M touches an edge of M with
+ * a larger key. With a strict key, local max reaches exactly this matching,
+ * so the check decides bit-exact equality at any size in one pass.
+ *
+ * Returns the number of violations: mate not an involution or not an edge,
+ * a free-free edge (maximality), or an edge outside M that beats every
+ * matched edge at both its endpoints. Negative on bad input.
+ */
+int64_t lmo_greedy_certificate(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, uint64_t seed,
+                               const int32_t* mate) {
+  if (n < 0 || !row_ptr) return LMO_EINVAL;
+  float* mw = (float*)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+  int8_t* has = (int8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!mw || !has) {
+    free(mw);
+    free(has);
+    return LMO_ENOMEM;
+  }
+  int64_t bad = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t p = mate[v];
+    if (p == -1) continue;
+    if (p < 0 || p >= n || p == v || mate[p] != v) {
+      ++bad;
+      continue;
+    }
+    for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k)
+      if (col[k] == p) {
+        mw[v] = w[k];
+        has[v] = 1;
+        break;
+      }
+    if (!has[v]) ++bad;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+      int32_t u = col[k];
+      if (u <= v) continue; /* each undirected edge once */
+      if (mate[v] == u) continue;
+      lmo_edge e = {(int32_t)v, u, w[k], lmo_edge_hash(seed, (int32_t)v, u)};
+      int dominated = 0;
+      int32_t ends[2] = {(int32_t)v, u};
+      for (int s = 0; s < 2 && !dominated; ++s) {
+        int32_t x = ends[s];
+        if (!has[x]) continue;
+        int32_t y = mate[x];
+        lmo_edge f = {x < y ? x : y, x < y ? y : x, mw[x], 0};
+        f.h = lmo_edge_hash(seed, f.lo, f.hi);
+        if (key_greater(&f, &e)) dominated = 1;
+      }
+      if (!dominated) ++bad;
+    }
+  }
+  free(mw);
+  free(has);
+  return bad;
+}
