@@ -1,0 +1,204 @@
+/*
+ * lm.h -- local-max matching on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Birn, Osipov, Sanders, Schulz, Sitchinava, "Efficient
+ * Parallel and External Matching", Section 1, the "local max" algorithm):
+ * an edge is locally maximal when its key beats the key of every incident
+ * remaining edge. Starting from M = {}, every phase adds all locally maximal
+ * edges to M and removes every edge incident to a newly matched vertex, until
+ * no edge remains. The result is a maximal matching and a 1/2-approximation
+ * of the maximum weight matching (Section 1, Preis' family); the number of
+ * phases is logarithmic in expectation and the work is linear (Lemma 1 and
+ * the argument after it, Section 2).
+ *
+ * Key and tie-break (the paper breaks ties by a random perturbation; this
+ * library fixes it so that results are reproducible): the key of the edge
+ * {lo, hi}, lo < hi in the graph's own (local) vertex ids, is the pair
+ *     ( w  compared as a number (-0 equals +0),
+ *       H  = mix( ((uint64)lo << 32 | hi) XOR mix(seed + 0x9E3779B97F4A7C15) )
+ *            compared as an unsigned 64-bit integer ),
+ * compared lexicographically; mix is the SplitMix64 output function
+ * (z ^= z>>30; z *= 0xBF58476D1CE4E5B9; z ^= z>>27; z *= 0x94D049BB133111EB;
+ * z ^= z>>31). Distinct edges have distinct H, so the order is strict and
+ * the matching is unique: it equals the greedy matching under this key
+ * (Section 3 defines greedy as the scan by decreasing weight). mate[] is a
+ * pure function of (the set of CSR entries, seed): independent of entry
+ * order, tuning, batching or serving mix.
+ *
+ * Graph input: a simple undirected graph as symmetric CSR. n vertices;
+ * row_ptr int64[n+1] with row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz;
+ * col int32[nnz] neighbour ids in [0, n); w float32[nnz] finite weights; the
+ * entries (v,u) and (u,v) both exist and carry the same weight; no self-loops
+ * and no duplicate entries. Limits: n < 2^31, nnz < 2^31 - 2^16.
+ *
+ * Output: mate int32[n], mate[v] = partner of v or -1.
+ *
+ * Memory and ownership: the caller owns every input and output buffer. The
+ * library never writes inputs and keeps no pointer after the call returns.
+ * Scratch memory comes from the context's device pool, bounded by the HBM
+ * budget given to lm_create. Pointers are host memory unless the flags say
+ * device memory (then they must be device memory of the context's GPU,
+ * e.g. torch tensors' data_ptr()).
+ *
+ * Errors: every entry point returns LM_OK (0), LM_PENDING (1, poll only) or
+ * a negative lm_status; lm_strerror gives a message. After an error mate[]
+ * is unspecified. LM_EDEVICE means a HIP call failed; destroy the context.
+ *
+ * Threading: an lm_ctx is used by one thread at a time. lm_server_submit,
+ * lm_server_poll and lm_server_wait are thread-safe.
+ */
+#ifndef LM_H_
+#define LM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lm_status;
+
+#define LM_OK 0
+#define LM_PENDING 1
+#define LM_EINVAL (-1)     /* null pointer, bad size, offsets or flags */
+#define LM_EGRAPH (-2)     /* structural violation found by a check */
+#define LM_EWEIGHT (-3)    /* NaN or infinite weight found by a check */
+#define LM_ENOMEM (-4)     /* device allocation failed */
+#define LM_ETOOBIG (-5)    /* the problem can never fit the HBM budget or limits */
+#define LM_EAGAIN (-6)     /* server queue full, retry later */
+#define LM_ENOTFOUND (-7)  /* unknown or already retired ticket */
+#define LM_EDEVICE (-8)    /* HIP runtime failure or no usable device */
+
+/* flags */
+#define LM_IN_DEVICE 0x1u    /* row_ptr, col, w are device pointers */
+#define LM_OUT_DEVICE 0x2u   /* mate is a device pointer */
+#define LM_CHECK_GRAPH 0x4u  /* validate ids, self-loops, weights (and, for host
+                                inputs, symmetry and duplicates) before solving */
+#define LM_PROFILE 0x8u      /* time every kernel launch with HIP events */
+
+typedef struct lm_ctx lm_ctx;
+typedef struct lm_server lm_server;
+
+typedef struct {
+  int64_t n;              /* vertices */
+  int64_t nnz;            /* directed entries = 2 * undirected edges = row_ptr[n] */
+  const int64_t* row_ptr; /* n+1 */
+  const int32_t* col;     /* nnz */
+  const float* w;         /* nnz */
+} lm_csr;
+
+/* One record per phase t = 1, 2, ... */
+typedef struct {
+  int64_t live_entries;    /* directed entries alive at the start of phase t */
+  int64_t live_rows;       /* vertices with at least one live entry */
+  int64_t matched_edges;   /* edges added to M in phase t */
+  int64_t matched_entries; /* live entries of the rows matched in phase t */
+} lm_phase_rec;
+
+/* kernel kinds reported under LM_PROFILE */
+#define LM_K_INIT 0     /* live-set construction from the input CSR */
+#define LM_K_ARGMAX 1   /* first-phase per-vertex argmax */
+#define LM_K_MUTUAL 2   /* mutual-candidate check and matched marking */
+#define LM_K_COMPACT 3  /* edge compaction fused with the next argmax */
+#define LM_K_KINDS 4
+
+typedef struct {
+  int32_t phases;         /* phases with at least one live edge */
+  int32_t log_len;        /* records written to log (<= log_cap) */
+  int64_t matched_edges;  /* |M| */
+  double device_ms;       /* stream time of the solve (events around it) */
+  double bytes_alg;       /* algorithmic HBM bytes of all kernels, from the log */
+  lm_phase_rec* log;      /* caller buffer for per-phase records, or NULL */
+  int32_t log_cap;        /* its capacity in records */
+  int32_t k_launches[LM_K_KINDS]; /* LM_PROFILE: launches per kernel kind */
+  double k_ms[LM_K_KINDS];        /* LM_PROFILE: summed event time per kind */
+  double k_bytes[LM_K_KINDS];     /* algorithmic bytes per kind */
+} lm_stats;
+
+/* Creates a context on HIP device `device`. hbm_budget_bytes caps the
+ * library's own device memory (0 = 64 GiB). Returns LM_EDEVICE when no GPU
+ * is usable. */
+lm_status lm_create(int device, size_t hbm_budget_bytes, lm_ctx** out);
+void lm_destroy(lm_ctx* ctx);
+
+/* Solves one graph. seed selects the tie-break hash. stream is a
+ * hipStream_t (NULL = the context's own stream); the call returns after the
+ * result is in mate. stats may be NULL. */
+lm_status lm_match(lm_ctx* ctx, const lm_csr* g, uint64_t seed, int32_t* mate, uint32_t flags, void* stream,
+                   lm_stats* stats);
+
+/* Solves G graphs in one batched run over their disjoint union. Graph k owns
+ * vertices [vtx_off[k], vtx_off[k+1]) of the union; row_ptr (N+1, N =
+ * vtx_off[G]) holds global entry offsets; col holds LOCAL ids (0-based per
+ * graph); mate receives local ids. Graph k uses seeds[k], or seed0 when seeds
+ * is NULL, so each graph's result equals lm_match of that graph alone.
+ * vtx_off and seeds are always host arrays. graph_phases (optional, host,
+ * G entries) receives each graph's phase count. */
+lm_status lm_match_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, int64_t nnz, const int64_t* row_ptr,
+                         const int32_t* col, const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate,
+                         uint32_t flags, void* stream, lm_stats* stats, int32_t* graph_phases);
+
+/* Tuning knobs of the phase kernels. short_max is the largest live degree
+ * handled by the shared segmented tiles; longer rows get a workgroup each.
+ * Results never depend on them. */
+typedef struct {
+  int32_t short_max;      /* 16..1024, power of two */
+  int32_t grid_per_cu;    /* persistent workgroups per compute unit, 1..8 */
+  int32_t phases_per_sync;/* phases enqueued between host termination checks */
+} lm_tuning;
+
+lm_status lm_get_tuning(lm_ctx* ctx, lm_tuning* out);
+lm_status lm_set_tuning(lm_ctx* ctx, const lm_tuning* t);
+
+/* Runs the autotuner: times candidate tunings on the given batch and keeps
+ * the fastest in the context. If cache_path is not NULL, results are read
+ * from and appended to that JSON-lines file, keyed by device name and size
+ * class. The chosen tuning is returned in out (may be NULL). */
+lm_status lm_autotune_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, int64_t nnz,
+                            const int64_t* row_ptr, const int32_t* col, const float* w, uint32_t flags,
+                            const char* cache_path, lm_tuning* out);
+
+/* ---------------- serving: continuous batching at phase granularity ----- */
+
+#define LM_SERVE_BATCHED 0  /* continuous batching: resident graphs share every phase launch */
+#define LM_SERVE_FIFO 1     /* baseline: one request at a time through lm_match */
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* admission budget for resident requests */
+  int32_t max_resident;     /* graphs on the GPU at once, 1..4096 */
+  int32_t queue_cap;        /* waiting requests before LM_EAGAIN */
+  int32_t phases_per_step;  /* phases run over all resident graphs per step */
+  int32_t mode;             /* LM_SERVE_BATCHED or LM_SERVE_FIFO */
+} lm_server_opts;
+
+typedef struct {
+  int32_t phases;           /* phases the request took */
+  int64_t matched_edges;
+  double submit_to_admit_ms;/* time in the queue */
+  double submit_to_done_ms; /* latency until the result was on the host */
+} lm_request_stats;
+
+/* Creates a server with its own scheduler thread on ctx's device. The
+ * server owns ctx's device while it lives: do not call lm_match on ctx. */
+lm_status lm_server_create(lm_ctx* ctx, const lm_server_opts* opts, lm_server** out);
+/* Deep-copies the host graph into pinned memory and queues it. Returns
+ * LM_EAGAIN when the queue is full, LM_ETOOBIG when the graph can never fit
+ * the admission budget. */
+lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_t* ticket);
+/* LM_PENDING while running; LM_OK copies mate (host, n entries) and retires
+ * the ticket; LM_ENOTFOUND for unknown or retired tickets. */
+lm_status lm_server_poll(lm_server* s, uint64_t ticket, int32_t* mate, lm_request_stats* st);
+/* Blocks until the ticket completes (or timeout_ms elapses: LM_PENDING),
+ * then behaves as lm_server_poll. timeout_ms < 0 waits forever. */
+lm_status lm_server_wait(lm_server* s, uint64_t ticket, int32_t* mate, lm_request_stats* st, int64_t timeout_ms);
+/* Drains every queued and running request, then stops the thread. */
+lm_status lm_server_destroy(lm_server* s);
+
+const char* lm_strerror(lm_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LM_H_ */

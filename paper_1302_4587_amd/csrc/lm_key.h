@@ -1,0 +1,109 @@
+// Edge key of local-max matching on the device: (weight, tie-break hash).
+//
+// The paper breaks weight ties by random perturbation (Section 1); the
+// library fixes the perturbation as a hash of the edge so that every run and
+// every schedule selects the same matching:
+//   key({lo,hi}) = ( w as a number, H(seed, lo, hi) as uint64 ), lexicographic
+//   H = mix( ((lo << 32) | hi) XOR mix(seed + gamma) )
+// with mix the SplitMix64 output function. Weights are compared through an
+// order-preserving map of the fp32 bit pattern (after folding -0 onto +0), so
+// the compare is exact and independent of denormal flushing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lm {
+
+constexpr uint64_t kGoldenGamma = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline uint64_t host_mix64(uint64_t z) { return mix64(z); }
+
+// Order-preserving image of a finite fp32 bit pattern; 0 is below all of them.
+__device__ __forceinline__ unsigned ord_weight_bits(unsigned b) {
+  if (b == 0x80000000u) b = 0u;  // -0 == +0
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t edge_hash(uint64_t S, unsigned a, unsigned b) {
+  const unsigned lo = a < b ? a : b;
+  const unsigned hi = a < b ? b : a;
+  return mix64(((uint64_t)lo << 32 | (uint64_t)hi) ^ S);
+}
+
+// A candidate with its full key; u = -1 is the dummy below every edge.
+struct Key {
+  unsigned w, hhi, hlo;
+  int u;
+};
+
+__device__ __forceinline__ Key key_ident() {
+  Key k;
+  k.w = 0u;
+  k.hhi = 0u;
+  k.hlo = 0u;
+  k.u = -1;
+  return k;
+}
+
+__device__ __forceinline__ bool key_gt(const Key& a, const Key& b) {
+  if (a.w != b.w) return a.w > b.w;
+  if (a.hhi != b.hhi) return a.hhi > b.hhi;
+  return a.hlo > b.hlo;
+}
+
+__device__ __forceinline__ Key key_max(const Key& a, const Key& b) { return key_gt(b, a) ? b : a; }
+
+// Running best of one lane over consecutive entries of one row. The hash is
+// evaluated only when a weight tie has to be decided.
+struct Run {
+  unsigned w;
+  int u;
+  uint64_t h;
+  bool hv;
+};
+
+__device__ __forceinline__ Run run_ident() {
+  Run r;
+  r.w = 0u;
+  r.u = -1;
+  r.h = 0ull;
+  r.hv = false;
+  return r;
+}
+
+__device__ __forceinline__ void run_update(Run& r, unsigned w, int u, unsigned vloc, uint64_t S) {
+  if (w > r.w) {
+    r.w = w;
+    r.u = u;
+    r.hv = false;
+  } else if (w == r.w) {  // r.u is a real edge: every real weight maps above 0
+    const uint64_t h = edge_hash(S, vloc, (unsigned)u);
+    if (!r.hv) {
+      r.h = edge_hash(S, vloc, (unsigned)r.u);
+      r.hv = true;
+    }
+    if (h > r.h) {
+      r.u = u;
+      r.h = h;
+    }
+  }
+}
+
+__device__ __forceinline__ Key run_key(const Run& r, unsigned vloc, uint64_t S) {
+  if (r.u < 0) return key_ident();
+  const uint64_t h = r.hv ? r.h : edge_hash(S, vloc, (unsigned)r.u);
+  Key k;
+  k.w = r.w;
+  k.hhi = (unsigned)(h >> 32);
+  k.hlo = (unsigned)h;
+  k.u = r.u;
+  return k;
+}
+
+}  // namespace lm

@@ -1,0 +1,84 @@
+// Host-side runtime objects of the local-max matching library: the device
+// memory pool with its HBM budget, the per-context solver state and the
+// problem descriptor handed to the phase loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lm.h"
+#include "lm_internal.h"
+
+namespace lm {
+
+constexpr int kLogCap = 1 << 16;  // device phase records kept per solve
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Grow-only device buffers, all charged against one budget.
+struct Pool {
+  size_t budget = 0;
+  size_t used = 0;
+  lm_status reserve(DevBuf& b, size_t bytes);
+  void release(DevBuf& b);
+};
+
+// Device-resident problem: the union of G graphs (G = 1 for lm_match).
+struct Problem {
+  int64_t N = 0, nnz = 0, G = 1;
+  const long long* row_ptr = nullptr;
+  const int* col = nullptr;
+  const float* w = nullptr;
+  const long long* vtx_off = nullptr;  // device, G+1
+  int* mate = nullptr;
+  int* gphase = nullptr;  // optional per-graph phase counts
+};
+
+struct Solver {
+  int dev = -1;
+  int num_cus = 0;
+  std::string dev_name;
+  hipStream_t own = nullptr;
+  Pool pool;
+  lm_tuning tun{};
+  int bpc_compact = 1, bpc_mutual = 4;
+  bool busy_server = false;
+  int last_phases = 0;
+
+  DevBuf C, state, rows[2], longs[2], tiles[2], ecol[2], ew[2];
+  DevBuf gbase, gseed, vtxoff, gphase, slots, totals, log;
+  DevBuf in_rp, in_col, in_w, out_mate;
+
+  Slot* h_slot = nullptr;
+  Totals* h_totals = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<hipEvent_t> evpool;
+
+  lm_status init_device(int device, size_t budget);
+  void shutdown();
+  lm_status prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase);
+  lm_status run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st);
+  hipEvent_t event(size_t i);
+};
+
+const char* status_text(lm_status st);
+lm_status dev_status(hipError_t e);
+size_t solve_footprint(int64_t N, int64_t nnz, int64_t G, int short_max);
+
+// Entry points shared with the server and the autotuner; the caller holds
+// the context lock.
+lm_status solve_locked(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, const int64_t* h_vtx_off, const int64_t* row_ptr,
+                       const int32_t* col, const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate,
+                       uint32_t flags, void* stream, lm_stats* st, int32_t* graph_phases);
+Solver& solver_of(lm_ctx* c);
+std::mutex& mutex_of(lm_ctx* c);
+
+}  // namespace lm

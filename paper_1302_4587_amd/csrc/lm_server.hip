@@ -1,0 +1,315 @@
+// Request server and autotuner of the local-max matching library.
+//
+// The server owns a scheduler thread. Requests are deep-copied into pinned
+// host memory at submit time and answered through tickets. In FIFO mode each
+// request is one lm_match call (the one-graph-per-launch baseline); in
+// batched mode the resident graphs share every phase launch (see
+// lm_batched_server.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lm.h"
+#include "lm_runtime.h"
+#include "lm_server_impl.h"
+
+using namespace lm;
+using Clock = std::chrono::steady_clock;
+
+namespace lm {
+
+static double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+Request::~Request() {
+  if (h_rp) (void)hipHostFree(h_rp);
+  if (h_col) (void)hipHostFree(h_col);
+  if (h_w) (void)hipHostFree(h_w);
+}
+
+void ServerCore::finish(const std::shared_ptr<Request>& r, lm_status st) {
+  std::lock_guard<std::mutex> lk(mu);
+  r->status = st;
+  r->t_done = Clock::now();
+  r->done = true;
+  running.erase(r->ticket);
+  finished[r->ticket] = r;
+  cv_done.notify_all();
+}
+
+// FIFO baseline: one request at a time, each a full lm_match solve.
+static void fifo_loop(ServerCore* S) {
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
+      if (S->queue.empty()) {
+        if (S->stopping) return;
+        continue;
+      }
+      r = S->queue.front();
+      S->queue.pop_front();
+      r->t_admit = Clock::now();
+      S->running[r->ticket] = r;
+    }
+    lm_status st;
+    {
+      std::lock_guard<std::mutex> ck(mutex_of(S->ctx));
+      lm_stats stats;
+      std::memset(&stats, 0, sizeof(stats));
+      r->mate.assign((size_t)r->n, -1);
+      st = solve_locked(S->ctx, r->n, r->nnz, 1, nullptr, r->h_rp, r->h_col, r->h_w, nullptr, r->seed,
+                        r->mate.data(), 0u, nullptr, &stats, nullptr);
+      r->phases = stats.phases;
+      r->matched = stats.matched_edges;
+    }
+    S->finish(r, st);
+  }
+}
+
+}  // namespace lm
+
+struct lm_server {
+  ServerCore core;
+};
+
+extern "C" {
+
+lm_status lm_server_create(lm_ctx* c, const lm_server_opts* o, lm_server** out) {
+  if (!c || !o || !out) return LM_EINVAL;
+  *out = nullptr;
+  if (o->max_resident < 1 || o->max_resident > 4096 || o->queue_cap < 1 || o->phases_per_step < 1 ||
+      o->phases_per_step > 64 || (o->mode != LM_SERVE_BATCHED && o->mode != LM_SERVE_FIFO))
+    return LM_EINVAL;
+  Solver& sv = solver_of(c);
+  {
+    std::lock_guard<std::mutex> lk(mutex_of(c));
+    if (sv.busy_server) return LM_EINVAL;
+    sv.busy_server = true;
+  }
+  lm_server* s = new (std::nothrow) lm_server();
+  if (!s) return LM_ENOMEM;
+  s->core.ctx = c;
+  s->core.opts = *o;
+  if (s->core.opts.hbm_budget_bytes == 0) s->core.opts.hbm_budget_bytes = (size_t)64 << 30;
+  lm_status st = LM_OK;
+  if (o->mode == LM_SERVE_FIFO) {
+    s->core.worker = std::thread(fifo_loop, &s->core);
+  } else {
+    st = start_batched(&s->core);
+  }
+  if (st != LM_OK) {
+    std::lock_guard<std::mutex> lk(mutex_of(c));
+    sv.busy_server = false;
+    delete s;
+    return st;
+  }
+  *out = s;
+  return LM_OK;
+}
+
+lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_t* ticket) {
+  if (!s || !g || !ticket) return LM_EINVAL;
+  if (g->n < 0 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w))) return LM_EINVAL;
+  if (g->n >= ((int64_t)1 << 31) || g->nnz >= ((int64_t)1 << 31) - 65536) return LM_ETOOBIG;
+  if (g->row_ptr[0] != 0 || g->row_ptr[g->n] != g->nnz) return LM_EINVAL;
+  ServerCore& S = s->core;
+  const size_t fp = request_footprint(g->n, g->nnz);
+  if (fp > S.opts.hbm_budget_bytes) return LM_ETOOBIG;
+  auto r = std::make_shared<Request>();
+  r->n = g->n;
+  r->nnz = g->nnz;
+  r->seed = seed;
+  r->footprint = fp;
+  r->t_submit = Clock::now();
+  if (hipHostMalloc((void**)&r->h_rp, (size_t)(g->n + 1) * 8) != hipSuccess ||
+      hipHostMalloc((void**)&r->h_col, (size_t)std::max<int64_t>(g->nnz, 1) * 4) != hipSuccess ||
+      hipHostMalloc((void**)&r->h_w, (size_t)std::max<int64_t>(g->nnz, 1) * 4) != hipSuccess)
+    return LM_ENOMEM;
+  std::memcpy(r->h_rp, g->row_ptr, (size_t)(g->n + 1) * 8);
+  if (g->nnz > 0) {
+    std::memcpy(r->h_col, g->col, (size_t)g->nnz * 4);
+    std::memcpy(r->h_w, g->w, (size_t)g->nnz * 4);
+  }
+  std::lock_guard<std::mutex> lk(S.mu);
+  if (S.stopping) return LM_EINVAL;
+  if ((int)S.queue.size() >= S.opts.queue_cap) return LM_EAGAIN;
+  r->ticket = ++S.next_ticket;
+  S.queue.push_back(r);
+  S.all[r->ticket] = r;
+  *ticket = r->ticket;
+  S.cv_work.notify_all();
+  return LM_OK;
+}
+
+static lm_status take_result(ServerCore& S, uint64_t ticket, int32_t* mate, lm_request_stats* st) {
+  // caller holds S.mu
+  auto it = S.finished.find(ticket);
+  if (it == S.finished.end()) return S.all.count(ticket) ? LM_PENDING : LM_ENOTFOUND;
+  std::shared_ptr<Request> r = it->second;
+  S.finished.erase(it);
+  S.all.erase(ticket);
+  if (r->status != LM_OK) return r->status;
+  if (mate && r->n > 0) std::memcpy(mate, r->mate.data(), (size_t)r->n * 4);
+  if (st) {
+    st->phases = r->phases;
+    st->matched_edges = r->matched;
+    st->submit_to_admit_ms = ms_between(r->t_submit, r->t_admit);
+    st->submit_to_done_ms = ms_between(r->t_submit, r->t_done);
+  }
+  return LM_OK;
+}
+
+lm_status lm_server_poll(lm_server* s, uint64_t ticket, int32_t* mate, lm_request_stats* st) {
+  if (!s) return LM_EINVAL;
+  std::lock_guard<std::mutex> lk(s->core.mu);
+  return take_result(s->core, ticket, mate, st);
+}
+
+lm_status lm_server_wait(lm_server* s, uint64_t ticket, int32_t* mate, lm_request_stats* st, int64_t timeout_ms) {
+  if (!s) return LM_EINVAL;
+  ServerCore& S = s->core;
+  std::unique_lock<std::mutex> lk(S.mu);
+  auto ready = [&] { return S.finished.count(ticket) != 0 || S.all.count(ticket) == 0; };
+  if (timeout_ms < 0)
+    S.cv_done.wait(lk, ready);
+  else if (!S.cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+    return LM_PENDING;
+  return take_result(S, ticket, mate, st);
+}
+
+lm_status lm_server_destroy(lm_server* s) {
+  if (!s) return LM_EINVAL;
+  ServerCore& S = s->core;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stopping = true;
+    S.cv_work.notify_all();
+  }
+  if (S.worker.joinable()) S.worker.join();
+  lm_status st = S.worker_status;
+  stop_batched(&S);
+  {
+    std::lock_guard<std::mutex> lk(mutex_of(S.ctx));
+    solver_of(S.ctx).busy_server = false;
+  }
+  delete s;
+  return st;
+}
+
+// ------------------------------------------------------------------ tuner
+
+static std::string size_class(int64_t N, int64_t nnz, int64_t G) {
+  auto lg = [](int64_t x) { return x <= 1 ? 0 : (int)std::ceil(std::log2((double)x)); };
+  std::ostringstream o;
+  o << "G" << lg(G) << "_N" << lg(N) << "_E" << lg(nnz);
+  return o.str();
+}
+
+static bool cache_lookup(const char* path, const std::string& dev, const std::string& cls, lm_tuning* t) {
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    if (line.find("\"device\": \"" + dev + "\"") == std::string::npos) continue;
+    if (line.find("\"class\": \"" + cls + "\"") == std::string::npos) continue;
+    int sm = 0, gp = 0, pp = 0;
+    const char* p = std::strstr(line.c_str(), "\"short_max\": ");
+    const char* q = std::strstr(line.c_str(), "\"grid_per_cu\": ");
+    const char* r = std::strstr(line.c_str(), "\"phases_per_sync\": ");
+    if (!p || !q || !r) continue;
+    sm = std::atoi(p + 13);
+    gp = std::atoi(q + 15);
+    pp = std::atoi(r + 19);
+    if (sm > 0 && gp > 0 && pp > 0) {
+      t->short_max = sm;
+      t->grid_per_cu = gp;
+      t->phases_per_sync = pp;
+      found = true;  // the last matching line wins
+    }
+  }
+  return found;
+}
+
+lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col, const float* w, uint32_t flags, const char* cache_path,
+                            lm_tuning* out) {
+  if (!c || graphs < 1 || !vtx_off) return LM_EINVAL;
+  std::lock_guard<std::mutex> lk(mutex_of(c));
+  Solver& sv = solver_of(c);
+  if (sv.busy_server) return LM_EINVAL;
+  const int64_t N = vtx_off[graphs];
+  const std::string cls = size_class(N, nnz, graphs);
+  lm_tuning best = sv.tun;
+  if (cache_lookup(cache_path, sv.dev_name, cls, &best)) {
+    sv.tun = best;
+    if (out) *out = best;
+    return LM_OK;
+  }
+  const uint32_t fl = flags & (LM_IN_DEVICE);
+  int32_t* mate = nullptr;
+  if (hipMalloc(&mate, (size_t)std::max<int64_t>(N, 1) * 4) != hipSuccess) return LM_ENOMEM;
+  const lm_tuning saved = sv.tun;
+  double best_ms = 1e300;
+  lm_status rs = LM_OK;
+  const int sms[] = {64, 128, 256, 512};
+  for (int sm : sms) {
+    for (int gp = 1; gp <= std::max(1, sv.bpc_compact); ++gp) {
+      for (int pp : {4, 8}) {
+        lm_tuning t{sm, gp, pp};
+        sv.tun = t;
+        std::vector<double> ms;
+        for (int rep = 0; rep < 3 && rs == LM_OK; ++rep) {
+          lm_stats st;
+          std::memset(&st, 0, sizeof(st));
+          rs = solve_locked(c, N, nnz, graphs, vtx_off, row_ptr, col, w, nullptr, 1, mate, fl | LM_OUT_DEVICE,
+                            nullptr, &st, nullptr);
+          ms.push_back(st.device_ms);
+        }
+        if (rs != LM_OK) break;
+        std::sort(ms.begin(), ms.end());
+        if (ms[1] < best_ms) {
+          best_ms = ms[1];
+          best = t;
+        }
+      }
+      if (rs != LM_OK) break;
+    }
+    if (rs != LM_OK) break;
+  }
+  (void)hipFree(mate);
+  if (rs != LM_OK) {
+    sv.tun = saved;
+    return rs;
+  }
+  sv.tun = best;
+  if (out) *out = best;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    if (f)
+      f << "{\"device\": \"" << sv.dev_name << "\", \"class\": \"" << cls << "\", \"short_max\": " << best.short_max
+        << ", \"grid_per_cu\": " << best.grid_per_cu << ", \"phases_per_sync\": " << best.phases_per_sync
+        << ", \"ms\": " << best_ms << "}\n";
+  }
+  return LM_OK;
+}
+
+}  // extern "C"

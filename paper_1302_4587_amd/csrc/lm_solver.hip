@@ -1,0 +1,622 @@
+// Host driver and C ABI of the local-max matching library (see include/lm.h).
+//
+// A solve is: [optional input check] -> init (live set R_1 from the CSR) ->
+// first argmax -> phases t = 1, 2, ...: mutual(t), compact(t). Phases are
+// enqueued in chunks without host synchronisation; after each chunk the host
+// reads one counter slot to see whether the live set is empty.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lm.h"
+#include "lm_internal.h"
+#include "lm_key.h"
+#include "lm_runtime.h"
+
+using namespace lm;
+
+namespace lm {
+
+const char* status_text(lm_status st) {
+  switch (st) {
+    case LM_OK: return "ok";
+    case LM_PENDING: return "pending";
+    case LM_EINVAL: return "invalid argument";
+    case LM_EGRAPH: return "graph violates the input contract";
+    case LM_EWEIGHT: return "NaN or infinite weight";
+    case LM_ENOMEM: return "device allocation failed";
+    case LM_ETOOBIG: return "problem exceeds the HBM budget or the size limits";
+    case LM_EAGAIN: return "server queue full";
+    case LM_ENOTFOUND: return "unknown or retired ticket";
+    case LM_EDEVICE: return "HIP device failure or no usable device";
+    default: return "unknown status";
+  }
+}
+
+lm_status dev_status(hipError_t e) {
+  if (e == hipSuccess) return LM_OK;
+  if (e == hipErrorOutOfMemory) return LM_ENOMEM;
+  return LM_EDEVICE;
+}
+
+lm_status Pool::reserve(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return LM_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    used -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (used + bytes > budget) return LM_ETOOBIG;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? LM_ENOMEM : LM_EDEVICE;
+  }
+  b.p = p;
+  b.bytes = bytes;
+  used += bytes;
+  return LM_OK;
+}
+
+void Pool::release(DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    used -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// Device bytes a solve needs beyond its inputs and outputs.
+size_t solve_footprint(int64_t N, int64_t nnz, int64_t G, int short_max) {
+  const int tw = kCap - short_max;
+  const int64_t ntiles = nnz / tw + 2;
+  const int64_t nlong = std::min<int64_t>(N, nnz / (short_max + 1) + 1);
+  size_t b = 0;
+  b += (size_t)N * 4 + 256;                // C
+  b += (size_t)N + 256;                    // state
+  b += 2 * ((size_t)N * 16 + 256);         // short lists
+  b += 2 * ((size_t)nlong * 16 + 256);     // long lists
+  b += 2 * ((size_t)ntiles * 4 + 256);     // tile starts
+  b += 2 * 2 * ((size_t)nnz * 4 + 256);    // entry ping-pong (col, w)
+  b += (size_t)G * 16 + (size_t)(G + 1) * 8 + 1024;
+  b += sizeof(Slot) * kRing + sizeof(Totals) + sizeof(LogRec) * (size_t)kLogCap + 1024;
+  return b;
+}
+
+// ------------------------------------------------------------------ solve
+
+lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
+  const int ts = tun.short_max;
+  const int tw = kCap - ts;
+  const int64_t ntiles = nnz / tw + 2;
+  const int64_t nlong = std::min<int64_t>(N, nnz / (ts + 1) + 1);
+  lm_status st;
+#define RES(buf, bytes)                 \
+  do {                                  \
+    st = pool.reserve(buf, (bytes));    \
+    if (st != LM_OK) return st;         \
+  } while (0)
+  RES(C, (size_t)N * 4);
+  RES(state, (size_t)N);
+  for (int i = 0; i < 2; ++i) {
+    RES(rows[i], (size_t)N * 16);
+    RES(longs[i], (size_t)nlong * 16);
+    RES(tiles[i], (size_t)ntiles * 4);
+    RES(ecol[i], (size_t)nnz * 4);
+    RES(ew[i], (size_t)nnz * 4);
+  }
+  RES(gbase, (size_t)G * 4);
+  RES(gseed, (size_t)G * 8);
+  RES(vtxoff, (size_t)(G + 1) * 8);
+  if (want_gphase) RES(gphase, (size_t)G * 4);
+  RES(slots, sizeof(Slot) * kRing);
+  RES(totals, sizeof(Totals));
+  RES(log, sizeof(LogRec) * (size_t)kLogCap);
+#undef RES
+  return LM_OK;
+}
+
+lm_status Solver::init_device(int device, size_t budget) {
+  dev = device;
+  pool.budget = budget;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0 || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return LM_EDEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) return LM_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return LM_EDEVICE;
+  num_cus = prop.multiProcessorCount;
+  dev_name = prop.gcnArchName;
+  if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return LM_EDEVICE;
+  if (hipHostMalloc((void**)&h_slot, sizeof(Slot) * kRing) != hipSuccess) return LM_EDEVICE;
+  if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
+  bpc_compact = max_blocks_per_cu_compact();
+  bpc_mutual = max_blocks_per_cu_mutual();
+  tun.short_max = 256;
+  tun.grid_per_cu = bpc_compact;
+  tun.phases_per_sync = 4;
+  return LM_OK;
+}
+
+void Solver::shutdown() {
+  if (dev >= 0) (void)hipSetDevice(dev);
+  if (own) (void)hipStreamSynchronize(own);
+  DevBuf* all[] = {&C, &state, &rows[0], &rows[1], &longs[0], &longs[1], &tiles[0], &tiles[1], &ecol[0], &ecol[1],
+                   &ew[0], &ew[1], &gbase, &gseed, &vtxoff, &gphase, &slots, &totals, &log, &in_rp, &in_col,
+                   &in_w, &out_mate};
+  for (DevBuf* b : all) pool.release(*b);
+  for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+  evpool.clear();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (h_slot) (void)hipHostFree(h_slot);
+  if (h_totals) (void)hipHostFree(h_totals);
+  if (own) (void)hipStreamDestroy(own);
+  own = nullptr;
+  h_slot = nullptr;
+  h_totals = nullptr;
+  e0 = e1 = nullptr;
+}
+
+hipEvent_t Solver::event(size_t i) {
+  while (evpool.size() <= i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    evpool.push_back(e);
+  }
+  return evpool[i];
+}
+
+// Runs the phase loop over a problem whose inputs are already on the device.
+lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st) {
+  const int ts = tun.short_max;
+  const int tw = kCap - ts;
+  const bool prof = (flags & LM_PROFILE) != 0;
+  std::vector<std::pair<int, size_t>> marks;  // (kind, event index of start)
+  size_t evn = 0;
+  auto mark_begin = [&](int kind) -> hipError_t {
+    if (!prof) return hipSuccess;
+    hipEvent_t e = event(evn);
+    if (!e) return hipErrorOutOfMemory;
+    marks.push_back({kind, evn});
+    evn += 2;
+    return hipEventRecord(e, s);
+  };
+  auto mark_end = [&]() -> hipError_t {
+    if (!prof) return hipSuccess;
+    return hipEventRecord(event(marks.back().second + 1), s);
+  };
+#define HIPCHK(x)                          \
+  do {                                     \
+    hipError_t _e = (x);                   \
+    if (_e != hipSuccess) {                \
+      (void)hipGetLastError();             \
+      return dev_status(_e);               \
+    }                                      \
+  } while (0)
+
+  HIPCHK(hipEventRecord(e0, s));
+  HIPCHK(launch_zero((Slot*)slots.p, (Totals*)totals.p, s));
+  if (p.gphase) HIPCHK(launch_fill_i32(p.gphase, p.G, 0, s));
+  const int maxgrid_x = std::max(1, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_compact)));
+  const int maxgrid_m = std::max(1, num_cus * bpc_mutual);
+  if (flags & LM_CHECK_GRAPH) {
+    CheckArgs ca{(Totals*)totals.p, p.nnz, p.row_ptr, p.col, p.w, (int)p.N, (int)p.G, p.vtx_off};
+    const int grid = (int)std::min<int64_t>(maxgrid_m, (p.N + kBlock - 1) / kBlock + 1);
+    HIPCHK(launch_check(ca, grid, s));
+  }
+  InitArgs ia;
+  ia.slot1 = (Slot*)slots.p + 1;
+  ia.totals = (Totals*)totals.p;
+  ia.row_ptr = p.row_ptr;
+  ia.nnz = p.nnz;
+  ia.n = (int)p.N;
+  ia.graphs = (int)p.G;
+  ia.vtx_off = p.vtx_off;
+  ia.short_max = ts;
+  ia.tile_width = tw;
+  ia.mate = p.mate;
+  ia.state = (unsigned char*)state.p;
+  ia.short_out = (int4*)rows[0].p;
+  ia.long_out = (int4*)longs[0].p;
+  ia.tiles_out = (int*)tiles[0].p;
+  ia.long_cap = (long long)(longs[0].bytes / 16);
+  ia.tiles_cap = (long long)(tiles[0].bytes / 4);
+  {
+    const int grid = (int)std::min<int64_t>(maxgrid_m, (p.N + kCap - 1) / kCap + 1);
+    HIPCHK(mark_begin(LM_K_INIT));
+    HIPCHK(launch_init(ia, grid, s));
+    HIPCHK(mark_end());
+  }
+  PhaseArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.slots = (Slot*)slots.p;
+  a.log = (LogRec*)log.p;
+  a.totals = (Totals*)totals.p;
+  a.log_cap = kLogCap;
+  a.short_max = ts;
+  a.tile_width = tw;
+  a.n = (int)p.N;
+  a.long_cap = (long long)(std::min(longs[0].bytes, longs[1].bytes) / 16);
+  a.tiles_cap = (long long)(std::min(tiles[0].bytes, tiles[1].bytes) / 4);
+  a.C = (int*)C.p;
+  a.state = (unsigned char*)state.p;
+  a.mate = p.mate;
+  a.gbase = (const int*)gbase.p;
+  a.gseed = (const unsigned long long*)gseed.p;
+  a.gphase = p.gphase;
+  auto set_phase = [&](int t) {
+    a.t = t;
+    const int li = (t - 1) & 1, lo = t & 1;
+    a.short_in = (const int4*)rows[li].p;
+    a.long_in = (const int4*)longs[li].p;
+    a.tiles_in = (const int*)tiles[li].p;
+    a.short_out = (int4*)rows[lo].p;
+    a.long_out = (int4*)longs[lo].p;
+    a.tiles_out = (int*)tiles[lo].p;
+    if (t == 1) {
+      a.src_col = p.col;
+      a.src_w = p.w;
+    } else {
+      a.src_col = (const int*)ecol[t & 1].p;
+      a.src_w = (const float*)ew[t & 1].p;
+    }
+    a.dst_col = (int*)ecol[(t + 1) & 1].p;
+    a.dst_w = (float*)ew[(t + 1) & 1].p;
+    a.dst_cap = p.nnz;
+  };
+  set_phase(1);
+  {
+    HIPCHK(mark_begin(LM_K_ARGMAX));
+    HIPCHK(launch_first_argmax(a, maxgrid_x, s));
+    HIPCHK(mark_end());
+  }
+  // phase loop
+  int t = 1;
+  int64_t est_items = p.nnz / tw + 1;  // work items of the current phase (estimate)
+  int64_t est_rows = p.N;
+  int64_t last_live = -1;
+  bool first_check = true;
+  bool stalled = false;
+  for (;;) {
+    const int chunk = first_check ? 2 : std::max(1, tun.phases_per_sync);
+    for (int j = 0; j < chunk; ++j) {
+      set_phase(t);
+      const int64_t shrink = (int64_t)1 << std::min(j, 20);
+      const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(maxgrid_m, (est_rows / shrink + kBlock - 1) / kBlock));
+      const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(maxgrid_x, est_items / shrink + 1));
+      HIPCHK(mark_begin(LM_K_MUTUAL));
+      HIPCHK(launch_mutual(a, gm, s));
+      HIPCHK(mark_end());
+      HIPCHK(mark_begin(LM_K_COMPACT));
+      HIPCHK(launch_compact(a, gx, s));
+      HIPCHK(mark_end());
+      ++t;
+    }
+    HIPCHK(hipMemcpyAsync(h_slot, (Slot*)slots.p + (t % kRing), sizeof(Slot), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_totals, totals.p, sizeof(Totals), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    first_check = false;
+    if (h_totals->err) break;
+    const int64_t nshort = (int64_t)(h_slot->short_packed >> 32);
+    const int64_t sent = (int64_t)(h_slot->short_packed & 0xffffffffull);
+    const int64_t nlong = h_slot->long_rows;
+    if (nshort + nlong == 0) break;
+    // every phase of a well-formed graph matches its globally heaviest live
+    // edge; no progress over a whole chunk means asymmetric input
+    const int64_t live = sent + (int64_t)h_slot->long_kept;
+    if (live == last_live) {
+      stalled = true;
+      break;
+    }
+    last_live = live;
+    est_rows = nshort + nlong;
+    est_items = nlong + (sent + tw - 1) / tw;
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  const unsigned err = h_totals->err;
+  if (stalled) return LM_EGRAPH;
+  if (err) {
+    if (err & kErrWeight) return LM_EWEIGHT;
+    if (err & (kErrRowPtr | kErrColRange | kErrSelfLoop)) return LM_EGRAPH;
+    if (err & kErrDegree) return LM_ETOOBIG;
+    return LM_EDEVICE;
+  }
+  const int phases = h_totals->last_nonempty;
+  last_phases = phases;
+  if (st) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    st->phases = phases;
+    st->matched_edges = (int64_t)(h_totals->matched / 2);
+    st->device_ms = ms;
+    for (int k = 0; k < LM_K_KINDS; ++k) {
+      st->k_launches[k] = 0;
+      st->k_ms[k] = 0.0;
+      st->k_bytes[k] = 0.0;
+    }
+    for (auto& m : marks) {
+      float km = 0.f;
+      HIPCHK(hipEventElapsedTime(&km, event(m.second), event(m.second + 1)));
+      st->k_launches[m.first] += 1;
+      st->k_ms[m.first] += km;
+    }
+    // per-phase records and algorithmic bytes
+    const int nrec = std::min(phases, kLogCap);
+    std::vector<LogRec> recs((size_t)nrec + 1);
+    if (nrec > 0)
+      HIPCHK(hipMemcpy(recs.data(), log.p, sizeof(LogRec) * (size_t)nrec, hipMemcpyDeviceToHost));
+    recs[(size_t)nrec] = LogRec{0, 0, 0, 0};
+    st->log_len = 0;
+    if (st->log && st->log_cap > 0) {
+      const int nl = std::min(nrec, st->log_cap);
+      std::memcpy(st->log, recs.data(), sizeof(LogRec) * (size_t)nl);
+      st->log_len = nl;
+    }
+    const double V1 = nrec > 0 ? (double)recs[0].live_rows : 0.0;
+    const double L1 = nrec > 0 ? (double)recs[0].live_entries : 0.0;
+    st->k_bytes[LM_K_INIT] = 8.0 * (double)(p.N + 1) + 5.0 * (double)p.N + 16.0 * V1 + 4.0 * L1 / tw;
+    st->k_bytes[LM_K_ARGMAX] = 16.0 * V1 + 8.0 * L1 + 4.0 * V1;
+    for (int i = 0; i < nrec; ++i) {
+      const double L = (double)recs[i].live_entries, V = (double)recs[i].live_rows;
+      const double mv = 2.0 * (double)recs[i].matched_edges, md = (double)recs[i].matched_entries;
+      const double L2 = (double)recs[i + 1].live_entries, V2 = (double)recs[i + 1].live_rows;
+      st->k_bytes[LM_K_MUTUAL] += 24.0 * V + 5.0 * mv;
+      st->k_bytes[LM_K_COMPACT] += 17.0 * V + 9.0 * (L - md) + 8.0 * L2 + 20.0 * V2;
+    }
+    st->bytes_alg = 0.0;
+    for (int k = 0; k < LM_K_KINDS; ++k) st->bytes_alg += st->k_bytes[k];
+  }
+#undef HIPCHK
+  return LM_OK;
+}
+
+}  // namespace lm
+
+// ==================================================================== C ABI
+
+struct lm_ctx {
+  Solver s;
+  std::mutex mu;
+};
+
+static bool csr_shape_ok(const lm_csr* g) {
+  if (!g) return false;
+  if (g->n < 0 || g->nnz < 0) return false;
+  if (g->n >= (int64_t)1 << 31) return false;
+  if (!g->row_ptr) return false;
+  if (g->nnz > 0 && (!g->col || !g->w)) return false;
+  return true;
+}
+
+// Full host-side contract check of a graph (LM_CHECK_GRAPH on host input).
+static lm_status host_check(int64_t n, const int64_t* rp, const int32_t* col, const float* w, int64_t nnz) {
+  if (rp[0] != 0 || rp[n] != nnz) return LM_EINVAL;
+  struct E {
+    int32_t lo, hi;
+    float w;
+  };
+  std::vector<E> es;
+  es.reserve((size_t)nnz);
+  for (int64_t v = 0; v < n; ++v) {
+    if (rp[v + 1] < rp[v]) return LM_EINVAL;
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+      const int32_t u = col[k];
+      if (u < 0 || u >= n || u == v) return LM_EGRAPH;
+      const float x = w[k];
+      if (!(x == x) || x == 1.0f / 0.0f || x == -1.0f / 0.0f) return LM_EWEIGHT;
+      es.push_back(E{(int32_t)std::min<int64_t>(v, u), (int32_t)std::max<int64_t>(v, u), x});
+    }
+  }
+  std::sort(es.begin(), es.end(), [](const E& a, const E& b) {
+    if (a.lo != b.lo) return a.lo < b.lo;
+    if (a.hi != b.hi) return a.hi < b.hi;
+    return a.w < b.w;
+  });
+  if (es.size() % 2) return LM_EGRAPH;
+  for (size_t i = 0; i < es.size(); i += 2) {
+    if (es[i].lo != es[i + 1].lo || es[i].hi != es[i + 1].hi) return LM_EGRAPH;  // missing twin
+    if (!(es[i].w == es[i + 1].w)) return LM_EGRAPH;                             // unequal weights
+    if (i + 2 < es.size() && es[i + 2].lo == es[i].lo && es[i + 2].hi == es[i].hi) return LM_EGRAPH;  // duplicate
+  }
+  return LM_OK;
+}
+
+extern "C" {
+
+const char* lm_strerror(lm_status st) { return status_text(st); }
+
+lm_status lm_create(int device, size_t hbm_budget_bytes, lm_ctx** out) {
+  if (!out) return LM_EINVAL;
+  *out = nullptr;
+  lm_ctx* c = new (std::nothrow) lm_ctx();
+  if (!c) return LM_ENOMEM;
+  const size_t budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)64 << 30);
+  lm_status st = c->s.init_device(device, budget);
+  if (st != LM_OK) {
+    c->s.shutdown();
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LM_OK;
+}
+
+void lm_destroy(lm_ctx* c) {
+  if (!c) return;
+  c->s.shutdown();
+  delete c;
+}
+
+lm_status lm_get_tuning(lm_ctx* c, lm_tuning* out) {
+  if (!c || !out) return LM_EINVAL;
+  *out = c->s.tun;
+  return LM_OK;
+}
+
+lm_status lm_set_tuning(lm_ctx* c, const lm_tuning* t) {
+  if (!c || !t) return LM_EINVAL;
+  const int sm = t->short_max;
+  if (sm < 16 || sm > 1024 || (sm & (sm - 1)) != 0) return LM_EINVAL;
+  if (t->grid_per_cu < 1 || t->grid_per_cu > 8) return LM_EINVAL;
+  if (t->phases_per_sync < 1 || t->phases_per_sync > 64) return LM_EINVAL;
+  c->s.tun = *t;
+  return LM_OK;
+}
+
+// Shared body of lm_match and lm_match_batch.
+static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, const int64_t* h_vtx_off,
+                              const int64_t* row_ptr, const int32_t* col, const float* w, const uint64_t* seeds,
+                              uint64_t seed0, int32_t* mate, uint32_t flags, void* stream, lm_stats* st,
+                              int32_t* graph_phases) {
+  const uint32_t known = LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE;
+  if (flags & ~known) return LM_EINVAL;
+  if (N < 0 || nnz < 0 || G < 1) return LM_EINVAL;
+  if (N >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 31) - 65536) return LM_ETOOBIG;
+  if (N > 0 && (!row_ptr || !mate)) return LM_EINVAL;
+  if (nnz > 0 && (!col || !w)) return LM_EINVAL;
+  Solver& S = c->s;
+  if (hipSetDevice(S.dev) != hipSuccess) return LM_EDEVICE;
+  hipStream_t s = stream ? (hipStream_t)stream : S.own;
+  const bool in_dev = (flags & LM_IN_DEVICE) != 0;
+  const bool out_dev = (flags & LM_OUT_DEVICE) != 0;
+  // host-side checks that need no device work
+  if (!in_dev && N > 0) {
+    if (row_ptr[0] != 0 || row_ptr[N] != nnz) return LM_EINVAL;
+    if (flags & LM_CHECK_GRAPH) {
+      for (int64_t g = 0; g < G; ++g) {
+        const int64_t a = h_vtx_off ? h_vtx_off[g] : 0, b = h_vtx_off ? h_vtx_off[g + 1] : N;
+        const int64_t e0 = row_ptr[a];
+        std::vector<int64_t> rp((size_t)(b - a + 1));
+        for (int64_t v = 0; v <= b - a; ++v) rp[(size_t)v] = row_ptr[a + v] - e0;
+        lm_status hs = host_check(b - a, rp.data(), col + e0, w + e0, rp[(size_t)(b - a)]);
+        if (hs != LM_OK) return hs;
+      }
+    }
+  }
+  if (st) {
+    st->phases = 0;
+    st->matched_edges = 0;
+    st->device_ms = 0.0;
+    st->bytes_alg = 0.0;
+    st->log_len = 0;
+  }
+  if (graph_phases)
+    for (int64_t g = 0; g < G; ++g) graph_phases[g] = 0;
+  if (N == 0) return LM_OK;
+  // memory: footprint plus staging of host inputs / outputs
+  size_t need = solve_footprint(N, nnz, G, S.tun.short_max);
+  if (!in_dev) need += (size_t)(N + 1) * 8 + (size_t)nnz * 8 + 1024;
+  if (!out_dev) need += (size_t)N * 4 + 256;
+  if (need > S.pool.budget) return LM_ETOOBIG;
+  lm_status rs = S.prepare(N, nnz, G, graph_phases != nullptr);
+  if (rs != LM_OK) return rs;
+  const int64_t* d_rp = row_ptr;
+  const int32_t* d_col = col;
+  const float* d_w = w;
+  if (!in_dev) {
+    if ((rs = S.pool.reserve(S.in_rp, (size_t)(N + 1) * 8)) != LM_OK) return rs;
+    if ((rs = S.pool.reserve(S.in_col, (size_t)nnz * 4)) != LM_OK) return rs;
+    if ((rs = S.pool.reserve(S.in_w, (size_t)nnz * 4)) != LM_OK) return rs;
+    if (hipMemcpyAsync(S.in_rp.p, row_ptr, (size_t)(N + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync(S.in_col.p, col, (size_t)nnz * 4, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (nnz > 0 && hipMemcpyAsync(S.in_w.p, w, (size_t)nnz * 4, hipMemcpyHostToDevice, s) != hipSuccess))
+      return LM_EDEVICE;
+    d_rp = (const int64_t*)S.in_rp.p;
+    d_col = (const int32_t*)S.in_col.p;
+    d_w = (const float*)S.in_w.p;
+  }
+  int32_t* d_mate = mate;
+  if (!out_dev) {
+    if ((rs = S.pool.reserve(S.out_mate, (size_t)N * 4)) != LM_OK) return rs;
+    d_mate = (int32_t*)S.out_mate.p;
+  }
+  // per-graph tables
+  std::vector<int32_t> hb((size_t)G);
+  std::vector<uint64_t> hs((size_t)G);
+  std::vector<int64_t> hv((size_t)G + 1);
+  for (int64_t g = 0; g < G; ++g) {
+    hb[(size_t)g] = (int32_t)(h_vtx_off ? h_vtx_off[g] : 0);
+    hs[(size_t)g] = premix_seed(seeds ? seeds[g] : seed0);
+    hv[(size_t)g] = h_vtx_off ? h_vtx_off[g] : 0;
+  }
+  hv[(size_t)G] = h_vtx_off ? h_vtx_off[G] : N;
+  if (hipMemcpyAsync(S.gbase.p, hb.data(), (size_t)G * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(S.gseed.p, hs.data(), (size_t)G * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(S.vtxoff.p, hv.data(), (size_t)(G + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+    return LM_EDEVICE;
+  Problem p;
+  p.N = N;
+  p.nnz = nnz;
+  p.G = G;
+  p.row_ptr = (const long long*)d_rp;
+  p.col = d_col;
+  p.w = d_w;
+  p.vtx_off = (const long long*)S.vtxoff.p;
+  p.mate = d_mate;
+  p.gphase = graph_phases ? (int*)S.gphase.p : nullptr;
+  lm_stats local;
+  std::memset(&local, 0, sizeof(local));
+  lm_stats* sp = st ? st : &local;
+  rs = S.run(p, s, flags, sp);
+  if (rs != LM_OK) return rs;
+  if (!out_dev) {
+    if (hipMemcpyAsync(mate, d_mate, (size_t)N * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return LM_EDEVICE;
+  }
+  if (graph_phases) {
+    if (hipMemcpyAsync(graph_phases, S.gphase.p, (size_t)G * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return LM_EDEVICE;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return LM_EDEVICE;
+  return LM_OK;
+}
+
+lm_status lm_match(lm_ctx* c, const lm_csr* g, uint64_t seed, int32_t* mate, uint32_t flags, void* stream,
+                   lm_stats* st) {
+  if (!c || !csr_shape_ok(g)) return LM_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->s.busy_server) return LM_EINVAL;
+  return solve_common(c, g->n, g->nnz, 1, nullptr, g->row_ptr, g->col, g->w, nullptr, seed, mate, flags, stream, st,
+                      nullptr);
+}
+
+lm_status lm_match_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, int64_t nnz, const int64_t* row_ptr,
+                         const int32_t* col, const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate,
+                         uint32_t flags, void* stream, lm_stats* st, int32_t* graph_phases) {
+  if (!c || graphs < 1 || !vtx_off) return LM_EINVAL;
+  if (vtx_off[0] != 0) return LM_EINVAL;
+  for (int32_t g = 0; g < graphs; ++g)
+    if (vtx_off[g + 1] < vtx_off[g]) return LM_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->s.busy_server) return LM_EINVAL;
+  return solve_common(c, vtx_off[graphs], nnz, graphs, vtx_off, row_ptr, col, w, seeds, seed0, mate, flags, stream,
+                      st, graph_phases);
+}
+
+}  // extern "C"
+
+namespace lm {
+// Used by the server and the autotuner (same translation-unit rules as the C
+// ABI entry points: the caller holds the context lock).
+lm_status solve_locked(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, const int64_t* h_vtx_off, const int64_t* row_ptr,
+                       const int32_t* col, const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate,
+                       uint32_t flags, void* stream, lm_stats* st, int32_t* graph_phases) {
+  return solve_common(c, N, nnz, G, h_vtx_off, row_ptr, col, w, seeds, seed0, mate, flags, stream, st, graph_phases);
+}
+Solver& solver_of(lm_ctx* c) { return c->s; }
+std::mutex& mutex_of(lm_ctx* c) { return c->mu; }
+}  // namespace lm

@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+mate[] must be identical element by element (integer work: tolerance 0), and
+the per-phase log (live entries, live rows, matched edges) must equal the
+oracle's iteration log, because both run synchronous phases of the same
+method (paper, Section 2, sequential model; Lemma 1 counts).
+"""
+import numpy as np
+import pytest
+
+import lmgen
+import oracle
+from tests import _pyref as ref
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    import paper_1302_4587_amd as lm
+    c = lm.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(torch_dev, g):
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(g.row_ptr)).to(torch_dev),
+            torch.from_numpy(np.ascontiguousarray(g.col)).to(torch_dev),
+            torch.from_numpy(np.ascontiguousarray(g.w)).to(torch_dev))
+
+
+def _solve(ctx, torch_dev, g, seed, host=False, **kw):
+    if host:
+        mate, st = ctx.match(g.row_ptr, g.col, g.w, seed=seed, **kw)
+        return np.asarray(mate), st
+    rp, col, w = _dev(torch_dev, g)
+    mate, st = ctx.match(rp, col, w, seed=seed, **kw)
+    return mate.cpu().numpy(), st
+
+
+def _assert_parity(g, seed, mate, st, what=""):
+    ref_mate, ref_log = oracle.local_max_graph(g, seed)
+    if not np.array_equal(mate, ref_mate):
+        bad = np.flatnonzero(mate != ref_mate)
+        raise AssertionError(f"{what}: mate differs at {len(bad)} vertices, first {bad[:5]}")
+    assert st.phases == len(ref_log), f"{what}: phases {st.phases} vs oracle {len(ref_log)}"
+    assert st.matched_edges == int((ref_mate >= 0).sum()) // 2
+    L = min(len(st.log), len(ref_log))
+    assert np.array_equal(st.log[:L, 0], 2 * ref_log[:L, 0]), f"{what}: live entries differ"
+    assert np.array_equal(st.log[:L, 1], ref_log[:L, 1]), f"{what}: live rows differ"
+    assert np.array_equal(st.log[:L, 2], ref_log[:L, 2]), f"{what}: matched per phase differ"
+
+
+def test_config1_er_4096(ctx, torch_dev):
+    print("case: ER n=4096 m=32768 seed=1", flush=True)
+    g = lmgen.er(4096, 32768, seed=1)
+    mate, st = _solve(ctx, torch_dev, g, 1)
+    _assert_parity(g, 1, mate, st, "config1")
+    assert np.array_equal(mate, ref.greedy(g, 1))
+
+
+@pytest.mark.parametrize("wkind", ["uniform", "tied", "unit", "signed"])
+def test_random_small_graphs(ctx, torch_dev, wkind):
+    rng = np.random.default_rng({"uniform": 11, "tied": 12, "unit": 13, "signed": 14}[wkind])
+    for it in range(40):
+        n = int(rng.integers(1, 3000))
+        m = int(rng.integers(0, min(n * (n - 1) // 2, 12 * n) + 1))
+        g = lmgen.er(n, m, int(rng.integers(1, 2**62)))
+        if wkind != "uniform":
+            lo, hi, _ = ref.undirected_edges(g)
+            if wkind == "tied":
+                w = rng.integers(1, 4, len(lo)).astype(np.float32)
+            elif wkind == "unit":
+                w = np.ones(len(lo), np.float32)
+            else:
+                w = rng.choice(np.array([-2.5, -0.0, 0.0, 1e-30, 3.0], np.float32), len(lo))
+            g = lmgen.from_edges(n, np.stack([lo, hi], 1), w)
+        seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+        print(f"case: {wkind} it={it} n={n} m={m} seed={seed}", flush=True)
+        mate, st = _solve(ctx, torch_dev, g, seed)
+        _assert_parity(g, seed, mate, st, f"{wkind} it={it}")
+
+
+def _star(k, center=0, n=None, unit=False, rng=None):
+    n = n or k + 1
+    leaves = [i for i in range(n) if i != center][:k]
+    e = np.array([[center, x] for x in leaves])
+    w = np.ones(k) if unit else (rng.random(k) if rng is not None else np.linspace(0.1, 1, k))
+    return lmgen.from_edges(n, e, w)
+
+
+def test_hubs_and_long_rows(ctx, torch_dev):
+    rng = np.random.default_rng(5)
+    cases = [
+        ("star 5000", _star(5000, rng=rng)),
+        ("star 5000 unit", _star(5000, unit=True)),
+        ("star 2048", _star(2048, rng=rng)),
+        ("star 2049", _star(2049, rng=rng)),
+        ("rmat 14", lmgen.rmat(14, 16, seed=3)),
+        ("rmat 15 uniform", lmgen.rmat(15, 16, seed=4, weights="uniform")),
+    ]
+    for name, g in cases:
+        for seed in (1, 99):
+            print(f"case: {name} seed={seed}", flush=True)
+            mate, st = _solve(ctx, torch_dev, g, seed)
+            _assert_parity(g, seed, mate, st, name)
+
+
+@pytest.mark.parametrize("short_max", [16, 64, 256, 1024])
+def test_tuning_invariance(ctx, torch_dev, short_max):
+    """Bins and launch shapes change the work split, never the result."""
+    gs = [lmgen.er(20000, 160000, seed=7), lmgen.rmat(13, 16, seed=8), lmgen.rgg(30000, 10.0, seed=9)]
+    base = ctx.tuning()
+    try:
+        for gp in sorted({1, base["grid_per_cu"]}):
+            for pps in (1, 8):
+                ctx.set_tuning(short_max=short_max, grid_per_cu=gp, phases_per_sync=pps)
+                for i, g in enumerate(gs):
+                    print(f"case: tuning sm={short_max} gp={gp} pps={pps} graph={i}", flush=True)
+                    mate, st = _solve(ctx, torch_dev, g, 3)
+                    _assert_parity(g, 3, mate, st, f"tuning {short_max}/{gp}/{pps} graph {i}")
+    finally:
+        ctx.set_tuning(**base)
+
+
+def test_edge_cases(ctx, torch_dev):
+    cases = [
+        ("isolated", lmgen.from_edges(7, np.zeros((0, 2)), np.zeros(0))),
+        ("single edge", lmgen.from_edges(2, [[0, 1]], [0.5])),
+        ("single edge + isolated", lmgen.from_edges(5, [[3, 1]], [2.0])),
+        ("triangle", lmgen.from_edges(3, [[0, 1], [1, 2], [0, 2]], [0.5, 0.9, 0.7])),
+        ("disjoint", lmgen.from_edges(200, [[2 * i, 2 * i + 1] for i in range(100)], np.linspace(1, 2, 100))),
+        ("increasing path 301", lmgen.from_edges(302, [[i, i + 1] for i in range(301)], np.arange(1, 302))),
+        ("all ties clique 40", lmgen.from_edges(40, [[i, j] for i in range(40) for j in range(i + 1, 40)],
+                                               np.ones(780))),
+    ]
+    for name, g in cases:
+        print(f"case: {name}", flush=True)
+        mate, st = _solve(ctx, torch_dev, g, 5)
+        _assert_parity(g, 5, mate, st, name)
+    g = cases[5][1]
+    mate, st = _solve(ctx, torch_dev, g, 5)
+    assert st.phases == 151  # ceil(301 / 2): one edge per phase
+
+
+def test_empty_graph(ctx, torch_dev):
+    import torch
+    rp = torch.zeros(1, dtype=torch.int64, device=torch_dev)
+    col = torch.zeros(0, dtype=torch.int32, device=torch_dev)
+    w = torch.zeros(0, dtype=torch.float32, device=torch_dev)
+    mate, st = ctx.match(rp, col, w, seed=1)
+    assert mate.numel() == 0 and st.phases == 0
+
+
+def test_entry_order_and_host_inputs(ctx, torch_dev):
+    g = lmgen.er(5000, 40000, seed=21)
+    rng = np.random.default_rng(0)
+    col, w = g.col.copy(), g.w.copy()
+    for v in range(g.n):
+        a, b = g.row_ptr[v], g.row_ptr[v + 1]
+        p = rng.permutation(b - a)
+        col[a:b] = col[a:b][p]
+        w[a:b] = w[a:b][p]
+    shuffled = lmgen.Graph(g.n, g.row_ptr, col, w)
+    print("case: shuffled rows, device", flush=True)
+    m1, _ = _solve(ctx, torch_dev, g, 2)
+    m2, _ = _solve(ctx, torch_dev, shuffled, 2)
+    print("case: host inputs", flush=True)
+    m3, st3 = _solve(ctx, torch_dev, g, 2, host=True)
+    assert np.array_equal(m1, m2) and np.array_equal(m1, m3)
+    _assert_parity(g, 2, m3, st3, "host")
+
+
+def test_repeatable(ctx, torch_dev):
+    g = lmgen.rmat(14, 16, seed=31)
+    outs = []
+    for i in range(10):
+        print(f"case: repeat {i}", flush=True)
+        outs.append(_solve(ctx, torch_dev, g, 4)[0])
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_checks_and_errors(ctx, torch_dev):
+    import paper_1302_4587_amd as lm
+    from paper_1302_4587_amd import _lib as L
+    g = lmgen.er(100, 300, seed=2)
+    bad = g.col.copy()
+    bad[0] = 0  # row 0 gets a self-loop
+    with pytest.raises(lm.LMError) as e:
+        ctx.match(*_dev(torch_dev, lmgen.Graph(g.n, g.row_ptr, bad, g.w)), seed=1, check_graph=True)
+    assert e.value.status == L.LM_EGRAPH
+    badw = g.w.copy()
+    badw[3] = np.nan
+    with pytest.raises(lm.LMError) as e:
+        ctx.match(*_dev(torch_dev, lmgen.Graph(g.n, g.row_ptr, g.col, badw)), seed=1, check_graph=True)
+    assert e.value.status == L.LM_EWEIGHT
+    # host checks: asymmetric weight
+    w2 = g.w.copy()
+    w2[5] += 1.0
+    with pytest.raises(lm.LMError) as e:
+        ctx.match(g.row_ptr, g.col, w2, seed=1, check_graph=True)
+    assert e.value.status == L.LM_EGRAPH
+    # bad offsets on the device: the init kernel flags them
+    rp = g.row_ptr.copy()
+    rp[-1] += 1
+    import torch
+    with pytest.raises(lm.LMError) as e:
+        ctx.match(torch.from_numpy(rp).to(torch_dev), *(_dev(torch_dev, g)[1:]), seed=1)
+    assert e.value.status == L.LM_EGRAPH
+    # the context still works after errors
+    mate, st = _solve(ctx, torch_dev, g, 1)
+    _assert_parity(g, 1, mate, st, "after errors")
+
+
+def test_budget_too_small(torch_dev):
+    import paper_1302_4587_amd as lm
+    from paper_1302_4587_amd import _lib as L
+    g = lmgen.er(4096, 32768, seed=1)
+    with lm.Context(0, hbm_budget_bytes=1 << 16) as small:
+        with pytest.raises(lm.LMError) as e:
+            small.match(*_dev(torch_dev, g), seed=1)
+        assert e.value.status == L.LM_ETOOBIG
+
+
+def test_profile_stats(ctx, torch_dev):
+    g = lmgen.rgg(100000, 10.0, seed=3)
+    mate, st = _solve(ctx, torch_dev, g, 1, profile=True)
+    _assert_parity(g, 1, mate, st, "profile")
+    assert st.kernel_launches["init"] == 1 and st.kernel_launches["argmax"] == 1
+    assert st.kernel_launches["mutual"] >= st.phases and st.kernel_launches["compact"] >= st.phases
+    assert all(st.kernel_ms[k] > 0 for k in ("init", "argmax", "mutual", "compact"))
+    assert st.bytes_alg > 8 * g.nnz
