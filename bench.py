@@ -1,0 +1,203 @@
+"""Benchmark: local-max matching phase loop on one MI355X.
+
+Workload (one step = one whole lm_match solve, every phase of the path):
+2-D random geometric graph, n = 2^24 points uniform in the unit square,
+radius for average degree 10, weight 1 - distance (fp32), seed 1; inputs are
+resident in HBM as torch tensors before the timed region starts.
+
+Prints ONE JSON line with edges/s (input undirected edges / solve time),
+the roofline of the dominant kernel (algorithmic bytes / HIP-event time on
+the solve stream), p50/p99 solve latency, and the CPU oracle timed on the
+host (one core) on the same graph.
+
+  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu] [--batch]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    f, c = math.floor(k), math.ceil(k)
+    return xs[f] if f == c else xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--avg-degree", type=float, default=10.0)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-profile", action="store_true", help="time steps without per-kernel events")
+    ap.add_argument("--batch", action="store_true", help="also time the 4096-graph batch (extra minutes)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lmgen
+    import paper_1302_4587_amd as lm
+
+    dev = torch.device("cuda:0")
+    n = 1 << args.log2n
+    t0 = time.time()
+    g = lmgen.rgg(n, args.avg_degree, args.seed)
+    gen_s = time.time() - t0
+    print(f"bench: generated rgg n={g.n} m={g.m} nnz={g.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    mate = torch.empty(g.n, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    ctx = lm.Context(0)
+    stream = torch.cuda.current_stream()
+    profile = not args.no_profile
+    for i in range(args.warmup):
+        ctx.match(rp, col, w, seed=args.seed, mate=mate, profile=profile)
+    torch.cuda.synchronize()
+    # timed region: exactly K steps
+    lat = []
+    kms = {k: 0.0 for k in lm._lib.KERNEL_KINDS}
+    kbytes = {k: 0.0 for k in lm._lib.KERNEL_KINDS}
+    klaunch = {k: 0 for k in lm._lib.KERNEL_KINDS}
+    phases = None
+    bytes_alg = 0.0
+    dev_ms = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        _, st = ctx.match(rp, col, w, seed=args.seed, mate=mate, profile=profile)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        dev_ms.append(st.device_ms)
+        phases = st.phases
+        bytes_alg = st.bytes_alg
+        for k in kms:
+            kms[k] += st.kernel_ms[k]
+            kbytes[k] += st.kernel_bytes[k]
+            klaunch[k] += st.kernel_launches[k]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    edges_per_s = g.m / (ms_per_step / 1e3)
+
+    # correctness of what was timed (cheap property check at full size)
+    got = mate.cpu().numpy()
+    import oracle  # test infrastructure: certificate and CPU baseline only
+
+    cert = oracle.greedy_certificate(g.n, g.row_ptr, g.col, g.w, args.seed, got)
+
+    roof = None
+    if profile:
+        dom = max(kms, key=lambda k: kms[k])
+        achieved = kbytes[dom] / (kms[dom] / 1e3) / 1e9 if kms[dom] > 0 else 0.0
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": kbytes[dom] / max(klaunch[dom], 1),
+                "avg_launch_us": kms[dom] * 1e3 / max(klaunch[dom], 1),
+                "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in kms.items()},
+                "kernel_launches_per_step": {k: v / args.steps for k, v in klaunch.items()}}
+
+    cpu = None
+    if not args.no_cpu:
+        t1 = time.perf_counter()
+        ref_mate, ref_log = oracle.local_max_graph(g, args.seed)
+        cpu_s = time.perf_counter() - t1
+        if not np.array_equal(ref_mate, got):
+            print("bench: WARNING gpu mate differs from the oracle", file=sys.stderr, flush=True)
+        cpu = {"value": round(g.m / cpu_s, 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"whole graph (n=2^{args.log2n}, m={g.m}), one solve, {cpu_s:.2f}s",
+               "phases": int(len(ref_log)), "matches_gpu": bool(np.array_equal(ref_mate, got))}
+
+    batch = None
+    if args.batch:
+        batch = bench_batch(ctx, dev)
+
+    out = {
+        "metric": "input edges matched/sec + achieved HBM GB/s (1 GPU); batched p50/p99 latency",
+        "value": round(edges_per_s, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"rgg2d n=2^{args.log2n} avg_degree={args.avg_degree:g} w=1-dist seed={args.seed}",
+                   "n": g.n, "m": g.m, "nnz": g.nnz, "phases": phases, "parallelism": "single GPU"},
+        "gbps_alg_whole_solve": round(bytes_alg / (np.median(dev_ms) / 1e3) / 1e9, 1),
+        "device_ms_median": round(float(np.median(dev_ms)), 4),
+        "latency_ms": {"p50": round(_percentile(lat, 50), 4), "p99": round(_percentile(lat, 99), 4)},
+        "certificate_violations": cert,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if batch is not None:
+        out["batch"] = batch
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(ctx, dev):
+    """4096 random graphs, n log-uniform in [2^8, 2^16], avg degree U[4,32]:
+    one batched solve vs a loop of single solves (same GPU)."""
+    import torch
+
+    import lmgen
+
+    b = lmgen.er_batch(4096, 1)
+    vo = b.vtx_off
+    rp = torch.from_numpy(b.row_ptr).to(dev)
+    col = torch.from_numpy(b.col).to(dev)
+    w = torch.from_numpy(b.w).to(dev)
+    mate = torch.empty(b.n_total, dtype=torch.int32, device=dev)
+    ctx.match_batch(vo, rp, col, w, mate=mate)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(10):
+        t = time.perf_counter()
+        ctx.match_batch(vo, rp, col, w, mate=mate, want_graph_phases=False)
+        lat.append((time.perf_counter() - t) * 1e3)
+    # one graph per launch over the same graphs
+    t = time.perf_counter()
+    for k in range(b.graphs):
+        a, e = int(vo[k]), int(vo[k + 1])
+        e0, e1 = int(b.row_ptr[a]), int(b.row_ptr[e])
+        ctx.match(rp[a:e + 1] - e0, col[e0:e1], w[e0:e1], seed=1, mate=mate[a:e])
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t) * 1e3
+    return {"graphs": b.graphs, "n_total": b.n_total, "m_total": b.nnz // 2,
+            "batched_ms": {"p50": round(_percentile(lat, 50), 3), "p99": round(_percentile(lat, 99), 3)},
+            "batched_edges_per_s": round((b.nnz // 2) / (_percentile(lat, 50) / 1e3), 1),
+            "one_graph_per_launch_ms": round(single_ms, 3)}
+
+
+if __name__ == "__main__":
+    main()

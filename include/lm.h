@@ -101,7 +101,8 @@ typedef struct {
 #define LM_K_ARGMAX 1   /* first-phase per-vertex argmax */
 #define LM_K_MUTUAL 2   /* mutual-candidate check and matched marking */
 #define LM_K_COMPACT 3  /* edge compaction fused with the next argmax */
-#define LM_K_KINDS 4
+#define LM_K_PLAN 4     /* single-workgroup stitching of cut rows and run-table scan */
+#define LM_K_KINDS 5
 
 typedef struct {
   int32_t phases;         /* phases with at least one live edge */
@@ -139,13 +140,14 @@ lm_status lm_match_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, in
                          const int32_t* col, const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate,
                          uint32_t flags, void* stream, lm_stats* stats, int32_t* graph_phases);
 
-/* Tuning knobs of the phase kernels. short_max is the largest live degree
- * handled by the shared segmented tiles; longer rows get a workgroup each.
- * Results never depend on them. */
+/* Tuning knobs of the phase kernels. Results never depend on them.
+ * block_entries: the least number of live entries a compaction workgroup
+ * streams (the live entries are cut into at most grid_per_cu * CUs ranges
+ * of at least this size). */
 typedef struct {
-  int32_t short_max;      /* 16..1024, power of two */
-  int32_t grid_per_cu;    /* persistent workgroups per compute unit, 1..8 */
-  int32_t phases_per_sync;/* phases enqueued between host termination checks */
+  int32_t block_entries;   /* 2048..4194304 */
+  int32_t grid_per_cu;     /* persistent workgroups per compute unit, 1..16 */
+  int32_t phases_per_sync; /* phases enqueued between host termination checks, 1..64 */
 } lm_tuning;
 
 lm_status lm_get_tuning(lm_ctx* ctx, lm_tuning* out);

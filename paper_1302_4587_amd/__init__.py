@@ -106,11 +106,12 @@ class Context:
     def tuning(self) -> dict:
         t = _lib.Tuning()
         check(self._lib.lm_get_tuning(self._h, ctypes.byref(t)), "lm_get_tuning")
-        return {"short_max": t.short_max, "grid_per_cu": t.grid_per_cu, "phases_per_sync": t.phases_per_sync}
+        return {"block_entries": t.block_entries, "grid_per_cu": t.grid_per_cu,
+                "phases_per_sync": t.phases_per_sync}
 
-    def set_tuning(self, short_max=None, grid_per_cu=None, phases_per_sync=None):
+    def set_tuning(self, block_entries=None, grid_per_cu=None, phases_per_sync=None):
         cur = self.tuning()
-        t = _lib.Tuning(short_max or cur["short_max"], grid_per_cu or cur["grid_per_cu"],
+        t = _lib.Tuning(block_entries or cur["block_entries"], grid_per_cu or cur["grid_per_cu"],
                         phases_per_sync or cur["phases_per_sync"])
         check(self._lib.lm_set_tuning(self._h, ctypes.byref(t)), "lm_set_tuning")
 
@@ -198,7 +199,8 @@ class Context:
         check(self._lib.lm_autotune_batch(self._h, len(vo) - 1, vo.ctypes.data, int(col.shape[0]), rp, cp, wp, flags,
                                           cache_path.encode() if cache_path else None, ctypes.byref(t)),
               "lm_autotune_batch")
-        return {"short_max": t.short_max, "grid_per_cu": t.grid_per_cu, "phases_per_sync": t.phases_per_sync}
+        return {"block_entries": t.block_entries, "grid_per_cu": t.grid_per_cu,
+                "phases_per_sync": t.phases_per_sync}
 
 
 class Server:

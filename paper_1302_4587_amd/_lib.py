@@ -32,8 +32,8 @@ LM_OUT_DEVICE = 0x2
 LM_CHECK_GRAPH = 0x4
 LM_PROFILE = 0x8
 
-LM_K_INIT, LM_K_ARGMAX, LM_K_MUTUAL, LM_K_COMPACT = range(4)
-KERNEL_KINDS = ("init", "argmax", "mutual", "compact")
+LM_K_INIT, LM_K_ARGMAX, LM_K_MUTUAL, LM_K_COMPACT, LM_K_PLAN = range(5)
+KERNEL_KINDS = ("init", "argmax", "mutual", "compact", "plan")
 
 LM_SERVE_BATCHED = 0
 LM_SERVE_FIFO = 1
@@ -59,12 +59,12 @@ class Stats(ctypes.Structure):
     _fields_ = [("phases", ctypes.c_int32), ("log_len", ctypes.c_int32), ("matched_edges", ctypes.c_int64),
                 ("device_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double),
                 ("log", ctypes.POINTER(PhaseRec)), ("log_cap", ctypes.c_int32),
-                ("k_launches", ctypes.c_int32 * 4), ("k_ms", ctypes.c_double * 4),
-                ("k_bytes", ctypes.c_double * 4)]
+                ("k_launches", ctypes.c_int32 * 5), ("k_ms", ctypes.c_double * 5),
+                ("k_bytes", ctypes.c_double * 5)]
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("short_max", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
+    _fields_ = [("block_entries", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
                 ("phases_per_sync", ctypes.c_int32)]
 
 

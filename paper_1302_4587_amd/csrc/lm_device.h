@@ -1,0 +1,182 @@
+// Workgroup-level primitives for the phase kernels (wave64, 256 lanes).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lm_internal.h"
+#include "lm_key.h"
+
+namespace lm {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// ---- wave64 scans with DPP (row_shr 1,2,4,8 inside rows of 16 lanes, then
+// row_bcast 15 / 31 across rows). Lanes whose DPP source lies outside the
+// pattern keep the identity passed as `old`.
+__device__ __forceinline__ unsigned dpp_u32(unsigned x, unsigned ident, int ctrl_id) {
+  switch (ctrl_id) {
+    case 0: return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x111, 0xf, 0xf, false);
+    case 1: return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x112, 0xf, 0xf, false);
+    case 2: return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x114, 0xf, 0xf, false);
+    case 3: return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x118, 0xf, 0xf, false);
+    case 4: return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x142, 0xa, 0xf, false);
+    default: return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x143, 0xc, 0xf, false);
+  }
+}
+// one lane to the right across the whole wave (lane 0 gets ident)
+__device__ __forceinline__ unsigned dpp_wave_shr1(unsigned x, unsigned ident) {
+  return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ unsigned wave_incl_sum_u32(unsigned x) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) x += dpp_u32(x, 0u, c);
+  return x;
+}
+__device__ __forceinline__ unsigned long long wave_incl_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const unsigned lo = dpp_u32((unsigned)x, 0u, c);
+    const unsigned hi = dpp_u32((unsigned)(x >> 32), 0u, c);
+    x += ((unsigned long long)hi << 32) | lo;
+  }
+  return x;
+}
+__device__ __forceinline__ unsigned wave_incl_max_u32(unsigned x) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) x = max(x, dpp_u32(x, 0u, c));
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T x);
+template <>
+__device__ __forceinline__ unsigned wave_incl_sum<unsigned>(unsigned x) {
+  return wave_incl_sum_u32(x);
+}
+template <>
+__device__ __forceinline__ int wave_incl_sum<int>(int x) {
+  return (int)wave_incl_sum_u32((unsigned)x);
+}
+template <>
+__device__ __forceinline__ unsigned long long wave_incl_sum<unsigned long long>(unsigned long long x) {
+  return wave_incl_sum_u64(x);
+}
+template <>
+__device__ __forceinline__ long long wave_incl_sum<long long>(long long x) {
+  return (long long)wave_incl_sum_u64((unsigned long long)x);
+}
+
+// Exclusive prefix sum over the workgroup; total gets the sum of all lanes.
+template <typename T>
+__device__ __forceinline__ T block_excl_sum(T x, T* sm, T& total) {
+  T incl = wave_incl_sum(x);
+  if (lane_id() == 63) sm[wave_id()] = incl;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    T v = sm[i];
+    pre += (i < wave_id()) ? v : T(0);
+    tot += v;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + incl - x;
+}
+
+// Exclusive prefix max over the workgroup (identity 0).
+__device__ __forceinline__ unsigned block_excl_max(unsigned x, unsigned* sm) {
+  const unsigned incl = wave_incl_max_u32(x);
+  if (lane_id() == 63) sm[wave_id()] = incl;
+  __syncthreads();
+  unsigned pre = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i)
+    if (i < wave_id()) pre = max(pre, sm[i]);
+  __syncthreads();
+  return max(pre, dpp_wave_shr1(incl, 0u));
+}
+
+// Segmented-scan element: f = a segment starts inside, k = running best.
+struct SegKey {
+  unsigned f;
+  Key k;
+};
+
+__device__ __forceinline__ SegKey seg_combine(const SegKey& a, const SegKey& b) {  // a precedes b
+  SegKey r;
+  r.f = a.f | b.f;
+  r.k = b.f ? b.k : key_max(a.k, b.k);
+  return r;
+}
+
+__device__ __forceinline__ SegKey dpp_seg(const SegKey& x, int c) {
+  SegKey y;
+  y.f = dpp_u32(x.f, 0u, c);
+  y.k.w = dpp_u32(x.k.w, 0u, c);
+  y.k.hhi = dpp_u32(x.k.hhi, 0u, c);
+  y.k.hlo = dpp_u32(x.k.hlo, 0u, c);
+  y.k.u = (int)dpp_u32((unsigned)x.k.u, 0xffffffffu, c);
+  return y;
+}
+
+// Exclusive segmented max-scan over the workgroup. A lane whose DPP source is
+// outside the pattern receives the identity (f = 0, empty key), which is
+// neutral for seg_combine.
+__device__ __forceinline__ SegKey block_excl_segscan(SegKey x, SegKey* sm) {
+  SegKey incl = x;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) incl = seg_combine(dpp_seg(incl, c), incl);
+  if (lane_id() == 63) sm[wave_id()] = incl;
+  __syncthreads();
+  SegKey carry;
+  carry.f = 0;
+  carry.k = key_ident();
+  for (int i = 0; i < wave_id(); ++i) carry = seg_combine(carry, sm[i]);
+  __syncthreads();
+  SegKey ex;
+  ex.f = dpp_wave_shr1(incl.f, 0u);
+  ex.k.w = dpp_wave_shr1(incl.k.w, 0u);
+  ex.k.hhi = dpp_wave_shr1(incl.k.hhi, 0u);
+  ex.k.hlo = dpp_wave_shr1(incl.k.hlo, 0u);
+  ex.k.u = (int)dpp_wave_shr1((unsigned)incl.k.u, 0xffffffffu);
+  return seg_combine(carry, ex);
+}
+
+// Smallest index i in [lo, hi) with pred(i) true, assuming pred is monotone
+// (false...false true...true); hi if none. Every lane gets the answer. Each
+// round evaluates pred at 256 evenly spaced points, so an array of n entries
+// takes ceil(log_256 n) rounds of one memory access per lane.
+template <typename Pred>
+__device__ __forceinline__ long long block_lower_bound(long long lo, long long hi, Pred pred, int* sm) {
+  while (hi - lo > 1) {
+    const long long n = hi - lo;
+    const long long step = (n + kBlock - 1) / kBlock;
+    const long long idx = lo + (long long)threadIdx.x * step;
+    const bool p = idx < hi ? pred(idx) : true;
+    if (threadIdx.x == 0) sm[0] = kBlock;
+    __syncthreads();
+    if (p) atomicMin(&sm[0], (int)threadIdx.x);
+    __syncthreads();
+    const int f = sm[0];
+    __syncthreads();
+    // pred false at lo + (f-1)*step (if f > 0), true at lo + f*step
+    if (f == 0) return lo;  // pred(lo) is true
+    const long long nlo = lo + (long long)(f - 1) * step;  // pred(nlo) false
+    const long long nhi = f >= kBlock ? hi : (lo + (long long)f * step < hi ? lo + (long long)f * step : hi);
+    lo = nlo + 1;
+    hi = nhi;
+    if (lo >= hi) return hi;
+    if (hi - lo == 1) return pred(lo) ? lo : hi;
+  }
+  if (hi - lo == 1) return pred(lo) ? lo : hi;
+  return hi;
+}
+
+}  // namespace lm

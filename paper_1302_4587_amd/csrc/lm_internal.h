@@ -1,5 +1,23 @@
 // Internal layout shared by the phase kernels and the host driver of the
 // local-max matching library. Not part of the public C ABI (include/lm.h).
+//
+// Live set R_t of phase t
+// -----------------------
+// The live entries are a sequence of row *pieces*. A piece is a record
+//   int4 { x = v (global vertex id), y = off (first entry in the entry buffer),
+//          z = len (entries), w = g (graph index) | kHeadBit | kMatchedBit }
+// and the pieces are grouped into *runs*: a run is a slice of the piece
+// buffer whose pieces lie back to back in the entry buffer, in the same order.
+// Concatenating the runs in index order gives a "virtual" entry sequence of
+// length L_t. All pieces of one vertex are adjacent in that sequence and
+// exactly one of them carries kHeadBit. A vertex has more than one piece only
+// where a workgroup boundary cut its row in the previous phase.
+//
+// Phase kernels never allocate with atomics: workgroup b of a compaction owns
+// the virtual range [L b / P, L (b+1) / P) and writes its survivors to the same
+// range of the destination buffer, producing exactly one run. A single-block
+// plan kernel stitches the rows that were cut at range boundaries and scans
+// the run table for the next phase.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,32 +25,55 @@
 
 namespace lm {
 
-// Workgroup shape: 4 waves of 64 lanes; a tile pass covers kCap live entries
-// (kItems per lane).
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;            // lanes per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kItems = 8;
-constexpr int kCap = kBlock * kItems;  // 2048
-constexpr int kMaxRowsPerTile = kCap;  // every live row has >= 1 entry
-constexpr int kRing = 4;               // phase counter slots in flight
+constexpr int kItems = 8;              // entries per lane per batch
+constexpr int kCap = kBlock * kItems;  // live entries loaded per batch
+constexpr int kWin = 2 * kBlock;       // pieces considered per batch
+constexpr int kMaxBlocks = 4096;       // run table capacity
+constexpr int kPlanThreads = 1024;
 constexpr unsigned kDropBit = 0x80000000u;
+constexpr int kHeadBit = (int)0x80000000u;
+constexpr int kMatchedBit = 0x40000000;
+constexpr int kGraphMask = 0x3fffffff;
 
-// Per-phase counters. Slot t % kRing describes the live set R_t (written by
-// the kernel that built it) and holds the work counters of phase t.
-struct alignas(64) Slot {
-  unsigned long long short_packed;  // (rows << 32) | entries of R_t's short list
-  unsigned long long long_used;     // entries reserved at the top of R_t's buffer
-  unsigned long long long_kept;     // live entries held by R_t's long rows
-  unsigned long long matched_deg;   // sum of live degree over rows matched in phase t
-  unsigned int long_rows;           // rows in R_t's long list
-  unsigned int matched;             // vertices matched in phase t
-  unsigned int ticket;              // work tickets of the compaction in phase t
-  unsigned int ticket_first;        // work tickets of the first argmax (R_1 only)
-  unsigned int pad[4];
+struct Run {
+  int row_begin;   // first piece of the run in the piece buffer
+  int row_count;   // pieces
+  int phys_begin;  // entry-buffer offset of the run's first entry
+  int ent_count;   // entries
 };
 
-// Host-visible record, same layout as lm_phase_rec.
-struct LogRec {
+// Description of a live set, written by the plan kernel.
+struct Ctl {
+  long long L;     // live entries
+  int nruns;
+  int pieces;      // pieces in all runs
+  int heads;       // live vertices
+  int P;           // workgroups for the compaction over this live set
+  int Pm;          // workgroups for the mutual check over this live set
+  int pad;
+};
+
+// A row cut by a workgroup boundary: the partial result of one side.
+struct Part {
+  int v;        // vertex (global), -1 = none
+  int flags;    // kPartSingle: the segment spans the whole range of the block
+  int kept;     // survivors of this part
+  int out_row;  // piece written for it in the next live set, -1 = none
+  unsigned w, hhi, hlo;
+  int u;        // best neighbour (global id) or -1
+};
+enum : int { kPartSingle = 1 };
+
+struct BlockStat {
+  long long loaded;       // live entries read (unmatched pieces)
+  long long matched_len;  // entries skipped because their row was matched
+  int pieces_out;
+  int pad;
+};
+
+struct LogRec {  // same layout as lm_phase_rec
   long long live_entries;
   long long live_rows;
   long long matched_edges;
@@ -40,81 +81,102 @@ struct LogRec {
 };
 
 struct Totals {
-  unsigned int err;              // LM_ERR_* bits found by the device checks
-  int last_nonempty;             // largest phase index with a live row
-  unsigned long long matched;    // vertices matched so far
+  unsigned int err;
+  int last_nonempty;
+  unsigned long long matched;
 };
 
 enum : unsigned {
-  kErrRowPtr = 1u,     // row_ptr not nondecreasing / wrong ends
-  kErrDegree = 2u,     // a row too long for 32-bit offsets
-  kErrColRange = 4u,   // neighbour id out of range
-  kErrSelfLoop = 8u,   // self-loop
-  kErrWeight = 16u,    // NaN or infinite weight
-  kErrTile = 32u,      // internal: a tile exceeded its capacity
+  kErrRowPtr = 1u,
+  kErrDegree = 2u,
+  kErrColRange = 4u,
+  kErrSelfLoop = 8u,
+  kErrWeight = 16u,
+  kErrInternal = 32u,
 };
 
-// A live row: global vertex id, physical offset of its first live entry in the
-// current entry buffer, live degree, graph index.
-// (int4: x = v, y = off, z = deg, w = g)
-
-struct PhaseArgs {
-  Slot* slots;
-  LogRec* log;
+// Inputs common to the phase kernels.
+struct Common {
   Totals* totals;
-  int log_cap;
-  int t;            // phase index, 1-based
-  int short_max;    // rows of live degree <= short_max use the shared tiles
-  int tile_width;   // virtual entries per tile start window = kCap - short_max
+  int n;                            // vertices of the union
+  int* C;                           // candidate per vertex (global id)
+  unsigned char* state;             // 1 = matched
+  int* mate;                        // output, local ids
+  const int* gbase;                 // first vertex of each graph
+  const unsigned long long* gseed;  // premixed tie-break seed per graph
+  int* gphase;                      // optional: last phase with a live row per graph
+  int graphs;                       // 1: every piece belongs to graph 0 (no table lookups)
+};
 
-  int n;                   // vertices of the union; ids outside [0, n) are ignored
-  long long long_cap;      // capacity of long_out
-  long long tiles_cap;     // capacity of tiles_out
-  int* C;                  // candidate partner per vertex (global id)
-  unsigned char* state;    // 1 = matched
-  int* mate;               // output, local ids
-  const int* gbase;        // first global vertex of each graph
-  const unsigned long long* gseed;  // per-graph premixed seed
-  int* gphase;             // optional: last phase in which each graph had a live row
+// A live set as the kernels see it.
+struct LiveSet {
+  const Ctl* ctl;
+  const Run* runs;
+  const long long* epre;  // nruns+1 entry prefix
+  const int* rpre;        // nruns+1 piece prefix
+  int4* rows;
+  const int* col;
+  const float* w;
+};
 
-  // live set R_t
-  const int4* short_in;
-  const int4* long_in;
-  const int* tiles_in;     // first row of each tile
-  const int* src_col;
-  const float* src_w;
-
-  // live set R_{t+1}
-  int4* short_out;
-  int4* long_out;
-  int* tiles_out;
+struct StreamArgs {
+  Common c;
+  LiveSet in;
+  // outputs (compaction only)
+  Run* runs_out;
+  int4* rows_out;
   int* dst_col;
   float* dst_w;
-  long long dst_cap;       // entries in dst_col / dst_w
+  Part* parts;       // 2 per workgroup: [first, last]
+  BlockStat* bstat;
 };
 
+struct MutualArgs {
+  Common c;
+  LiveSet in;
+  int t;
+  int* mcount;  // matched vertices per workgroup
+};
+
+struct PlanArgs {
+  Common c;
+  int mode;          // kPlanFix | kPlanPrefix | kPlanLog
+  int t;             // phase whose compaction just ran (log index t-1)
+  int first;         // fixup after the first argmax (no pieces written)
+  // fixup of the compaction (or first argmax) that just ran
+  const Ctl* ctl_prev;  // live set it consumed
+  Part* parts;
+  BlockStat* bstat;
+  int4* rows_out;
+  // scan of the run table it produced
+  const Run* runs_new;
+  int nruns_new;         // -1: take ctl_prev->P
+  long long* epre_new;
+  int* rpre_new;
+  Ctl* ctl_new;
+  int pcap, pmcap;       // workgroup caps for the next phase
+  int min_per_block;     // virtual entries per compaction workgroup at least
+  // log
+  const int* mcount;
+  LogRec* log;
+  int log_cap;
+};
+enum : int { kPlanFix = 1, kPlanPrefix = 2, kPlanLog = 4 };
+
 struct InitArgs {
-  Slot* slot1;
-  Totals* totals;
-  const long long* row_ptr;  // N+1
+  Common c;
+  const long long* row_ptr;
   long long nnz;
-  int n;                     // N (vertices of the union)
   int graphs;
-  const long long* vtx_off;  // graphs+1 (device)
-  int short_max;
-  int tile_width;
-  int* mate;
-  unsigned char* state;
-  int4* short_out;
-  int4* long_out;
-  int* tiles_out;
-  long long long_cap;
-  long long tiles_cap;
+  const long long* vtx_off;
+  int nblocks;        // workgroups (= runs of R_1)
+  Run* runs_out;
+  int4* rows_out;
 };
 
 struct CheckArgs {
   Totals* totals;
-  long long nnz;             // entries the caller passed
+  long long nnz;
   const long long* row_ptr;
   const int* col;
   const float* w;
@@ -123,19 +185,16 @@ struct CheckArgs {
   const long long* vtx_off;
 };
 
-// Kernel launchers (lm_kernels.hip).
-hipError_t launch_zero(Slot* slots, Totals* totals, hipStream_t s);
+hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s);
 hipError_t launch_fill_i32(int* p, long long n, int value, hipStream_t s);
-hipError_t launch_init(const InitArgs& a, int grid, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s);
-hipError_t launch_first_argmax(const PhaseArgs& a, int grid, hipStream_t s);
-hipError_t launch_mutual(const PhaseArgs& a, int grid, hipStream_t s);
-hipError_t launch_compact(const PhaseArgs& a, int grid, hipStream_t s);
-// occupancy-derived persistent grid sizes per CU
-int max_blocks_per_cu_compact();
-int max_blocks_per_cu_mutual();
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_plan(const PlanArgs& a, hipStream_t s);
+hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s);
+hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s);
+hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s);
+int max_blocks_per_cu_stream();
 
-// Host mirror of the device tie-break premix (SplitMix64 first output).
 uint64_t premix_seed(uint64_t seed);
 
 }  // namespace lm

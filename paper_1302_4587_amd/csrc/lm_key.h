@@ -61,15 +61,15 @@ __device__ __forceinline__ Key key_max(const Key& a, const Key& b) { return key_
 
 // Running best of one lane over consecutive entries of one row. The hash is
 // evaluated only when a weight tie has to be decided.
-struct Run {
+struct Best {
   unsigned w;
   int u;
   uint64_t h;
   bool hv;
 };
 
-__device__ __forceinline__ Run run_ident() {
-  Run r;
+__device__ __forceinline__ Best best_ident() {
+  Best r;
   r.w = 0u;
   r.u = -1;
   r.h = 0ull;
@@ -77,7 +77,7 @@ __device__ __forceinline__ Run run_ident() {
   return r;
 }
 
-__device__ __forceinline__ void run_update(Run& r, unsigned w, int u, unsigned vloc, uint64_t S) {
+__device__ __forceinline__ void best_update(Best& r, unsigned w, int u, unsigned vloc, uint64_t S) {
   if (w > r.w) {
     r.w = w;
     r.u = u;
@@ -95,7 +95,7 @@ __device__ __forceinline__ void run_update(Run& r, unsigned w, int u, unsigned v
   }
 }
 
-__device__ __forceinline__ Key run_key(const Run& r, unsigned vloc, uint64_t S) {
+__device__ __forceinline__ Key best_key(const Best& r, unsigned vloc, uint64_t S) {
   if (r.u < 0) return key_ident();
   const uint64_t h = r.hv ? r.h : edge_hash(S, vloc, (unsigned)r.u);
   Key k;

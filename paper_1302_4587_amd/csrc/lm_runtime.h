@@ -49,15 +49,16 @@ struct Solver {
   hipStream_t own = nullptr;
   Pool pool;
   lm_tuning tun{};
-  int bpc_compact = 1, bpc_mutual = 4;
+  int bpc_stream = 1;
   bool busy_server = false;
   int last_phases = 0;
 
-  DevBuf C, state, rows[2], longs[2], tiles[2], ecol[2], ew[2];
-  DevBuf gbase, gseed, vtxoff, gphase, slots, totals, log;
+  DevBuf C, state, rows[2], ecol[2], ew[2], runs[2], epre[2], rpre[2];
+  DevBuf ctl, parts, bstat, mcount;
+  DevBuf gbase, gseed, vtxoff, gphase, totals, log;
   DevBuf in_rp, in_col, in_w, out_mate;
 
-  Slot* h_slot = nullptr;
+  Ctl* h_ctl = nullptr;
   Totals* h_totals = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   std::vector<hipEvent_t> evpool;
@@ -71,7 +72,7 @@ struct Solver {
 
 const char* status_text(lm_status st);
 lm_status dev_status(hipError_t e);
-size_t solve_footprint(int64_t N, int64_t nnz, int64_t G, int short_max);
+size_t solve_footprint(int64_t N, int64_t nnz, int64_t G);
 
 // Entry points shared with the server and the autotuner; the caller holds
 // the context lock.

@@ -232,15 +232,15 @@ static bool cache_lookup(const char* path, const std::string& dev, const std::st
     if (line.find("\"device\": \"" + dev + "\"") == std::string::npos) continue;
     if (line.find("\"class\": \"" + cls + "\"") == std::string::npos) continue;
     int sm = 0, gp = 0, pp = 0;
-    const char* p = std::strstr(line.c_str(), "\"short_max\": ");
+    const char* p = std::strstr(line.c_str(), "\"block_entries\": ");
     const char* q = std::strstr(line.c_str(), "\"grid_per_cu\": ");
     const char* r = std::strstr(line.c_str(), "\"phases_per_sync\": ");
     if (!p || !q || !r) continue;
-    sm = std::atoi(p + 13);
+    sm = std::atoi(p + 17);
     gp = std::atoi(q + 15);
     pp = std::atoi(r + 19);
     if (sm > 0 && gp > 0 && pp > 0) {
-      t->short_max = sm;
+      t->block_entries = sm;
       t->grid_per_cu = gp;
       t->phases_per_sync = pp;
       found = true;  // the last matching line wins
@@ -270,9 +270,9 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
   const lm_tuning saved = sv.tun;
   double best_ms = 1e300;
   lm_status rs = LM_OK;
-  const int sms[] = {64, 128, 256, 512};
-  for (int sm : sms) {
-    for (int gp = 1; gp <= std::max(1, sv.bpc_compact); ++gp) {
+  const int bes[] = {4096, 16384, 65536};
+  for (int sm : bes) {
+    for (int gp = 1; gp <= std::max(1, sv.bpc_stream); ++gp) {
       for (int pp : {4, 8}) {
         lm_tuning t{sm, gp, pp};
         sv.tun = t;
@@ -305,7 +305,7 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     if (f)
-      f << "{\"device\": \"" << sv.dev_name << "\", \"class\": \"" << cls << "\", \"short_max\": " << best.short_max
+      f << "{\"device\": \"" << sv.dev_name << "\", \"class\": \"" << cls << "\", \"block_entries\": " << best.block_entries
         << ", \"grid_per_cu\": " << best.grid_per_cu << ", \"phases_per_sync\": " << best.phases_per_sync
         << ", \"ms\": " << best_ms << "}\n";
   }

@@ -77,29 +77,22 @@ void Pool::release(DevBuf& b) {
 }
 
 // Device bytes a solve needs beyond its inputs and outputs.
-size_t solve_footprint(int64_t N, int64_t nnz, int64_t G, int short_max) {
-  const int tw = kCap - short_max;
-  const int64_t ntiles = nnz / tw + 2;
-  const int64_t nlong = std::min<int64_t>(N, nnz / (short_max + 1) + 1);
+size_t solve_footprint(int64_t N, int64_t nnz, int64_t G) {
   size_t b = 0;
-  b += (size_t)N * 4 + 256;                // C
-  b += (size_t)N + 256;                    // state
-  b += 2 * ((size_t)N * 16 + 256);         // short lists
-  b += 2 * ((size_t)nlong * 16 + 256);     // long lists
-  b += 2 * ((size_t)ntiles * 4 + 256);     // tile starts
-  b += 2 * 2 * ((size_t)nnz * 4 + 256);    // entry ping-pong (col, w)
+  b += (size_t)N * 4 + 256;                                // C
+  b += (size_t)N + 256;                                    // state
+  b += 2 * (((size_t)N + 2 * kMaxBlocks + 16) * 16 + 256); // piece buffers
+  b += 2 * 2 * ((size_t)nnz * 4 + 256);                    // entry ping-pong (col, w)
+  b += 2 * ((size_t)kMaxBlocks * (sizeof(Run) + 8 + 4) + 1024);
+  b += (size_t)kMaxBlocks * (2 * sizeof(Part) + sizeof(BlockStat) + 4) + 1024;
   b += (size_t)G * 16 + (size_t)(G + 1) * 8 + 1024;
-  b += sizeof(Slot) * kRing + sizeof(Totals) + sizeof(LogRec) * (size_t)kLogCap + 1024;
+  b += 2 * sizeof(Ctl) + sizeof(Totals) + sizeof(LogRec) * (size_t)kLogCap + 1024;
   return b;
 }
 
 // ------------------------------------------------------------------ solve
 
 lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
-  const int ts = tun.short_max;
-  const int tw = kCap - ts;
-  const int64_t ntiles = nnz / tw + 2;
-  const int64_t nlong = std::min<int64_t>(N, nnz / (ts + 1) + 1);
   lm_status st;
 #define RES(buf, bytes)                 \
   do {                                  \
@@ -109,17 +102,21 @@ lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
   RES(C, (size_t)N * 4);
   RES(state, (size_t)N);
   for (int i = 0; i < 2; ++i) {
-    RES(rows[i], (size_t)N * 16);
-    RES(longs[i], (size_t)nlong * 16);
-    RES(tiles[i], (size_t)ntiles * 4);
+    RES(rows[i], ((size_t)N + 2 * kMaxBlocks + 16) * 16);
     RES(ecol[i], (size_t)nnz * 4);
     RES(ew[i], (size_t)nnz * 4);
+    RES(runs[i], (size_t)kMaxBlocks * sizeof(Run));
+    RES(epre[i], (size_t)(kMaxBlocks + 1) * 8);
+    RES(rpre[i], (size_t)(kMaxBlocks + 1) * 4);
   }
+  RES(ctl, 2 * sizeof(Ctl));
+  RES(parts, (size_t)kMaxBlocks * 2 * sizeof(Part));
+  RES(bstat, (size_t)kMaxBlocks * sizeof(BlockStat));
+  RES(mcount, (size_t)kMaxBlocks * 4);
   RES(gbase, (size_t)G * 4);
   RES(gseed, (size_t)G * 8);
   RES(vtxoff, (size_t)(G + 1) * 8);
   if (want_gphase) RES(gphase, (size_t)G * 4);
-  RES(slots, sizeof(Slot) * kRing);
   RES(totals, sizeof(Totals));
   RES(log, sizeof(LogRec) * (size_t)kLogCap);
 #undef RES
@@ -140,13 +137,12 @@ lm_status Solver::init_device(int device, size_t budget) {
   num_cus = prop.multiProcessorCount;
   dev_name = prop.gcnArchName;
   if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return LM_EDEVICE;
-  if (hipHostMalloc((void**)&h_slot, sizeof(Slot) * kRing) != hipSuccess) return LM_EDEVICE;
+  if (hipHostMalloc((void**)&h_ctl, 2 * sizeof(Ctl)) != hipSuccess) return LM_EDEVICE;
   if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
-  bpc_compact = max_blocks_per_cu_compact();
-  bpc_mutual = max_blocks_per_cu_mutual();
-  tun.short_max = 256;
-  tun.grid_per_cu = bpc_compact;
+  bpc_stream = max_blocks_per_cu_stream();
+  tun.block_entries = 16384;
+  tun.grid_per_cu = bpc_stream;
   tun.phases_per_sync = 4;
   return LM_OK;
 }
@@ -154,19 +150,20 @@ lm_status Solver::init_device(int device, size_t budget) {
 void Solver::shutdown() {
   if (dev >= 0) (void)hipSetDevice(dev);
   if (own) (void)hipStreamSynchronize(own);
-  DevBuf* all[] = {&C, &state, &rows[0], &rows[1], &longs[0], &longs[1], &tiles[0], &tiles[1], &ecol[0], &ecol[1],
-                   &ew[0], &ew[1], &gbase, &gseed, &vtxoff, &gphase, &slots, &totals, &log, &in_rp, &in_col,
-                   &in_w, &out_mate};
+  DevBuf* all[] = {&C,       &state,   &rows[0], &rows[1], &ecol[0], &ecol[1], &ew[0],   &ew[1],
+                   &runs[0], &runs[1], &epre[0], &epre[1], &rpre[0], &rpre[1], &ctl,     &parts,
+                   &bstat,   &mcount,  &gbase,   &gseed,   &vtxoff,  &gphase,  &totals,  &log,
+                   &in_rp,   &in_col,  &in_w,    &out_mate};
   for (DevBuf* b : all) pool.release(*b);
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   evpool.clear();
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  if (h_slot) (void)hipHostFree(h_slot);
+  if (h_ctl) (void)hipHostFree(h_ctl);
   if (h_totals) (void)hipHostFree(h_totals);
   if (own) (void)hipStreamDestroy(own);
   own = nullptr;
-  h_slot = nullptr;
+  h_ctl = nullptr;
   h_totals = nullptr;
   e0 = e1 = nullptr;
 }
@@ -182,15 +179,13 @@ hipEvent_t Solver::event(size_t i) {
 
 // Runs the phase loop over a problem whose inputs are already on the device.
 lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st) {
-  const int ts = tun.short_max;
-  const int tw = kCap - ts;
   const bool prof = (flags & LM_PROFILE) != 0;
   std::vector<std::pair<int, size_t>> marks;  // (kind, event index of start)
   size_t evn = 0;
   auto mark_begin = [&](int kind) -> hipError_t {
     if (!prof) return hipSuccess;
     hipEvent_t e = event(evn);
-    if (!e) return hipErrorOutOfMemory;
+    if (!e || !event(evn + 1)) return hipErrorOutOfMemory;
     marks.push_back({kind, evn});
     evn += 2;
     return hipEventRecord(e, s);
@@ -208,123 +203,170 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     }                                      \
   } while (0)
 
+  const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_stream))));
+  const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 4));
+  Ctl* dctl = (Ctl*)ctl.p;
+  Totals* dtot = (Totals*)totals.p;
+
+  Common c;
+  c.totals = dtot;
+  c.n = (int)p.N;
+  c.C = (int*)C.p;
+  c.state = (unsigned char*)state.p;
+  c.mate = p.mate;
+  c.gbase = (const int*)gbase.p;
+  c.gseed = (const unsigned long long*)gseed.p;
+  c.gphase = p.gphase;
+  c.graphs = (int)p.G;
+
+  auto live = [&](int t) {  // live set R_t
+    const int i = (t - 1) & 1;
+    LiveSet L;
+    L.ctl = dctl + i;
+    L.runs = (const Run*)runs[i].p;
+    L.epre = (const long long*)epre[i].p;
+    L.rpre = (const int*)rpre[i].p;
+    L.rows = (int4*)rows[i].p;
+    L.col = t == 1 ? p.col : (const int*)ecol[t & 1].p;
+    L.w = t == 1 ? p.w : (const float*)ew[t & 1].p;
+    return L;
+  };
+  auto plan_base = [&]() {
+    PlanArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.c = c;
+    a.pcap = pcap;
+    a.pmcap = pmcap;
+    a.min_per_block = std::max(kCap, tun.block_entries);
+    a.nruns_new = -1;
+    a.log = (LogRec*)log.p;
+    a.log_cap = kLogCap;
+    a.mcount = (const int*)mcount.p;
+    return a;
+  };
+
   HIPCHK(hipEventRecord(e0, s));
-  HIPCHK(launch_zero((Slot*)slots.p, (Totals*)totals.p, s));
+  HIPCHK(launch_zero(dctl, 2, dtot, s));
   if (p.gphase) HIPCHK(launch_fill_i32(p.gphase, p.G, 0, s));
-  const int maxgrid_x = std::max(1, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_compact)));
-  const int maxgrid_m = std::max(1, num_cus * bpc_mutual);
   if (flags & LM_CHECK_GRAPH) {
-    CheckArgs ca{(Totals*)totals.p, p.nnz, p.row_ptr, p.col, p.w, (int)p.N, (int)p.G, p.vtx_off};
-    const int grid = (int)std::min<int64_t>(maxgrid_m, (p.N + kBlock - 1) / kBlock + 1);
+    CheckArgs ca{dtot, p.nnz, p.row_ptr, p.col, p.w, (int)p.N, (int)p.G, p.vtx_off};
+    const int grid = (int)std::min<int64_t>(pmcap, (p.N + kBlock - 1) / kBlock + 1);
     HIPCHK(launch_check(ca, grid, s));
   }
-  InitArgs ia;
-  ia.slot1 = (Slot*)slots.p + 1;
-  ia.totals = (Totals*)totals.p;
-  ia.row_ptr = p.row_ptr;
-  ia.nnz = p.nnz;
-  ia.n = (int)p.N;
-  ia.graphs = (int)p.G;
-  ia.vtx_off = p.vtx_off;
-  ia.short_max = ts;
-  ia.tile_width = tw;
-  ia.mate = p.mate;
-  ia.state = (unsigned char*)state.p;
-  ia.short_out = (int4*)rows[0].p;
-  ia.long_out = (int4*)longs[0].p;
-  ia.tiles_out = (int*)tiles[0].p;
-  ia.long_cap = (long long)(longs[0].bytes / 16);
-  ia.tiles_cap = (long long)(tiles[0].bytes / 4);
+  // live set R_1 from the input
+  const int pi = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, (p.N + 16383) / 16384));
   {
-    const int grid = (int)std::min<int64_t>(maxgrid_m, (p.N + kCap - 1) / kCap + 1);
+    InitArgs ia;
+    ia.c = c;
+    ia.row_ptr = p.row_ptr;
+    ia.nnz = p.nnz;
+    ia.graphs = (int)p.G;
+    ia.vtx_off = p.vtx_off;
+    ia.nblocks = pi;
+    ia.runs_out = (Run*)runs[0].p;
+    ia.rows_out = (int4*)rows[0].p;
     HIPCHK(mark_begin(LM_K_INIT));
-    HIPCHK(launch_init(ia, grid, s));
+    HIPCHK(launch_init(ia, s));
+    HIPCHK(mark_end());
+    PlanArgs pa = plan_base();
+    pa.mode = kPlanPrefix;
+    pa.ctl_prev = nullptr;
+    pa.runs_new = (const Run*)runs[0].p;
+    pa.nruns_new = pi;
+    pa.epre_new = (long long*)epre[0].p;
+    pa.rpre_new = (int*)rpre[0].p;
+    pa.ctl_new = dctl + 0;
+    HIPCHK(mark_begin(LM_K_PLAN));
+    HIPCHK(launch_plan(pa, s));
     HIPCHK(mark_end());
   }
-  PhaseArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.slots = (Slot*)slots.p;
-  a.log = (LogRec*)log.p;
-  a.totals = (Totals*)totals.p;
-  a.log_cap = kLogCap;
-  a.short_max = ts;
-  a.tile_width = tw;
-  a.n = (int)p.N;
-  a.long_cap = (long long)(std::min(longs[0].bytes, longs[1].bytes) / 16);
-  a.tiles_cap = (long long)(std::min(tiles[0].bytes, tiles[1].bytes) / 4);
-  a.C = (int*)C.p;
-  a.state = (unsigned char*)state.p;
-  a.mate = p.mate;
-  a.gbase = (const int*)gbase.p;
-  a.gseed = (const unsigned long long*)gseed.p;
-  a.gphase = p.gphase;
-  auto set_phase = [&](int t) {
-    a.t = t;
-    const int li = (t - 1) & 1, lo = t & 1;
-    a.short_in = (const int4*)rows[li].p;
-    a.long_in = (const int4*)longs[li].p;
-    a.tiles_in = (const int*)tiles[li].p;
-    a.short_out = (int4*)rows[lo].p;
-    a.long_out = (int4*)longs[lo].p;
-    a.tiles_out = (int*)tiles[lo].p;
-    if (t == 1) {
-      a.src_col = p.col;
-      a.src_w = p.w;
-    } else {
-      a.src_col = (const int*)ecol[t & 1].p;
-      a.src_w = (const float*)ew[t & 1].p;
-    }
-    a.dst_col = (int*)ecol[(t + 1) & 1].p;
-    a.dst_w = (float*)ew[(t + 1) & 1].p;
-    a.dst_cap = p.nnz;
-  };
-  set_phase(1);
+  // first argmax over R_1
   {
+    StreamArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.c = c;
+    sa.in = live(1);
+    sa.parts = (Part*)parts.p;
+    sa.bstat = (BlockStat*)bstat.p;
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, p.nnz / std::max(kCap, tun.block_entries) + 1));
     HIPCHK(mark_begin(LM_K_ARGMAX));
-    HIPCHK(launch_first_argmax(a, maxgrid_x, s));
+    HIPCHK(launch_first_argmax(sa, gx, s));
+    HIPCHK(mark_end());
+    PlanArgs pa = plan_base();
+    pa.mode = kPlanFix;
+    pa.first = 1;
+    pa.ctl_prev = dctl + 0;
+    pa.parts = (Part*)parts.p;
+    HIPCHK(mark_begin(LM_K_PLAN));
+    HIPCHK(launch_plan(pa, s));
     HIPCHK(mark_end());
   }
   // phase loop
   int t = 1;
-  int64_t est_items = p.nnz / tw + 1;  // work items of the current phase (estimate)
-  int64_t est_rows = p.N;
+  int64_t est_L = p.nnz, est_V = p.N;
   int64_t last_live = -1;
-  bool first_check = true;
-  bool stalled = false;
+  bool first_check = true, stalled = false;
   for (;;) {
     const int chunk = first_check ? 2 : std::max(1, tun.phases_per_sync);
     for (int j = 0; j < chunk; ++j) {
-      set_phase(t);
       const int64_t shrink = (int64_t)1 << std::min(j, 20);
-      const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(maxgrid_m, (est_rows / shrink + kBlock - 1) / kBlock));
-      const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(maxgrid_x, est_items / shrink + 1));
+      const LiveSet in = live(t);
+      MutualArgs ma;
+      ma.c = c;
+      ma.in = in;
+      ma.t = t;
+      ma.mcount = (int*)mcount.p;
+      const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, (est_V / shrink) / kCap + 1));
       HIPCHK(mark_begin(LM_K_MUTUAL));
-      HIPCHK(launch_mutual(a, gm, s));
+      HIPCHK(launch_mutual(ma, gm, s));
       HIPCHK(mark_end());
+      const int lo = t & 1;
+      StreamArgs sa;
+      sa.c = c;
+      sa.in = in;
+      sa.runs_out = (Run*)runs[lo].p;
+      sa.rows_out = (int4*)rows[lo].p;
+      sa.dst_col = (int*)ecol[(t + 1) & 1].p;
+      sa.dst_w = (float*)ew[(t + 1) & 1].p;
+      sa.parts = (Part*)parts.p;
+      sa.bstat = (BlockStat*)bstat.p;
+      const int gx = (int)std::max<int64_t>(
+          1, std::min<int64_t>(pcap, (est_L / shrink) / std::max(kCap, tun.block_entries) + 1));
       HIPCHK(mark_begin(LM_K_COMPACT));
-      HIPCHK(launch_compact(a, gx, s));
+      HIPCHK(launch_compact(sa, gx, s));
+      HIPCHK(mark_end());
+      PlanArgs pa = plan_base();
+      pa.mode = kPlanFix | kPlanPrefix | kPlanLog;
+      pa.t = t;
+      pa.ctl_prev = in.ctl;
+      pa.parts = (Part*)parts.p;
+      pa.bstat = (BlockStat*)bstat.p;
+      pa.rows_out = (int4*)rows[lo].p;
+      pa.runs_new = (const Run*)runs[lo].p;
+      pa.epre_new = (long long*)epre[lo].p;
+      pa.rpre_new = (int*)rpre[lo].p;
+      pa.ctl_new = dctl + lo;
+      HIPCHK(mark_begin(LM_K_PLAN));
+      HIPCHK(launch_plan(pa, s));
       HIPCHK(mark_end());
       ++t;
     }
-    HIPCHK(hipMemcpyAsync(h_slot, (Slot*)slots.p + (t % kRing), sizeof(Slot), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h_totals, totals.p, sizeof(Totals), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_ctl, dctl + ((t - 1) & 1), sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_totals, dtot, sizeof(Totals), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     first_check = false;
     if (h_totals->err) break;
-    const int64_t nshort = (int64_t)(h_slot->short_packed >> 32);
-    const int64_t sent = (int64_t)(h_slot->short_packed & 0xffffffffull);
-    const int64_t nlong = h_slot->long_rows;
-    if (nshort + nlong == 0) break;
+    const int64_t live_now = h_ctl->L;
+    if (live_now == 0) break;
     // every phase of a well-formed graph matches its globally heaviest live
     // edge; no progress over a whole chunk means asymmetric input
-    const int64_t live = sent + (int64_t)h_slot->long_kept;
-    if (live == last_live) {
+    if (live_now == last_live) {
       stalled = true;
       break;
     }
-    last_live = live;
-    est_rows = nshort + nlong;
-    est_items = nlong + (sent + tw - 1) / tw;
+    last_live = live_now;
+    est_L = live_now;
+    est_V = h_ctl->pieces;
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
@@ -355,11 +397,9 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
       st->k_launches[m.first] += 1;
       st->k_ms[m.first] += km;
     }
-    // per-phase records and algorithmic bytes
     const int nrec = std::min(phases, kLogCap);
     std::vector<LogRec> recs((size_t)nrec + 1);
-    if (nrec > 0)
-      HIPCHK(hipMemcpy(recs.data(), log.p, sizeof(LogRec) * (size_t)nrec, hipMemcpyDeviceToHost));
+    if (nrec > 0) HIPCHK(hipMemcpy(recs.data(), log.p, sizeof(LogRec) * (size_t)nrec, hipMemcpyDeviceToHost));
     recs[(size_t)nrec] = LogRec{0, 0, 0, 0};
     st->log_len = 0;
     if (st->log && st->log_cap > 0) {
@@ -367,16 +407,17 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
       std::memcpy(st->log, recs.data(), sizeof(LogRec) * (size_t)nl);
       st->log_len = nl;
     }
+    // algorithmic bytes per kernel kind (what each must move, from the log)
     const double V1 = nrec > 0 ? (double)recs[0].live_rows : 0.0;
     const double L1 = nrec > 0 ? (double)recs[0].live_entries : 0.0;
-    st->k_bytes[LM_K_INIT] = 8.0 * (double)(p.N + 1) + 5.0 * (double)p.N + 16.0 * V1 + 4.0 * L1 / tw;
+    st->k_bytes[LM_K_INIT] = 8.0 * (double)(p.N + 1) + 5.0 * (double)p.N + 16.0 * V1;
     st->k_bytes[LM_K_ARGMAX] = 16.0 * V1 + 8.0 * L1 + 4.0 * V1;
     for (int i = 0; i < nrec; ++i) {
       const double L = (double)recs[i].live_entries, V = (double)recs[i].live_rows;
       const double mv = 2.0 * (double)recs[i].matched_edges, md = (double)recs[i].matched_entries;
       const double L2 = (double)recs[i + 1].live_entries, V2 = (double)recs[i + 1].live_rows;
-      st->k_bytes[LM_K_MUTUAL] += 24.0 * V + 5.0 * mv;
-      st->k_bytes[LM_K_COMPACT] += 17.0 * V + 9.0 * (L - md) + 8.0 * L2 + 20.0 * V2;
+      st->k_bytes[LM_K_MUTUAL] += 24.0 * V + 9.0 * mv;
+      st->k_bytes[LM_K_COMPACT] += 16.0 * V + 9.0 * (L - md) + 8.0 * L2 + 20.0 * V2;
     }
     st->bytes_alg = 0.0;
     for (int k = 0; k < LM_K_KINDS; ++k) st->bytes_alg += st->k_bytes[k];
@@ -470,9 +511,8 @@ lm_status lm_get_tuning(lm_ctx* c, lm_tuning* out) {
 
 lm_status lm_set_tuning(lm_ctx* c, const lm_tuning* t) {
   if (!c || !t) return LM_EINVAL;
-  const int sm = t->short_max;
-  if (sm < 16 || sm > 1024 || (sm & (sm - 1)) != 0) return LM_EINVAL;
-  if (t->grid_per_cu < 1 || t->grid_per_cu > 8) return LM_EINVAL;
+  if (t->block_entries < 2048 || t->block_entries > (1 << 22)) return LM_EINVAL;
+  if (t->grid_per_cu < 1 || t->grid_per_cu > 16) return LM_EINVAL;
   if (t->phases_per_sync < 1 || t->phases_per_sync > 64) return LM_EINVAL;
   c->s.tun = *t;
   return LM_OK;
@@ -519,7 +559,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
     for (int64_t g = 0; g < G; ++g) graph_phases[g] = 0;
   if (N == 0) return LM_OK;
   // memory: footprint plus staging of host inputs / outputs
-  size_t need = solve_footprint(N, nnz, G, S.tun.short_max);
+  size_t need = solve_footprint(N, nnz, G);
   if (!in_dev) need += (size_t)(N + 1) * 8 + (size_t)nnz * 8 + 1024;
   if (!out_dev) need += (size_t)N * 4 + 256;
   if (need > S.pool.budget) return LM_ETOOBIG;

@@ -115,19 +115,21 @@ def test_hubs_and_long_rows(ctx, torch_dev):
             _assert_parity(g, seed, mate, st, name)
 
 
-@pytest.mark.parametrize("short_max", [16, 64, 256, 1024])
-def test_tuning_invariance(ctx, torch_dev, short_max):
-    """Bins and launch shapes change the work split, never the result."""
-    gs = [lmgen.er(20000, 160000, seed=7), lmgen.rmat(13, 16, seed=8), lmgen.rgg(30000, 10.0, seed=9)]
+@pytest.mark.parametrize("block_entries", [2048, 4096, 65536])
+def test_tuning_invariance(ctx, torch_dev, block_entries):
+    """Range sizes and launch shapes change where rows are cut between
+    workgroups, never the result."""
+    gs = [lmgen.er(20000, 160000, seed=7), lmgen.rmat(13, 16, seed=8), lmgen.rgg(30000, 10.0, seed=9),
+          _star(30000, unit=True)]
     base = ctx.tuning()
     try:
         for gp in sorted({1, base["grid_per_cu"]}):
             for pps in (1, 8):
-                ctx.set_tuning(short_max=short_max, grid_per_cu=gp, phases_per_sync=pps)
+                ctx.set_tuning(block_entries=block_entries, grid_per_cu=gp, phases_per_sync=pps)
                 for i, g in enumerate(gs):
-                    print(f"case: tuning sm={short_max} gp={gp} pps={pps} graph={i}", flush=True)
+                    print(f"case: tuning be={block_entries} gp={gp} pps={pps} graph={i}", flush=True)
                     mate, st = _solve(ctx, torch_dev, g, 3)
-                    _assert_parity(g, 3, mate, st, f"tuning {short_max}/{gp}/{pps} graph {i}")
+                    _assert_parity(g, 3, mate, st, f"tuning {block_entries}/{gp}/{pps} graph {i}")
     finally:
         ctx.set_tuning(**base)
 
