@@ -90,6 +90,36 @@ __device__ __forceinline__ T block_excl_sum(T x, T* sm, T& total) {
   return pre + incl - x;
 }
 
+// Single-barrier variants: `sm` (kWaves slots) is written before the barrier
+// and only read after it, so the caller must not write it again before the
+// workgroup has passed another barrier.
+template <typename T>
+__device__ __forceinline__ T block_excl_sum_1b(T x, T* sm, T& total) {
+  const T incl = wave_incl_sum(x);
+  if (lane_id() == 63) sm[wave_id()] = incl;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    const T v = sm[i];
+    pre += (i < wave_id()) ? v : T(0);
+    tot += v;
+  }
+  total = tot;
+  return pre + incl - x;
+}
+
+__device__ __forceinline__ unsigned block_excl_max_1b(unsigned x, unsigned* sm) {
+  const unsigned incl = wave_incl_max_u32(x);
+  if (lane_id() == 63) sm[wave_id()] = incl;
+  __syncthreads();
+  unsigned pre = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i)
+    if (i < wave_id()) pre = max(pre, sm[i]);
+  return max(pre, dpp_wave_shr1(incl, 0u));
+}
+
 // Exclusive prefix max over the workgroup (identity 0).
 __device__ __forceinline__ unsigned block_excl_max(unsigned x, unsigned* sm) {
   const unsigned incl = wave_incl_max_u32(x);

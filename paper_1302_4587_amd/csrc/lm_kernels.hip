@@ -360,50 +360,65 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
 
 // ---------------------------------------------------------------- stream
 
-// Block-uniform state of one compaction workgroup while it walks its range.
+// Compaction (and first argmax) over one virtual range [E0, E1) of the live
+// set, in batches of at most kWin pieces and kCap loaded entries:
+//   1. lane j takes piece cur_k + j; a prefix scan decides which pieces fit;
+//   2. continuity flags (a piece continuing the previous piece's vertex) and,
+//      for every loaded position, the piece it belongs to;
+//   3. coalesced loads of the loaded entries, the neighbour's state, and the
+//      survivors written in order to the destination (ballot ranks);
+//   4. the best candidate of every piece, one lane per piece (a wave per
+//      piece longer than kLong);
+//   5. vertex segments: the lane of a segment's last piece closes it (writes
+//      C[v] and the next live set's piece record); the batch's last segment
+//      stays open while its row may continue.
+// Candidate keys travel as (ordered weight, local neighbour id): the 64-bit
+// tie-break hash is a bijection of the neighbour for a fixed vertex, so the
+// pair identifies the key and the hash is recomputed when a full key is due.
+
+// Open vertex segment carried from one batch to the next.
 struct Carry {
-  int active;      // a segment is open from the previous batch
-  int v, g;        // its vertex and graph
-  unsigned w, hhi, hlo;
+  int active;
+  int v, g, base;  // vertex, graph, first vertex of the graph
+  unsigned w;      // best ordered weight so far (0 = none)
   int u;           // best neighbour so far (local id) or -1
   int kept;        // survivors so far
   int out_start;   // destination offset of its first survivor, -1 if none
   int is_first;    // it is the segment that contains the range start
 };
 
+constexpr int kLong = 32;                        // longer pieces are reduced by a whole wave
+constexpr int kLongMax = kCap / (kLong + 1) + 1;  // long pieces per batch at most
+
 struct StreamSmem {
   int p_v[kWin];
-  int p_off[kWin];
+  int p_delta[kWin];            // entry-buffer offset minus batch position of the piece's first entry
   int p_g[kWin];
-  int p_base[kWin];                  // first vertex of the piece's graph
-  unsigned short p_vo[kWin];    // first loaded position of the piece in the batch
-  unsigned short p_take[kWin];  // loaded entries of the piece in the batch
-  unsigned short p_seg[kWin];   // segment id: head piece + 1, 0 = continuation
-  unsigned char p_fl[kWin];     // kFl* flags
-  unsigned short s_kst[kWin + 1];
-  unsigned short s_kend[kWin + 1];
-  int s_best[kWin + 1];         // best local id per segment
-  unsigned short rowof[kCap];
-  int e_col[kCap];
-  unsigned e_w[kCap];
-  unsigned long long s64[kWaves];
-  unsigned s32[kWaves];
-  SegKey sseg[kWaves];
+  int p_base[kWin];             // first vertex of the piece's graph
+  unsigned short p_vo[kWin];    // batch position of the piece's first loaded entry
+  unsigned short p_ld[kWin];    // loaded entries of the piece
+  unsigned p_w[kWin];           // best ordered weight of the piece (0 = none)
+  int p_u[kWin];                // best neighbour of the piece (local id) or -1
+  unsigned char p_cont[kWin];   // the piece continues the previous piece's vertex
+  unsigned short rowof[kCap];   // piece of every loaded position
+  unsigned short kpre[kCap + 2];  // survivors before every loaded position; [NLD] = total
+  uint2 e_cw[kCap];             // {ordered weight or 0 when dropped, local neighbour id}
+  unsigned long long s_scan[kWaves];
+  unsigned s_max[kWaves];
+  unsigned s_cnt[kItems * kWaves];
+  unsigned s_emit[kWaves];
+  int longlist[kLongMax];
   int lb[1];
-  Key firstkey, lastkey;        // full keys of the batch's first and last segment
-  // walk state
   Carry carry;
+  Part pf;  // the range's first segment when its row began before E0
+  int pf_valid;
   int cur_k, cur_o, cur_r;
   int run_rb, run_lo, run_hi;  // cached run cur_r: row_begin, rpre[cur_r], rpre[cur_r+1]
   long long pos;
   int out_cursor, row_cursor;
-  int nt, nld, consumed;
-  int last_partial, last_take;
-  int out_base_batch;
+  int nt, nld, last_partial, next_cont, nlong;
   int open_left;
 };
-
-enum : unsigned char { kFlHead = 1, kFlSegEnd = 2, kFlSegFirst = 4, kFlMatched = 8 };
 
 // Global row index of piece k, walking forward from run r (updated).
 __device__ __forceinline__ int piece_row(const LiveSet& in, long long k, int& r, int nruns) {
@@ -411,16 +426,71 @@ __device__ __forceinline__ int piece_row(const LiveSet& in, long long k, int& r,
   return in.runs[r].row_begin + (int)(k - in.rpre[r]);
 }
 
+// Full key of the candidate (w, u) of vertex vloc (local ids).
+__device__ __forceinline__ Key full_key(unsigned w, int u, unsigned vloc, unsigned long long S) {
+  if (u < 0) return key_ident();
+  const uint64_t h = edge_hash(S, vloc, (unsigned)u);
+  Key k;
+  k.w = w;
+  k.hhi = (unsigned)(h >> 32);
+  k.hlo = (unsigned)h;
+  k.u = u;
+  return k;
+}
+
+__device__ __forceinline__ Key dpp_key(const Key& x, int c) {
+  Key y;
+  y.w = dpp_u32(x.w, 0u, c);
+  y.hhi = dpp_u32(x.hhi, 0u, c);
+  y.hlo = dpp_u32(x.hlo, 0u, c);
+  y.u = (int)dpp_u32((unsigned)x.u, 0xffffffffu, c);
+  return y;
+}
+
+// Largest key of the wave, returned to every lane.
+__device__ __forceinline__ Key wave_max_key(Key k) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) k = key_max(dpp_key(k, c), k);
+  Key r;
+  r.w = (unsigned)__builtin_amdgcn_readlane((int)k.w, 63);
+  r.hhi = (unsigned)__builtin_amdgcn_readlane((int)k.hhi, 63);
+  r.hlo = (unsigned)__builtin_amdgcn_readlane((int)k.hlo, 63);
+  r.u = __builtin_amdgcn_readlane(k.u, 63);
+  return r;
+}
+
+template <bool FIRST>
+__device__ __forceinline__ void close_segment(const StreamArgs& a, StreamSmem& sm, bool cut_left, int v, int g,
+                                              int base, unsigned w, int u, unsigned long long S, int kept,
+                                              int start, int slot) {
+  if (cut_left) {  // the row began in the previous range: the plan kernel merges the parts
+    const Key k = full_key(w, u, (unsigned)(v - base), S);
+    Part p;
+    p.v = v;
+    p.flags = 0;
+    p.kept = kept;
+    p.out_row = slot;
+    p.w = k.w;
+    p.hhi = k.hhi;
+    p.hlo = k.hlo;
+    p.u = u >= 0 ? base + u : -1;
+    sm.pf = p;
+    sm.pf_valid = 1;
+    if (!FIRST && slot >= 0) a.rows_out[slot] = make_int4(v, start, kept, g & kGraphMask);
+    return;
+  }
+  if (u >= 0) a.c.C[v] = base + u;
+  if (!FIRST && slot >= 0) a.rows_out[slot] = make_int4(v, start, kept, (g & kGraphMask) | kHeadBit);
+}
+
 template <bool FIRST>
 __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem& sm,
                              unsigned long long seed0) {
   const int tid = threadIdx.x;
+  const int lane = lane_id(), wv = wave_id();
   const bool single = a.c.graphs == 1;
   const long long E0 = ctl.L * b / ctl.P;
   const long long E1 = ctl.L * (b + 1) / ctl.P;
-  Part pf_out, pl_out;
-  pf_out.v = -1;
-  pl_out.v = -1;
   if (E0 >= E1) {
     if (tid == 0) {
       if (!FIRST) {
@@ -437,8 +507,10 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         st.pad = 0;
         a.bstat[b] = st;
       }
-      a.parts[2 * b] = pf_out;
-      a.parts[2 * b + 1] = pl_out;
+      Part none;
+      none.v = -1;
+      a.parts[2 * b] = none;
+      a.parts[2 * b + 1] = none;
     }
     return;
   }
@@ -452,17 +524,17 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       [&](long long i) { return (long long)(a.in.rows[run0.row_begin + i].y - run0.phys_begin) > lo; }, sm.lb);
   const int pidx = (int)ip - 1;
   const int k0 = a.in.rpre[r0] + pidx;
-  const int4 rec0 = a.in.rows[run0.row_begin + pidx];
-  const int o0 = (int)(lo - (rec0.y - run0.phys_begin));
   if (tid == 0) {
+    const int4 rec0 = a.in.rows[run0.row_begin + pidx];
+    const int o0 = (int)(lo - (rec0.y - run0.phys_begin));
+    // the range starts inside a row when it cuts a piece or when the previous
+    // piece (of this run or of the last non-empty run before it) has the same vertex
     int open_left = o0 > 0;
     if (!open_left && k0 > 0) {
-      int rr = 0;
-      // run of piece k0-1: the last non-empty run before r0 (or r0 itself)
       if (pidx > 0) {
         open_left = a.in.rows[run0.row_begin + pidx - 1].x == rec0.x;
       } else {
-        rr = r0 - 1;
+        int rr = r0 - 1;
         while (rr > 0 && a.in.runs[rr].row_count == 0) --rr;
         const Run rp = a.in.runs[rr];
         if (rp.row_count > 0) open_left = a.in.rows[rp.row_begin + rp.row_count - 1].x == rec0.x;
@@ -480,537 +552,368 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     sm.row_cursor = k0 + b;
     sm.carry.active = 0;
     sm.carry.v = -1;
-    sm.carry.kept = 0;
-    sm.carry.out_start = -1;
-    sm.carry.u = -1;
-    sm.carry.is_first = 0;
+    sm.pf_valid = 0;
   }
   __syncthreads();
+  const bool open_left = sm.open_left != 0;
   const int row_start = k0 + b;
-  long long loaded_total = 0, matched_total = 0;  // lane 0 only
+  long long loaded_total = 0;  // lane 0 only
   bool first_batch = true;
   for (;;) {
     const long long pos = sm.pos;
     if (pos >= E1) break;
     const int cur_k = sm.cur_k, cur_o = sm.cur_o;
-    int rr = sm.cur_r;
     const int run_rb = sm.run_rb, run_lo = sm.run_lo, run_hi = sm.run_hi;
+    const int out_base = sm.out_cursor, row_base = sm.row_cursor;
     const Carry carry = sm.carry;
-    __syncthreads();
-    // ---- 1. window of pieces: lane t owns pieces 2t, 2t+1
-    int4 rec[2];
-    long long cov[2];
-    int ld[2];
-    int rrh[2];
-    bool mt[2], valid[2];
-    unsigned long long mine = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * tid + h;
-      const long long gk = (long long)cur_k + j;
-      valid[h] = gk < ctl.pieces;
-      cov[h] = 0;
-      ld[h] = 0;
-      mt[h] = false;
-      rec[h] = make_int4(-1, 0, 0, 0);
-      rrh[h] = rr;
-      if (valid[h]) {
-        // pieces of the cached run need no run-table reads
-        const int row = gk < run_hi ? run_rb + (int)(gk - run_lo) : piece_row(a.in, gk, rr, ctl.nruns);
-        rec[h] = a.in.rows[row];
-        rrh[h] = gk < run_hi ? rr : rr;
-        const int sub = j == 0 ? cur_o : 0;
-        rec[h].y += sub;
-        rec[h].z -= sub;
-        if (!FIRST)
-          mt[h] = (rec[h].w & kHeadBit) ? (rec[h].w & kMatchedBit) != 0 : a.c.state[rec[h].x] != 0;
-        cov[h] = rec[h].z;
-      }
-      mine += ((unsigned long long)cov[h] << 32) | (unsigned long long)(mt[h] ? 0 : (unsigned)cov[h]);
+    int rr = sm.cur_r;
+    {
+      unsigned* z = reinterpret_cast<unsigned*>(sm.rowof);
+      for (int i = tid; i < kCap / 2; i += kBlock) z[i] = 0u;
     }
+    if (tid == 0) {
+      sm.nt = 0;
+      sm.nlong = 0;
+    }
+    // ---- 1. window: lane j looks at piece cur_k + j
+    const long long gk = (long long)cur_k + tid;
+    const bool valid = gk < ctl.pieces;
+    int4 rec = make_int4(-1, 0, 0, 0);
+    bool mt = false;
+    if (valid) {
+      const int row = gk < run_hi ? run_rb + (int)(gk - run_lo) : piece_row(a.in, gk, rr, ctl.nruns);
+      rec = a.in.rows[row];
+      if (tid == 0) {
+        rec.y += cur_o;
+        rec.z -= cur_o;
+      }
+      if (!FIRST) mt = (rec.w & kHeadBit) ? (rec.w & kMatchedBit) != 0 : a.c.state[rec.x] != 0;
+    }
+    const long long cov = valid ? rec.z : 0;
     unsigned long long tot;
-    const unsigned long long ex = block_excl_sum<unsigned long long>(mine, sm.s64, tot);
+    const unsigned long long ex = block_excl_sum_1b<unsigned long long>(
+        ((unsigned long long)cov << 32) | (mt ? 0ull : (unsigned long long)cov), sm.s_scan, tot);
     const long long Rrem = E1 - pos;
-    long long cpre = (long long)(ex >> 32);
-    long long lpre = (long long)(ex & 0xffffffffull);
-    int take[2];
-    unsigned taken_cnt = 0, loaded = 0;
-    long long consumed = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      take[h] = 0;
-      if (valid[h] && cpre < Rrem && lpre < kCap) {
-        long long tk = std::min<long long>(cov[h], Rrem - cpre);
-        if (!mt[h]) tk = std::min<long long>(tk, kCap - lpre);
-        take[h] = (int)tk;
-      }
-      if (take[h] > 0) {
-        ++taken_cnt;
-        consumed += take[h];
-        if (!mt[h]) loaded += (unsigned)take[h];
-      }
-      cpre += cov[h];
-      lpre += mt[h] ? 0 : cov[h];
+    const long long cpre = (long long)(ex >> 32);  // virtual entries before the piece
+    const long long lpre = (long long)(ex & 0xffffffffull);  // loadable entries before the piece
+    // Whole pieces are taken while the range and the load budget last; the
+    // last one may be cut. Matched pieces are skipped without loading.
+    int take = 0;
+    if (valid && cpre < Rrem && lpre < kCap) {
+      long long tk = cov < Rrem - cpre ? cov : Rrem - cpre;
+      if (!mt && tk > kCap - lpre) tk = kCap - lpre;
+      take = (int)tk;
     }
-    // counts: taken pieces and loaded entries (prefix), consumed (total)
-    unsigned long long cnt2 = ((unsigned long long)consumed << 32) | ((unsigned long long)taken_cnt << 16) | loaded;
-    unsigned long long tot2;
-    const unsigned long long ex2 = block_excl_sum<unsigned long long>(cnt2, sm.s64, tot2);
-    const int nt = (int)((tot2 >> 16) & 0xffffu);
-    const int NLD = (int)(tot2 & 0xffffu);
-    unsigned vo = (unsigned)(ex2 & 0xffffu);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * tid + h;
-      if (take[h] > 0) {
-        sm.p_v[j] = rec[h].x;
-        sm.p_off[j] = rec[h].y;
-        const int g = rec[h].w & kGraphMask;
-        sm.p_g[j] = g;
-        sm.p_base[j] = single ? 0 : a.c.gbase[g];
-        sm.p_vo[j] = (unsigned short)vo;
-        sm.p_take[j] = (unsigned short)(mt[h] ? 0 : take[h]);
-        sm.p_fl[j] = mt[h] ? kFlMatched : 0;
-        if (!mt[h]) vo += (unsigned)take[h];
-        if (j == nt - 1) {
-          sm.last_partial = take[h] < cov[h];
-          sm.last_take = take[h];
-          sm.cur_r = rrh[h];
-        }
+    const int ldt = mt ? 0 : take;
+    if (take > 0) {
+      const bool next_taken = take == cov && tid + 1 < kWin && gk + 1 < ctl.pieces && cpre + cov < Rrem &&
+                              lpre + (mt ? 0 : cov) < kCap;
+      if (!next_taken) {  // this lane holds the batch's last piece
+        sm.nt = tid + 1;
+        sm.nld = (int)lpre + ldt;
+        sm.last_partial = take < cov;
+        sm.cur_r = rr;
       }
+      const int g = rec.w & kGraphMask;
+      sm.p_delta[tid] = rec.y - (int)lpre;
+      sm.p_g[tid] = g;
+      sm.p_base[tid] = single ? 0 : a.c.gbase[g];
+      sm.p_vo[tid] = (unsigned short)lpre;
+      sm.p_ld[tid] = (unsigned short)ldt;
+      if (ldt > 0) sm.rowof[lpre] = (unsigned short)tid;
+      if (ldt > kLong) sm.longlist[atomicAdd(&sm.nlong, 1)] = tid;
     }
+    if (valid) sm.p_v[tid] = rec.x;
+    __syncthreads();
+    const int nt = sm.nt;
     if (nt == 0) {  // nothing consumable: the live set is inconsistent; stop, never spin
       if (tid == 0) atomicOr(&a.c.totals->err, kErrInternal);
       break;
     }
-    if (tid == 0) {
-      sm.nt = nt;
-      sm.nld = NLD;
-      sm.consumed = (int)(tot2 >> 32);
-      sm.firstkey = key_ident();
-      sm.lastkey = key_ident();
+    const int NLD = sm.nld;
+    const bool mine = tid < nt;
+    // ---- 2. vertex continuity; piece of every loaded position (prefix max)
+    bool cont = false;
+    if (mine) {
+      cont = tid == 0 ? (carry.active && carry.v == rec.x) : (sm.p_v[tid - 1] == rec.x);
+      sm.p_cont[tid] = cont ? 1 : 0;
     }
-    __syncthreads();
-    // ---- 2. segment heads (by vertex) and segment ids
-    unsigned hmax = 0;
-    unsigned char hflag[2] = {0, 0};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * tid + h;
-      if (j < nt) {
-        const int v = sm.p_v[j];
-        const bool head = j == 0 ? !(carry.active && carry.v == v) : (sm.p_v[j - 1] != v);
-        hflag[h] = head ? kFlHead : 0;
-        if (head) hmax = (unsigned)(j + 1);
-      }
-    }
-    // segment id of piece j = largest head index + 1 at or before j
-    unsigned segs[2];
-    {
-      const unsigned carry_in = block_excl_max(hmax, sm.s32);
-      unsigned run_seg = carry_in;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = 2 * tid + h;
-        if (hflag[h]) run_seg = (unsigned)(j + 1);
-        segs[h] = run_seg;
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * tid + h;
-      if (j < nt) {
-        sm.p_seg[j] = (unsigned short)segs[h];
-        sm.p_fl[j] |= hflag[h];
-      }
-    }
-    for (int s = tid; s <= nt; s += kBlock) {
-      sm.s_kst[s] = 0;
-      sm.s_kend[s] = 0;
-      sm.s_best[s] = -1;
-    }
-    for (int q = tid; q < NLD; q += kBlock) sm.rowof[q] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * tid + h;
-      if (j < nt) {
-        const unsigned s = segs[h];
-        const bool last_of_seg = (j + 1 >= nt) || (sm.p_seg[j + 1] != s);
-        const bool first_of_seg = s == 0 ? (j == 0) : (j == (int)s - 1);
-        unsigned char f = sm.p_fl[j];
-        if (last_of_seg) f |= kFlSegEnd;
-        if (first_of_seg) f |= kFlSegFirst;
-        sm.p_fl[j] = f;
-        if (sm.p_take[j] > 0) sm.rowof[sm.p_vo[j]] = (unsigned short)j;
-      }
-    }
-    __syncthreads();
-    // ---- 3. piece of every loaded position: prefix max of the piece heads
+    if (tid == nt) sm.next_cont = (valid && sm.p_v[nt - 1] == rec.x) ? 1 : 0;
+    if (tid == 0 && nt == kWin) sm.next_cont = -1;  // the window ended: unknown, keep the segment open
     {
       const int q0 = tid * kItems;
       unsigned runv = 0, vals[kItems];
 #pragma unroll
       for (int i = 0; i < kItems; ++i) {
-        const int q = q0 + i;
-        if (q < NLD) runv = max(runv, (unsigned)sm.rowof[q]);
+        runv = max(runv, (unsigned)sm.rowof[q0 + i]);
         vals[i] = runv;
       }
-      const unsigned cin = block_excl_max(runv, sm.s32);
+      const unsigned cin = block_excl_max_1b(runv, sm.s_max);
 #pragma unroll
-      for (int i = 0; i < kItems; ++i) {
-        const int q = q0 + i;
-        if (q < NLD) sm.rowof[q] = (unsigned short)max(cin, vals[i]);
-      }
+      for (int i = 0; i < kItems; ++i)
+        if (q0 + i < NLD) sm.rowof[q0 + i] = (unsigned short)max(cin, vals[i]);
     }
     __syncthreads();
-    // ---- 4. striped coalesced loads, neighbour state gather
+    // ---- 3. coalesced loads, neighbour state, survivors in order
+    unsigned ktot = 0;
     {
       int cc[kItems];
       float ww[kItems];
+      int jp[kItems];
 #pragma unroll
       for (int jj = 0; jj < kItems; ++jj) {
         const int q = tid + kBlock * jj;
         cc[jj] = 0;
         ww[jj] = 0.f;
+        jp[jj] = 0;
         if (q < NLD) {
           const int j = sm.rowof[q];
-          const int addr = sm.p_off[j] + (q - (int)sm.p_vo[j]);
+          jp[jj] = j;
+          const int addr = q + sm.p_delta[j];
           cc[jj] = a.in.col[addr];
           ww[jj] = a.in.w[addr];
         }
       }
+      unsigned rank[kItems];
+      unsigned kpm = 0;
+      const unsigned long long lt = lanemask_lt();
 #pragma unroll
       for (int jj = 0; jj < kItems; ++jj) {
         const int q = tid + kBlock * jj;
+        bool kp = false;
         if (q < NLD) {
-          const int j = sm.rowof[q];
-          unsigned col = (unsigned)cc[jj];
-          const unsigned ug = (unsigned)(sm.p_base[j] + cc[jj]);
-          if (cc[jj] < 0 || ug >= (unsigned)a.c.n)
-            col |= kDropBit;  // id outside the graph: never a candidate
-          else if (!FIRST && a.c.state[ug] != 0)
-            col |= kDropBit;
-          sm.e_col[q] = (int)col;
-          sm.e_w[q] = __float_as_uint(ww[jj]);
+          const int base = single ? 0 : sm.p_base[jp[jj]];
+          const unsigned ug = (unsigned)(base + cc[jj]);
+          kp = cc[jj] >= 0 && ug < (unsigned)a.c.n;  // ids outside the graph are dropped
+          if (!FIRST && kp) kp = a.c.state[ug] == 0;
+          sm.e_cw[q] = make_uint2(kp ? ord_weight_bits(__float_as_uint(ww[jj])) : 0u, (unsigned)cc[jj]);
+        }
+        if (!FIRST) {
+          const unsigned long long bal = __ballot(kp);
+          rank[jj] = (unsigned)__popcll(bal & lt);
+          if (lane == 0) sm.s_cnt[jj * kWaves + wv] = (unsigned)__popcll(bal);
+          kpm |= (kp ? 1u : 0u) << jj;
         }
       }
+      __syncthreads();
+      if (!FIRST) {
+        // survivors before (round jj, wave w), in position order q = tid + kBlock * jj
+        const unsigned c = lane < kItems * kWaves ? sm.s_cnt[lane] : 0u;
+        const unsigned incl = wave_incl_sum_u32(c);
+        ktot = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+        const unsigned excl = incl - c;
+#pragma unroll
+        for (int jj = 0; jj < kItems; ++jj) {
+          const int q = tid + kBlock * jj;
+          const unsigned kq = (unsigned)__builtin_amdgcn_readlane((int)excl, jj * kWaves + wv) + rank[jj];
+          if (q < NLD) {
+            sm.kpre[q] = (unsigned short)kq;
+            if ((kpm >> jj) & 1u) {
+              a.dst_col[out_base + (int)kq] = cc[jj];
+              a.dst_w[out_base + (int)kq] = ww[jj];
+            }
+          }
+        }
+        if (tid == 0) sm.kpre[NLD] = (unsigned short)ktot;
+      }
     }
-    __syncthreads();
-    // ---- 5. blocked pass: kept counts, segmented argmax
-    const int q0 = tid * kItems;
-    unsigned mycol[kItems], myw[kItems];
-    unsigned short myseg[kItems];
-    unsigned char mypos[kItems];  // 1 = first entry of its segment, 2 = last entry
-    unsigned kc = 0;
-    SegKey agg;
-    agg.f = 0;
-    agg.k = key_ident();
-    Key p1 = key_ident();
-    int c0_seg = -1;
-    bool c0_ends = false, head0 = false;
-    {
+    // ---- 4. best candidate per piece
+    const int my_vo = (int)lpre;
+    int mybase = 0;
+    unsigned long long mySeed = seed0;
+    unsigned myvloc = 0;
+    if (mine) {
+      mybase = single ? 0 : sm.p_base[tid];
+      if (!single) mySeed = a.c.gseed[rec.w & kGraphMask];
+      myvloc = (unsigned)(rec.x - mybase);
+    }
+    unsigned bw = 0u;
+    int bu = -1;
+    if (mine && ldt <= kLong) {
       Best run = best_ident();
-      int cur_s = -1;
-      bool first_open = true;
-      unsigned vloc = 0;
-      unsigned long long S = 0;
-#pragma unroll
-      for (int i = 0; i < kItems; ++i) {
-        const int q = q0 + i;
-        myseg[i] = 0xffff;
-        mypos[i] = 0;
-        if (q >= NLD) continue;
-        const int j = sm.rowof[q];
-        const int s = sm.p_seg[j];
-        const unsigned char fl = sm.p_fl[j];
-        const bool seg_first = (fl & kFlSegFirst) && q == (int)sm.p_vo[j];
-        const bool seg_last = (fl & kFlSegEnd) && q == (int)sm.p_vo[j] + (int)sm.p_take[j] - 1;
-        if (s != cur_s) {
-          S = single ? seed0 : a.c.gseed[sm.p_g[j]];
-          vloc = (unsigned)(sm.p_v[j] - sm.p_base[j]);
-          if (cur_s < 0) {
-            c0_seg = s;
-            head0 = seg_first && s >= 1;
-            agg.f = head0 ? 1u : 0u;
-          } else {
-            agg.f = 1u;  // a segment starts inside this lane's items
-          }
-          cur_s = s;
-          run = best_ident();
-        }
-        myseg[i] = (unsigned short)s;
-        mypos[i] = (seg_first ? 1 : 0) | (seg_last ? 2 : 0);
-        const unsigned col = (unsigned)sm.e_col[q];
-        const unsigned wb = sm.e_w[q];
-        mycol[i] = col;
-        myw[i] = wb;
-        if (!(col & kDropBit)) {
-          ++kc;
-          best_update(run, ord_weight_bits(wb), (int)col, vloc, S);
-        }
-        if (seg_last) {
-          const Key k = best_key(run, vloc, S);
-          if (first_open) {
-            p1 = k;
-            c0_ends = true;
-            first_open = false;
-          } else {
-            sm.s_best[s] = k.u;
-            if (q == NLD - 1) sm.lastkey = k;
-          }
-        }
+      for (int i = 0; i < ldt; ++i) {
+        const uint2 e = sm.e_cw[my_vo + i];
+        if (e.x != 0u) best_update(run, e.x, (int)e.y, myvloc, mySeed);
       }
-      if (cur_s >= 0) {
-        if (first_open) p1 = best_key(run, vloc, S);
-        agg.k = best_key(run, vloc, S);
-      }
-    }
-    unsigned ktot;
-    const unsigned kpre = block_excl_sum<unsigned>(kc, sm.s32, ktot);
-    SegKey cin = block_excl_segscan(agg, sm.sseg);
-    {
-      // the open segment of the previous batch precedes every entry
-      SegKey cel;
-      cel.f = 0;
-      cel.k = key_ident();
-      if (carry.active && carry.u >= 0) {
-        cel.k.w = carry.w;
-        cel.k.hhi = carry.hhi;
-        cel.k.hlo = carry.hlo;
-        cel.k.u = carry.u;
-      }
-      cin = seg_combine(cel, cin);
-    }
-    if (c0_ends) {
-      const Key k = head0 ? p1 : key_max(cin.k, p1);
-      sm.s_best[c0_seg] = k.u;
-      if (c0_seg == sm.p_seg[nt - 1] && sm.p_take[nt - 1] > 0) {
-        // the batch's last segment ended in this lane's first segment
-        sm.lastkey = k;
-      }
-      if (c0_seg == sm.p_seg[0]) sm.firstkey = k;
-    }
-    // kept positions of segment starts and ends
-    {
-      unsigned p = kpre;
-#pragma unroll
-      for (int i = 0; i < kItems; ++i) {
-        if (myseg[i] == 0xffff) continue;
-        if (mypos[i] & 1) sm.s_kst[myseg[i]] = (unsigned short)p;
-        if (!(mycol[i] & kDropBit)) ++p;
-        if (mypos[i] & 2) sm.s_kend[myseg[i]] = (unsigned short)p;
-      }
-    }
-    // (the batch's first segment starts at q = 0, so it is always the first
-    // segment of the lane where it ends: its full key was stored above)
-    __syncthreads();
-    // ---- 6. segment outputs
-    // Segments of this batch in piece order: ids s_first = p_seg[0] ... ; the
-    // segment of piece nt-1 stays open (new carry). The old carry closes
-    // first when piece 0 starts a new segment.
-    const int last_seg = sm.p_seg[nt - 1];
-    const bool cont = (sm.p_seg[0] == 0);  // piece 0 continues the carry
-    // per segment: finalize? kept>0? one lane per segment head (plus lane 0
-    // for the continuation segment and the old carry)
-    int my_out[2] = {0, 0};
-    unsigned want = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * tid + h;
-      if (j < nt && (sm.p_fl[j] & kFlHead)) {
-        const int s = j + 1;
-        if (s != last_seg) {
-          const int kept = (int)sm.s_kend[s] - (int)sm.s_kst[s];
-          if (kept > 0 && !FIRST) {
-            my_out[h] = 1;
-            ++want;
-          }
-        }
-      }
-    }
-    // lane 0: old carry (closed at batch start) and continuation segment
-    int old_out = 0, cont_out = 0;
-    if (tid == 0) {
-      if (carry.active && !cont && carry.kept > 0 && !FIRST) old_out = 1;
-      if (cont && last_seg != 0) {
-        const int kept = carry.kept + ((int)sm.s_kend[0] - (int)sm.s_kst[0]);
-        if (kept > 0 && !FIRST) cont_out = 1;
-      }
-      want += old_out + cont_out;
-    }
-    unsigned wtot;
-    const unsigned wpre = block_excl_sum<unsigned>(want, sm.s32, wtot);
-    const int out_base = sm.out_cursor;   // destination of this batch's first survivor
-    const int row_base = sm.row_cursor;
-    auto finalize = [&](int v, int g, int kept, int out_off, int u_local, const Key* full, int row_slot,
-                        bool is_first_seg) {
-      // row_slot: output piece index or -1; is_first_seg: segment containing E0
-      const int gb = a.c.gbase[g];
-      if (is_first_seg && sm.open_left) {
-        Part p;
-        p.v = v;
-        p.flags = 0;
-        p.kept = kept;
-        p.out_row = row_slot;
-        p.w = full ? full->w : 0u;
-        p.hhi = full ? full->hhi : 0u;
-        p.hlo = full ? full->hlo : 0u;
-        p.u = (full && full->u >= 0) ? gb + full->u : -1;
-        pf_out = p;
-        if (!FIRST && row_slot >= 0) a.rows_out[row_slot] = make_int4(v, out_off, kept, g & kGraphMask);
-        return;
-      }
-      if (u_local >= 0) a.c.C[v] = gb + u_local;
-      if (!FIRST && row_slot >= 0) a.rows_out[row_slot] = make_int4(v, out_off, kept, (g & kGraphMask) | kHeadBit);
-    };
-    if (tid == 0) {
-      unsigned at = wpre;
-      if (carry.active && !cont) {
-        // the previous batch's last segment ended with the previous batch
-        Key full;
-        full.w = carry.w;
-        full.hhi = carry.hhi;
-        full.hlo = carry.hlo;
-        full.u = carry.u;
-        const int slot = old_out ? row_base + (int)(at++) : -1;
-        finalize(carry.v, carry.g, carry.kept, carry.out_start, carry.u, &full, slot, carry.is_first);
-      }
-      if (cont && last_seg != 0) {
-        const int kb = (int)sm.s_kend[0] - (int)sm.s_kst[0];
-        const int kept = carry.kept + kb;
-        const int start = carry.out_start >= 0 ? carry.out_start : out_base + (int)sm.s_kst[0];
-        const int slot = cont_out ? row_base + (int)(at++) : -1;
-        finalize(sm.p_v[0], sm.p_g[0], kept, start, sm.s_best[0], &sm.firstkey, slot, carry.is_first);
-      }
+      bw = run.w;
+      bu = run.u;
+      sm.p_w[tid] = bw;
+      sm.p_u[tid] = bu;
     }
     {
-      unsigned at = wpre + (tid == 0 ? (unsigned)(old_out + cont_out) : 0u);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = 2 * tid + h;
-        if (j < nt && (sm.p_fl[j] & kFlHead)) {
-          const int s = j + 1;
-          if (s == last_seg) continue;
-          const int kept = (int)sm.s_kend[s] - (int)sm.s_kst[s];
-          const int slot = my_out[h] ? row_base + (int)(at++) : -1;
-          const bool is_first_seg = first_batch && j == 0;
-          finalize(sm.p_v[j], sm.p_g[j], kept, out_base + (int)sm.s_kst[s], sm.s_best[s],
-                   is_first_seg ? &sm.firstkey : nullptr, slot, is_first_seg);
+      const int nlong = sm.nlong;
+      for (int li = wv; li < nlong; li += kWaves) {  // a wave per long piece
+        const int j = sm.longlist[li];
+        const int vo = sm.p_vo[j], ld = sm.p_ld[j];
+        const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+        const unsigned vloc = (unsigned)(sm.p_v[j] - sm.p_base[j]);
+        Best run = best_ident();
+        for (int i = lane; i < ld; i += 64) {
+          const uint2 e = sm.e_cw[vo + i];
+          if (e.x != 0u) best_update(run, e.x, (int)e.y, vloc, S);
         }
-      }
-    }
-    // in-place compaction of kept entries (all reads of e_* are done)
-    if (!FIRST) {
-      unsigned p = kpre;
-#pragma unroll
-      for (int i = 0; i < kItems; ++i) {
-        if (myseg[i] == 0xffff || (mycol[i] & kDropBit)) continue;
-        sm.e_col[p] = (int)(mycol[i] & ~kDropBit);
-        sm.e_w[p] = myw[i];
-        ++p;
+        const Key k = wave_max_key(best_key(run, vloc, S));
+        if (lane == 0) {
+          sm.p_w[j] = k.w;
+          sm.p_u[j] = k.u;
+        }
       }
     }
     __syncthreads();
-    if (!FIRST) {
-      for (int p = tid; p < (int)ktot; p += kBlock) {
-        a.dst_col[out_base + p] = sm.e_col[p];
-        a.dst_w[out_base + p] = __uint_as_float(sm.e_w[p]);
+    if (mine && ldt > kLong) {
+      bw = sm.p_w[tid];
+      bu = sm.p_u[tid];
+    }
+    // ---- 5. vertex segments
+    // The segment of piece j closes in this batch when piece j+1 starts another
+    // vertex; the batch's last segment closes only when the next piece is known
+    // to start another vertex. The carried segment closes before piece 0 when
+    // piece 0 starts another vertex.
+    const bool last_open = sm.last_partial || sm.next_cont != 0;
+    const bool old_closes = carry.active && !sm.p_cont[0];
+    bool closes = false, seg_has_carry = false;
+    int seg_head = tid, seg_kept = 0;
+    unsigned sw = bw;
+    int su = bu;
+    if (mine) {
+      closes = (tid + 1 < nt) ? !sm.p_cont[tid + 1] : !last_open;
+      if (cont && (closes || tid == nt - 1)) {
+        // the vertex has several pieces here (its row was cut before): walk back
+        Key k = full_key(bw, bu, myvloc, mySeed);
+        int j = tid;
+        while (sm.p_cont[j]) {
+          if (j == 0) {
+            seg_has_carry = true;
+            break;
+          }
+          --j;
+          k = key_max(k, full_key(sm.p_w[j], sm.p_u[j], myvloc, mySeed));
+        }
+        if (seg_has_carry) k = key_max(k, full_key(carry.w, carry.u, myvloc, mySeed));
+        seg_head = j;
+        sw = k.w;
+        su = k.u;
+      }
+      if (!FIRST)
+        seg_kept = (int)sm.kpre[my_vo + ldt] - (int)sm.kpre[sm.p_vo[seg_head]] + (seg_has_carry ? carry.kept : 0);
+    }
+    const bool seg_is_first = seg_has_carry ? carry.is_first != 0 : (first_batch && seg_head == 0);
+    const bool emit = !FIRST && mine && closes && seg_kept > 0;
+    const bool emit_old = !FIRST && tid == 0 && old_closes && carry.kept > 0;
+    unsigned epre = 0, etot = 0;
+    if (!FIRST) {  // slots of the emitted piece records, in piece order
+      const unsigned ne = (emit ? 1u : 0u) + (emit_old ? 1u : 0u);
+      const unsigned inc = wave_incl_sum_u32(ne);
+      if (lane == 63) sm.s_emit[wv] = inc;
+      __syncthreads();
+      epre = inc - ne;
+#pragma unroll
+      for (int i = 0; i < kWaves; ++i) {
+        const unsigned x = sm.s_emit[i];
+        if (i < wv) epre += x;
+        etot += x;
       }
     }
-    // ---- 7. new carry and advance
-    if (tid == 0) {
+    int slot = row_base + (int)epre;
+    if (tid == 0 && old_closes) {
+      close_segment<FIRST>(a, sm, carry.is_first && open_left, carry.v, carry.g, carry.base, carry.w, carry.u,
+                           single ? seed0 : a.c.gseed[carry.g], carry.kept, carry.out_start,
+                           emit_old ? slot++ : -1);
+    }
+    int seg_start = -1;
+    if (!FIRST && mine && (closes || tid == nt - 1)) {
+      const int bstart = out_base + (int)sm.kpre[sm.p_vo[seg_head]];
+      seg_start = seg_has_carry && carry.out_start >= 0
+                      ? carry.out_start
+                      : (seg_kept > (seg_has_carry ? carry.kept : 0) ? bstart : -1);
+    }
+    if (mine && closes) {
+      close_segment<FIRST>(a, sm, seg_is_first && open_left, rec.x, rec.w & kGraphMask, mybase, sw, su, mySeed,
+                           seg_kept, seg_start, emit ? slot : -1);
+    }
+    // ---- 6. carry and advance (lane of the last piece)
+    if (tid == nt - 1) {
       Carry nc;
-      nc.active = 1;
-      nc.v = sm.p_v[nt - 1];
-      nc.g = sm.p_g[nt - 1];
-      const bool has_entries = sm.p_take[nt - 1] > 0;
-      const int kb = (int)sm.s_kend[last_seg] - (int)sm.s_kst[last_seg];
-      Key lk = key_ident();
-      if (has_entries) lk = sm.lastkey;
-      if (last_seg == 0) {  // still the carried segment
-        Key ck;
-        ck.w = carry.w;
-        ck.hhi = carry.hhi;
-        ck.hlo = carry.hlo;
-        ck.u = carry.u;
-        if (carry.u < 0) ck = key_ident();
-        lk = has_entries ? key_max(ck, lk) : ck;
-        nc.kept = carry.kept + kb;
-        nc.out_start = carry.out_start >= 0 ? carry.out_start : (kb > 0 ? out_base + (int)sm.s_kst[0] : -1);
-        nc.is_first = carry.is_first;
-      } else {
-        nc.kept = kb;
-        nc.out_start = kb > 0 ? out_base + (int)sm.s_kst[last_seg] : -1;
-        nc.is_first = first_batch && last_seg == (int)sm.p_seg[0] && sm.p_seg[0] == 1;
+      nc.active = 0;
+      nc.v = rec.x;
+      if (last_open) {
+        nc.active = 1;
+        nc.g = rec.w & kGraphMask;
+        nc.base = mybase;
+        nc.w = sw;
+        nc.u = su;
+        nc.kept = seg_kept;
+        nc.out_start = seg_start;
+        nc.is_first = seg_is_first ? 1 : 0;
       }
-      nc.w = lk.w;
-      nc.hhi = lk.hhi;
-      nc.hlo = lk.hlo;
-      nc.u = lk.u;
       sm.carry = nc;
       sm.out_cursor = out_base + (int)ktot;
-      sm.row_cursor = row_base + (int)wtot;
-      sm.pos = pos + sm.consumed;
-      if (sm.last_partial) {
-        sm.cur_k = cur_k + nt - 1;
-        sm.cur_o = (nt == 1 ? cur_o : 0) + sm.last_take;
+      sm.row_cursor = row_base + (int)etot;
+      const long long consumed = cpre + take;
+      sm.pos = pos + consumed;
+      int nk, no;
+      if (take < cov) {
+        nk = cur_k + nt - 1;
+        no = (nt == 1 ? cur_o : 0) + take;
       } else {
-        sm.cur_k = cur_k + nt;
-        sm.cur_o = 0;
+        nk = cur_k + nt;
+        no = 0;
       }
-      if (sm.cur_k >= sm.run_hi && sm.cur_k < ctl.pieces) {
-        int r2 = sm.cur_r;
-        (void)piece_row(a.in, sm.cur_k, r2, ctl.nruns);
+      sm.cur_k = nk;
+      sm.cur_o = no;
+      if (nk >= run_hi && nk < ctl.pieces) {
+        int r2 = rr;
+        (void)piece_row(a.in, nk, r2, ctl.nruns);
         sm.cur_r = r2;
         sm.run_rb = a.in.runs[r2].row_begin;
         sm.run_lo = a.in.rpre[r2];
         sm.run_hi = a.in.rpre[r2 + 1];
       }
-      loaded_total += NLD;
     }
+    if (tid == 0) loaded_total += NLD;
     first_batch = false;
     __syncthreads();
   }
   // ---- close the range: the open segment is cut iff its row continues at E1
   if (tid == 0) {
+    Part pf_out, pl_out;
+    pf_out.v = -1;
+    pl_out.v = -1;
+    if (sm.pf_valid) pf_out = sm.pf;
     const Carry c = sm.carry;
-    bool open_right = false;
-    if (sm.cur_o > 0) {
-      open_right = true;
-    } else if (sm.cur_k < ctl.pieces) {
-      int rr = sm.cur_r;
-      open_right = a.in.rows[piece_row(a.in, sm.cur_k, rr, ctl.nruns)].x == c.v;
-    }
-    Key full;
-    full.w = c.w;
-    full.hhi = c.hhi;
-    full.hlo = c.hlo;
-    full.u = c.u;
-    if (c.u < 0) full = key_ident();
-    const int gb = a.c.gbase[c.g];
-    const int slot = (!FIRST && c.kept > 0) ? sm.row_cursor : -1;
-    if (!FIRST && slot >= 0) {
-      const bool closed = !open_right && !(c.is_first && sm.open_left);
-      a.rows_out[slot] = make_int4(c.v, c.out_start, c.kept, (c.g & kGraphMask) | (closed ? kHeadBit : 0));
-      sm.row_cursor = slot + 1;
-    }
-    Part p;
-    p.v = c.v;
-    p.flags = 0;
-    p.kept = c.kept;
-    p.out_row = slot;
-    p.w = full.w;
-    p.hhi = full.hhi;
-    p.hlo = full.hlo;
-    p.u = full.u >= 0 ? gb + full.u : -1;
-    if (c.is_first && sm.open_left) {
-      p.flags = open_right ? kPartSingle : 0;
-      pf_out = p;
-    } else if (open_right) {
-      pl_out = p;
-    } else if (full.u >= 0) {
-      a.c.C[c.v] = gb + full.u;
+    if (c.active) {
+      bool open_right = false;
+      if (sm.cur_o > 0) {
+        open_right = true;
+      } else if (sm.cur_k < ctl.pieces) {
+        int rr = sm.cur_r;
+        open_right = a.in.rows[piece_row(a.in, sm.cur_k, rr, ctl.nruns)].x == c.v;
+      }
+      const bool cut_left = c.is_first && open_left;
+      const int slot = (!FIRST && c.kept > 0) ? sm.row_cursor : -1;
+      if (slot >= 0) {
+        a.rows_out[slot] =
+            make_int4(c.v, c.out_start, c.kept, (c.g & kGraphMask) | ((open_right || cut_left) ? 0 : kHeadBit));
+        sm.row_cursor = slot + 1;
+      }
+      if (cut_left || open_right) {
+        const Key k = full_key(c.w, c.u, (unsigned)(c.v - c.base), single ? seed0 : a.c.gseed[c.g]);
+        Part p;
+        p.v = c.v;
+        p.flags = (cut_left && open_right) ? kPartSingle : 0;
+        p.kept = c.kept;
+        p.out_row = slot;
+        p.w = k.w;
+        p.hhi = k.hhi;
+        p.hlo = k.hlo;
+        p.u = c.u >= 0 ? c.base + c.u : -1;
+        if (cut_left)
+          pf_out = p;
+        else
+          pl_out = p;
+      } else if (c.u >= 0) {
+        a.c.C[c.v] = c.base + c.u;
+      }
     }
     a.parts[2 * b] = pf_out;
     a.parts[2 * b + 1] = pl_out;
