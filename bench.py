@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-profile", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--batch", action="store_true", help="also time the 4096-graph batch (extra minutes)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -74,8 +76,17 @@ def main():
     mate = torch.empty(g.n, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 
+    if args.copy_calib_mib > 0:
+        # a plain elementwise copy of known size: reads and writes exactly
+        # copy_calib_mib MiB, so HBM counters of the same run can be scaled
+        src = torch.ones((args.copy_calib_mib << 20) // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.add(src, 0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     ctx = lm.Context(0)
-    stream = torch.cuda.current_stream()
     profile = not args.no_profile
     for i in range(args.warmup):
         ctx.match(rp, col, w, seed=args.seed, mate=mate, profile=profile)
