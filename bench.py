@@ -50,6 +50,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-profile", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--batch", action="store_true", help="also time the 4096-graph batch (extra minutes)")
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the serving trace: continuous-batching server vs FIFO (extra minutes)")
+    ap.add_argument("--serve-rates", type=str, default="50,150",
+                    help="Poisson arrival rates (requests/s) for --serve")
+    ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -148,6 +153,10 @@ def main():
     batch = None
     if args.batch:
         batch = bench_batch(ctx, dev)
+    serve = None
+    if args.serve:
+        serve = bench_serve(ctx, [float(x) for x in args.serve_rates.split(",") if x],
+                            args.serve_requests)
 
     out = {
         "metric": "input edges matched/sec + achieved HBM GB/s (1 GPU); batched p50/p99 latency",
@@ -173,6 +182,8 @@ def main():
     }
     if batch is not None:
         out["batch"] = batch
+    if serve is not None:
+        out["serve"] = serve
     print(json.dumps(out), flush=True)
 
 
@@ -208,6 +219,67 @@ def bench_batch(ctx, dev):
             "batched_ms": {"p50": round(_percentile(lat, 50), 3), "p99": round(_percentile(lat, 99), 3)},
             "batched_edges_per_s": round((b.nnz // 2) / (_percentile(lat, 50) / 1e3), 1),
             "one_graph_per_launch_ms": round(single_ms, 3)}
+
+
+def bench_serve(ctx, rates, requests, pool=48, seed=1):
+    """Serving trace: Poisson arrivals of host graphs (50/50 RGG avg degree 10
+    and R-MAT edge factor 16, uniform weights, n log-uniform in [2^10, 2^22];
+    a pool of `pool` pre-generated graphs is cycled, generation is not timed),
+    64 GB admission budget. The continuous-batching server and the FIFO
+    server (one lm_match per request) see the same trace; latency is submit
+    to result on the host, throughput is input edges over the makespan."""
+    import threading
+
+    import lmgen
+    import paper_1302_4587_amd as lm
+
+    t0 = time.time()
+    shapes = lmgen.serving_trace(pool, 1.0, seed)
+    graphs = [lmgen.serving_graph(k, n, seed) for _, k, n in shapes]
+    print(f"bench: serving pool of {pool} graphs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    refs = {}
+    out = {"pool_graphs": pool, "requests_per_point": requests, "budget_gb": 64,
+           "pool_mean_edges": round(float(np.mean([g.nnz // 2 for g in graphs])), 1), "points": []}
+    for rate in rates:
+        arr = [a for a, _, _ in lmgen.serving_trace(requests, rate, seed + 1)]
+        point = {"rate_per_s": rate}
+        for name, mode in (("batched", lm.LM_SERVE_BATCHED), ("fifo", lm.LM_SERVE_FIFO)):
+            tickets = [None] * requests
+            with lm.Server(ctx, hbm_budget_bytes=64 << 30, max_resident=256, mode=mode) as srv:
+                def submitter(part, parts):
+                    for i in range(part, requests, parts):
+                        dt = arr[i] - (time.perf_counter() - t_start)
+                        if dt > 0:
+                            time.sleep(dt)
+                        g = graphs[i % pool]
+                        tickets[i] = srv.submit(g.row_ptr, g.col, g.w, seed=1)
+
+                t_start = time.perf_counter()
+                ths = [threading.Thread(target=submitter, args=(p, 4)) for p in range(4)]
+                for th in ths:
+                    th.start()
+                lat, edges, bad = [], 0, 0
+                for i in range(requests):
+                    while tickets[i] is None:
+                        time.sleep(0.0002)
+                    mate, info = srv.wait(tickets[i], -1)
+                    lat.append(info["latency_ms"])
+                    g = graphs[i % pool]
+                    edges += g.nnz // 2
+                    k = i % pool
+                    if k not in refs:
+                        refs[k] = mate.copy()
+                    elif not np.array_equal(refs[k], mate):
+                        bad += 1
+                makespan = time.perf_counter() - t_start
+                for th in ths:
+                    th.join()
+            point[name] = {"p50_ms": round(_percentile(lat, 50), 3), "p99_ms": round(_percentile(lat, 99), 3),
+                           "edges_per_s": round(edges / makespan, 1), "requests_per_s": round(requests / makespan, 2),
+                           "mismatches": bad}
+            print(f"bench: serve rate={rate} {name}: {point[name]}", file=sys.stderr, flush=True)
+        out["points"].append(point)
+    return out
 
 
 if __name__ == "__main__":

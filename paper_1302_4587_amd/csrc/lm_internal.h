@@ -136,6 +136,7 @@ struct MutualArgs {
   LiveSet in;
   int t;
   int* mcount;  // matched vertices per workgroup
+  int census;   // only record gphase[g] = t for graphs with a live row (no matching)
 };
 
 struct PlanArgs {
@@ -163,13 +164,23 @@ struct PlanArgs {
 };
 enum : int { kPlanFix = 1, kPlanPrefix = 2, kPlanLog = 4 };
 
+// Live-set construction for vertices [vfirst, vfirst + vcount) of the
+// vertex space: row_ptr (vcount + 1 offsets into the entry buffer, from ebase
+// to ebase + nnz) and vtx_off (graphs + 1 offsets, relative to vfirst) are
+// indexed from vfirst. Pieces go to rows_out[rows_base ...], run b to
+// runs_out[runs_base + b]; graph i of the group is table slot slot_of[i]
+// (slot_of == nullptr: slot i).
 struct InitArgs {
   Common c;
   const long long* row_ptr;
   long long nnz;
+  long long ebase;
+  long long vfirst, vcount;
   int graphs;
   const long long* vtx_off;
-  int nblocks;        // workgroups (= runs of R_1)
+  const int* slot_of;
+  int nblocks;        // workgroups (= runs produced)
+  int rows_base, runs_base;
   Run* runs_out;
   int4* rows_out;
 };
@@ -187,6 +198,7 @@ struct CheckArgs {
 
 hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s);
 hipError_t launch_fill_i32(int* p, long long n, int value, hipStream_t s);
+hipError_t launch_add_i64(long long* p, long long n, long long delta, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s);

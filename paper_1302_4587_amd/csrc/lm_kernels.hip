@@ -47,6 +47,11 @@ __global__ void k_fill_i32(int* p, long long n, int value) {
     p[i] = value;
 }
 
+__global__ void k_add_i64(long long* p, long long n, long long delta) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] += delta;
+}
+
 // Optional input check: ids in range, no self-loops, finite weights.
 __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
   unsigned err = 0;
@@ -81,16 +86,17 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
 // ---------------------------------------------------------------- init
 
 // Live set R_1 straight from the input CSR: workgroup b covers vertices
-// [N b / B, N (b+1) / B); every vertex with at least one entry becomes one
-// head piece pointing at its input row, and the workgroup's pieces form run
-// b (their rows are back to back in the input). Also clears mate and state
-// and checks the offsets.
+// [vcount b / B, vcount (b+1) / B) of the group; every vertex with at least one
+// entry becomes one head piece pointing at its input row, and the workgroup's
+// pieces form one run (their rows are back to back in the entry buffer). Also
+// clears mate and state and checks the offsets.
 __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
   __shared__ unsigned s32[kWaves];
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
-  const long long N = a.c.n;
+  const long long N = a.vcount;
   const long long vb = N * b / a.nblocks, ve = N * (b + 1) / a.nblocks;
+  const long long eend = a.ebase + a.nnz;
   unsigned err = 0;
   // graph of this lane's first vertex (lanes own kItems consecutive vertices)
   int g = 0;
@@ -118,9 +124,9 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
       const long long v = v0 + i;
       if (v < ve) {
         const long long d = rp[i + 1] - rp[i];
-        if (d < 0 || rp[i] < 0 || rp[i + 1] > a.nnz) err |= kErrRowPtr;
+        if (d < 0 || rp[i] < a.ebase || rp[i + 1] > eend) err |= kErrRowPtr;
         if (d > 0x7fff0000LL) err |= kErrDegree;
-        if (d > 0) ++cnt;
+        if (d > 0 && d <= 0x7fff0000LL && rp[i] >= a.ebase && rp[i + 1] <= eend) ++cnt;
       }
     }
     unsigned tot;
@@ -132,11 +138,13 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
       if (v < ve) {
         if (a.graphs > 1)
           while (a.vtx_off[g + 1] <= v) ++g;
-        a.c.mate[v] = -1;
-        a.c.state[v] = 0;
+        const long long vg = a.vfirst + v;
+        a.c.mate[vg] = -1;
+        a.c.state[vg] = 0;
         const long long d = rp[i + 1] - rp[i];
-        if (d > 0 && d <= 0x7fff0000LL) {
-          a.rows_out[vb + at] = make_int4((int)v, (int)rp[i], (int)d, (g & kGraphMask) | kHeadBit);
+        if (d > 0 && d <= 0x7fff0000LL && rp[i] >= a.ebase && rp[i + 1] <= eend) {
+          const int slot = a.slot_of ? a.slot_of[g] : g;
+          a.rows_out[a.rows_base + vb + at] = make_int4((int)vg, (int)rp[i], (int)d, (slot & kGraphMask) | kHeadBit);
           ++at;
         }
       }
@@ -145,16 +153,16 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
   }
   if (tid == 0) {
     Run r;
-    r.row_begin = (int)vb;
+    r.row_begin = a.rows_base + (int)vb;
     r.row_count = (int)cursor;
-    const long long pb = vb < N ? a.row_ptr[vb] : a.nnz;
+    const long long pb = vb < N ? a.row_ptr[vb] : eend;
     const long long pe = a.row_ptr[ve];
     r.phys_begin = (int)pb;
     r.ent_count = (int)(pe - pb);
-    if (vb == 0 && pb != 0) err |= kErrRowPtr;
-    if (ve == N && pe != a.nnz) err |= kErrRowPtr;
+    if (vb == 0 && pb != a.ebase) err |= kErrRowPtr;
+    if (ve == N && pe != eend) err |= kErrRowPtr;
     if (pe < pb) err |= kErrRowPtr;
-    a.runs_out[b] = r;
+    a.runs_out[a.runs_base + b] = r;
   }
   if (err) atomicOr(&a.c.totals->err, err);
 }
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
           if (rec.w & kHeadBit) {
             const int v = rec.x;
             g = rec.w & kGraphMask;
-            const int u = a.c.C[v];
+            const int u = a.census ? -1 : a.c.C[v];
             if ((unsigned)u < (unsigned)a.c.n && a.c.C[u] == v) {
               a.c.mate[v] = u - a.c.gbase[g];
               a.c.state[v] = 1;
@@ -457,6 +465,22 @@ __device__ __forceinline__ Key wave_max_key(Key k) {
   r.hlo = (unsigned)__builtin_amdgcn_readlane((int)k.hlo, 63);
   r.u = __builtin_amdgcn_readlane(k.u, 63);
   return r;
+}
+
+// Among the entries of one row piece whose ordered weight equals m (at
+// least two), the neighbour with the largest tie-break hash.
+__device__ __noinline__ int tie_break(const uint2* e, int n, unsigned m, unsigned vloc, unsigned long long S) {
+  uint64_t hb = 0;
+  int ub = -1;
+  for (int i = 0; i < n; ++i) {
+    if (e[i].x != m) continue;
+    const uint64_t h = edge_hash(S, vloc, e[i].y);
+    if (ub < 0 || h > hb) {
+      hb = h;
+      ub = (int)e[i].y;
+    }
+  }
+  return ub;
 }
 
 template <bool FIRST>
@@ -655,24 +679,34 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     }
     __syncthreads();
     // ---- 3. coalesced loads, neighbour state, survivors in order
+    // Lanes past the loaded count repeat the last valid position, so every
+    // load is unconditional and the compiler can issue them back to back.
     unsigned ktot = 0;
-    {
+    if (NLD > 0) {
       int cc[kItems];
       float ww[kItems];
       int jp[kItems];
 #pragma unroll
+      for (int jj = 0; jj < kItems; ++jj) jp[jj] = sm.rowof[min(tid + kBlock * jj, NLD - 1)];
+#pragma unroll
       for (int jj = 0; jj < kItems; ++jj) {
-        const int q = tid + kBlock * jj;
-        cc[jj] = 0;
-        ww[jj] = 0.f;
-        jp[jj] = 0;
-        if (q < NLD) {
-          const int j = sm.rowof[q];
-          jp[jj] = j;
-          const int addr = q + sm.p_delta[j];
-          cc[jj] = a.in.col[addr];
-          ww[jj] = a.in.w[addr];
-        }
+        const int addr = min(tid + kBlock * jj, NLD - 1) + sm.p_delta[jp[jj]];
+        cc[jj] = a.in.col[addr];
+        ww[jj] = a.in.w[addr];
+      }
+      bool ok[kItems];
+      unsigned ug[kItems];
+#pragma unroll
+      for (int jj = 0; jj < kItems; ++jj) {
+        const int base = single ? 0 : sm.p_base[jp[jj]];
+        ug[jj] = (unsigned)(base + cc[jj]);
+        // ids outside the graph are dropped
+        ok[jj] = tid + kBlock * jj < NLD && cc[jj] >= 0 && ug[jj] < (unsigned)a.c.n;
+      }
+      unsigned char st[kItems];
+      if (!FIRST) {
+#pragma unroll
+        for (int jj = 0; jj < kItems; ++jj) st[jj] = a.c.state[ok[jj] ? ug[jj] : 0u];
       }
       unsigned rank[kItems];
       unsigned kpm = 0;
@@ -680,14 +714,8 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
 #pragma unroll
       for (int jj = 0; jj < kItems; ++jj) {
         const int q = tid + kBlock * jj;
-        bool kp = false;
-        if (q < NLD) {
-          const int base = single ? 0 : sm.p_base[jp[jj]];
-          const unsigned ug = (unsigned)(base + cc[jj]);
-          kp = cc[jj] >= 0 && ug < (unsigned)a.c.n;  // ids outside the graph are dropped
-          if (!FIRST && kp) kp = a.c.state[ug] == 0;
-          sm.e_cw[q] = make_uint2(kp ? ord_weight_bits(__float_as_uint(ww[jj])) : 0u, (unsigned)cc[jj]);
-        }
+        const bool kp = ok[jj] && (FIRST || st[jj] == 0);
+        if (q < NLD) sm.e_cw[q] = make_uint2(kp ? ord_weight_bits(__float_as_uint(ww[jj])) : 0u, (unsigned)cc[jj]);
         if (!FIRST) {
           const unsigned long long bal = __ballot(kp);
           rank[jj] = (unsigned)__popcll(bal & lt);
@@ -706,16 +734,16 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         for (int jj = 0; jj < kItems; ++jj) {
           const int q = tid + kBlock * jj;
           const unsigned kq = (unsigned)__builtin_amdgcn_readlane((int)excl, jj * kWaves + wv) + rank[jj];
-          if (q < NLD) {
-            sm.kpre[q] = (unsigned short)kq;
-            if ((kpm >> jj) & 1u) {
-              a.dst_col[out_base + (int)kq] = cc[jj];
-              a.dst_w[out_base + (int)kq] = ww[jj];
-            }
+          if (q < NLD) sm.kpre[q] = (unsigned short)kq;
+          if ((kpm >> jj) & 1u) {
+            a.dst_col[out_base + (int)kq] = cc[jj];
+            a.dst_w[out_base + (int)kq] = ww[jj];
           }
         }
         if (tid == 0) sm.kpre[NLD] = (unsigned short)ktot;
       }
+    } else if (tid == 0) {
+      sm.kpre[0] = 0;
     }
     // ---- 4. best candidate per piece
     const int my_vo = (int)lpre;
@@ -730,13 +758,21 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     unsigned bw = 0u;
     int bu = -1;
     if (mine && ldt <= kLong) {
-      Best run = best_ident();
+      // largest ordered weight, its first neighbour, and whether it repeats;
+      // only a repeated largest weight needs the tie-break hash
+      unsigned m = 0u;
+      int mu = -1, ties = 0;
+#pragma unroll 4
       for (int i = 0; i < ldt; ++i) {
         const uint2 e = sm.e_cw[my_vo + i];
-        if (e.x != 0u) best_update(run, e.x, (int)e.y, myvloc, mySeed);
+        const bool gt = e.x > m;
+        ties = gt ? 0 : ties + (e.x == m ? 1 : 0);
+        mu = gt ? (int)e.y : mu;
+        m = gt ? e.x : m;
       }
-      bw = run.w;
-      bu = run.u;
+      if (m != 0u && ties > 0) mu = tie_break(sm.e_cw + my_vo, ldt, m, myvloc, mySeed);
+      bw = m;
+      bu = mu;
       sm.p_w[tid] = bw;
       sm.p_u[tid] = bu;
     }
@@ -745,14 +781,19 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       for (int li = wv; li < nlong; li += kWaves) {  // a wave per long piece
         const int j = sm.longlist[li];
         const int vo = sm.p_vo[j], ld = sm.p_ld[j];
-        const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
-        const unsigned vloc = (unsigned)(sm.p_v[j] - sm.p_base[j]);
-        Best run = best_ident();
-        for (int i = lane; i < ld; i += 64) {
-          const uint2 e = sm.e_cw[vo + i];
-          if (e.x != 0u) best_update(run, e.x, (int)e.y, vloc, S);
+        unsigned m = 0u;
+        for (int i = lane; i < ld; i += 64) m = max(m, sm.e_cw[vo + i].x);
+        m = (unsigned)__builtin_amdgcn_readlane((int)wave_incl_max_u32(m), 63);
+        Key k = key_ident();
+        if (m != 0u) {
+          const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+          const unsigned vloc = (unsigned)(sm.p_v[j] - sm.p_base[j]);
+          for (int i = lane; i < ld; i += 64) {
+            const uint2 e = sm.e_cw[vo + i];
+            if (e.x == m) k = key_max(k, full_key(m, (int)e.y, vloc, S));
+          }
+          k = wave_max_key(k);
         }
-        const Key k = wave_max_key(best_key(run, vloc, S));
         if (lane == 0) {
           sm.p_w[j] = k.w;
           sm.p_u[j] = k.u;
@@ -956,6 +997,11 @@ hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s) {
 hipError_t launch_fill_i32(int* p, long long n, int value, hipStream_t s) {
   const long long blocks = std::min<long long>((n + kBlock - 1) / kBlock, 4096);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::max<long long>(blocks, 1)), dim3(kBlock), 0, s, p, n, value);
+  return hipGetLastError();
+}
+hipError_t launch_add_i64(long long* p, long long n, long long delta, hipStream_t s) {
+  const long long blocks = std::min<long long>((n + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_add_i64, dim3((unsigned)std::max<long long>(blocks, 1)), dim3(kBlock), 0, s, p, n, delta);
   return hipGetLastError();
 }
 hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s) {

@@ -80,6 +80,7 @@ lm_status solve_locked(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, const int64
                        const int32_t* col, const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate,
                        uint32_t flags, void* stream, lm_stats* st, int32_t* graph_phases);
 Solver& solver_of(lm_ctx* c);
+lm_status host_check(int64_t n, const int64_t* rp, const int32_t* col, const float* w, int64_t nnz);
 std::mutex& mutex_of(lm_ctx* c);
 
 }  // namespace lm

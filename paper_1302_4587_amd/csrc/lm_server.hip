@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "lm.h"
+#include "lm_key.h"
 #include "lm_runtime.h"
 #include "lm_server_impl.h"
 
@@ -83,6 +84,75 @@ static void fifo_loop(ServerCore* S) {
   }
 }
 
+// Runs fn(lo, hi) over [0, n) on up to 16 threads when n is large.
+template <typename F>
+static void parallel_ranges(int64_t n, int64_t grain, F fn) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int64_t parts = std::min<int64_t>({(int64_t)std::min(hw, 16u), (n + grain - 1) / grain});
+  if (parts <= 1) {
+    fn((int64_t)0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int64_t i = 0; i < parts; ++i) th.emplace_back(fn, n * i / parts, n * (i + 1) / parts, (int)i);
+  for (auto& x : th) x.join();
+}
+
+// Linear-time check of a submitted graph: offsets, ids, self-loops, finite
+// weights, and symmetry as equal multisets of (pair, weight) in the two
+// directions (compared through a sum of 64-bit hashes, -0 folded onto +0).
+// Duplicate entries are not detected here; they cannot stall the phase loop.
+static lm_status quick_check(const lm_csr* g) {
+  const int64_t n = g->n;
+  for (int64_t v = 0; v < n; ++v)
+    if (g->row_ptr[v] < 0 || g->row_ptr[v + 1] < g->row_ptr[v] || g->row_ptr[v + 1] > g->nnz) return LM_EINVAL;
+  struct Acc {
+    uint64_t up = 0, down = 0;
+    lm_status st = LM_OK;
+  };
+  std::vector<Acc> acc(16);
+  parallel_ranges(n, (int64_t)1 << 16, [&](int64_t v0, int64_t v1, int part) {
+    Acc a;
+    for (int64_t v = v0; v < v1 && a.st == LM_OK; ++v) {
+      for (int64_t k = g->row_ptr[v]; k < g->row_ptr[v + 1]; ++k) {
+        const int32_t u = g->col[k];
+        if (u < 0 || u >= n || u == v) {
+          a.st = LM_EGRAPH;
+          break;
+        }
+        const float x = g->w[k];
+        if (!(x == x) || x == 1.0f / 0.0f || x == -1.0f / 0.0f) {
+          a.st = LM_EWEIGHT;
+          break;
+        }
+        uint32_t bits;
+        std::memcpy(&bits, &x, 4);
+        if (bits == 0x80000000u) bits = 0;
+        const uint64_t lo = (uint64_t)std::min<int64_t>(v, u), hi = (uint64_t)std::max<int64_t>(v, u);
+        const uint64_t h = host_mix64(((lo << 32) | hi) ^ host_mix64((uint64_t)bits + kGoldenGamma));
+        if (v < u)
+          a.up += h;
+        else
+          a.down += h;
+      }
+    }
+    acc[(size_t)part] = a;
+  });
+  uint64_t up = 0, down = 0;
+  for (const Acc& a : acc) {
+    if (a.st != LM_OK) return a.st;
+    up += a.up;
+    down += a.down;
+  }
+  return up == down ? LM_OK : LM_EGRAPH;
+}
+
+static void parallel_copy(void* dst, const void* src, size_t bytes) {
+  parallel_ranges((int64_t)bytes, (int64_t)16 << 20, [&](int64_t a, int64_t b, int) {
+    std::memcpy((char*)dst + a, (const char*)src + a, (size_t)(b - a));
+  });
+}
+
 }  // namespace lm
 
 struct lm_server {
@@ -132,6 +202,13 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
   ServerCore& S = s->core;
   const size_t fp = request_footprint(g->n, g->nnz);
   if (fp > S.opts.hbm_budget_bytes) return LM_ETOOBIG;
+  if (S.opts.mode == LM_SERVE_BATCHED) {
+    int64_t ncap = 0, ecap = 0;
+    server_caps(S.opts.hbm_budget_bytes, &ncap, &ecap);
+    if (g->n > ncap || g->nnz > ecap) return LM_ETOOBIG;
+  }
+  const lm_status qc = quick_check(g);
+  if (qc != LM_OK) return qc;
   auto r = std::make_shared<Request>();
   r->n = g->n;
   r->nnz = g->nnz;
@@ -142,10 +219,10 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
       hipHostMalloc((void**)&r->h_col, (size_t)std::max<int64_t>(g->nnz, 1) * 4) != hipSuccess ||
       hipHostMalloc((void**)&r->h_w, (size_t)std::max<int64_t>(g->nnz, 1) * 4) != hipSuccess)
     return LM_ENOMEM;
-  std::memcpy(r->h_rp, g->row_ptr, (size_t)(g->n + 1) * 8);
+  parallel_copy(r->h_rp, g->row_ptr, (size_t)(g->n + 1) * 8);
   if (g->nnz > 0) {
-    std::memcpy(r->h_col, g->col, (size_t)g->nnz * 4);
-    std::memcpy(r->h_w, g->w, (size_t)g->nnz * 4);
+    parallel_copy(r->h_col, g->col, (size_t)g->nnz * 4);
+    parallel_copy(r->h_w, g->w, (size_t)g->nnz * 4);
   }
   std::lock_guard<std::mutex> lk(S.mu);
   if (S.stopping) return LM_EINVAL;

@@ -60,6 +60,10 @@ inline size_t request_footprint(int64_t n, int64_t nnz) {
   return (size_t)n * (4 + 1 + 4 + 2 * 16) + (size_t)nnz * (2 * 8 + 8) + 4096;
 }
 
+// Resident-set capacity (vertices, entries) of the batched server for an HBM
+// budget; a request larger than either can never be admitted.
+void server_caps(size_t budget, int64_t* n_cap, int64_t* e_cap);
+
 lm_status start_batched(ServerCore* s);
 void stop_batched(ServerCore* s);
 

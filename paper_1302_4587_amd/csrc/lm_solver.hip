@@ -260,9 +260,15 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ia.c = c;
     ia.row_ptr = p.row_ptr;
     ia.nnz = p.nnz;
+    ia.ebase = 0;
+    ia.vfirst = 0;
+    ia.vcount = p.N;
     ia.graphs = (int)p.G;
     ia.vtx_off = p.vtx_off;
+    ia.slot_of = nullptr;
     ia.nblocks = pi;
+    ia.rows_base = 0;
+    ia.runs_base = 0;
     ia.runs_out = (Run*)runs[0].p;
     ia.rows_out = (int4*)rows[0].p;
     HIPCHK(mark_begin(LM_K_INIT));
@@ -316,6 +322,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
       ma.in = in;
       ma.t = t;
       ma.mcount = (int*)mcount.p;
+      ma.census = 0;
       const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, (est_V / shrink) / kCap + 1));
       HIPCHK(mark_begin(LM_K_MUTUAL));
       HIPCHK(launch_mutual(ma, gm, s));
@@ -444,8 +451,9 @@ static bool csr_shape_ok(const lm_csr* g) {
   return true;
 }
 
-// Full host-side contract check of a graph (LM_CHECK_GRAPH on host input).
-static lm_status host_check(int64_t n, const int64_t* rp, const int32_t* col, const float* w, int64_t nnz) {
+// Full host-side contract check of a graph (LM_CHECK_GRAPH on host input,
+// and every request at server submit).
+lm_status lm::host_check(int64_t n, const int64_t* rp, const int32_t* col, const float* w, int64_t nnz) {
   if (rp[0] != 0 || rp[n] != nnz) return LM_EINVAL;
   struct E {
     int32_t lo, hi;

@@ -1,0 +1,72 @@
+"""Full-size parity in the launch configuration the benchmark times.
+
+RGG 2^24 (average degree 10, w = 1 - distance): mate[] and the phase log
+against the oracle, element by element. R-MAT scale 24 (edge factor 16,
+unit weights, so the order is the tie-break hash alone): the oracle takes
+about a minute there, so the check is the greedy certificate, which decides
+equality with the greedy matching under the key -- the oracle's result by
+the theorem that local max with a strict key reaches greedy -- in one pass,
+plus the phase-log invariants (Lemma 1: live entries shrink every phase).
+"""
+import numpy as np
+import pytest
+
+import lmgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1302_4587_amd as lm
+    c = lm.Context(0)
+    yield c
+    c.close()
+
+
+def _solve_device(ctx, g, seed):
+    import torch
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    mate, st = ctx.match(rp, col, w, seed=seed)
+    out = mate.cpu().numpy()
+    del rp, col, w, mate
+    torch.cuda.empty_cache()
+    return out, st
+
+
+def _log_invariants(st, mate):
+    log = st.log
+    assert st.phases == len(log) and st.phases >= 1
+    assert np.all(np.diff(log[:, 0]) < 0), "live entries must shrink every phase"
+    assert int(log[:, 2].sum()) == int((mate >= 0).sum()) // 2 == st.matched_edges
+
+
+def test_rgg_2p24_equals_oracle(ctx):
+    print("case: rgg n=2^24 avg_degree=10 seed=1 (bench workload)", flush=True)
+    g = lmgen.rgg(1 << 24, 10.0, 1)
+    mate, st = _solve_device(ctx, g, 1)
+    ref_mate, ref_log = oracle.local_max_graph(g, 1)
+    if not np.array_equal(mate, ref_mate):
+        bad = np.flatnonzero(mate != ref_mate)
+        raise AssertionError(f"{len(bad)} vertices differ, first {bad[:5]}")
+    assert st.phases == len(ref_log)
+    assert np.array_equal(st.log[:, 0], 2 * ref_log[:, 0])
+    assert np.array_equal(st.log[:, 1], ref_log[:, 1])
+    assert np.array_equal(st.log[:, 2], ref_log[:, 2])
+    _log_invariants(st, mate)
+
+
+def test_rmat_scale24_unit_weights_certificate(ctx):
+    print("case: rmat scale=24 edge_factor=16 unit weights seed=1", flush=True)
+    g = lmgen.rmat(24, 16, seed=1)
+    mate, st = _solve_device(ctx, g, 1)
+    viol = oracle.greedy_certificate(g.n, g.row_ptr, g.col, g.w, 1, mate)
+    assert viol == 0, f"{viol} certificate violations"
+    _log_invariants(st, mate)
