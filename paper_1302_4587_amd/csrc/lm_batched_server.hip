@@ -356,7 +356,6 @@ lm_status BatchedState::step(int k) {
   Ctl* dctl = (Ctl*)ctl.p;
   hipError_t e = hipSuccess;
   for (int j = 0; j < k && e == hipSuccess; ++j) {
-    const int64_t shrink = (int64_t)1 << std::min(j, 20);
     const LiveSet in = live(t);
     MutualArgs ma;
     ma.c = c;
@@ -364,7 +363,7 @@ lm_status BatchedState::step(int k) {
     ma.t = t;
     ma.mcount = (int*)mcount.p;
     ma.census = 0;
-    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, (pieces_now / shrink) / kCap + 1));
+    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, pieces_now / kCap + 1));
     e = launch_mutual(ma, gm, s);
     if (e != hipSuccess) break;
     const int lo = t & 1;
@@ -378,7 +377,7 @@ lm_status BatchedState::step(int k) {
     sa.parts = (Part*)parts.p;
     sa.bstat = (BlockStat*)bstat.p;
     const int gx =
-        (int)std::max<int64_t>(1, std::min<int64_t>(pcap, (L_now / shrink) / std::max(kCap, tun.block_entries) + 1));
+        (int)std::max<int64_t>(1, std::min<int64_t>(pcap, L_now / std::max(kCap, tun.block_entries) + 1));
     e = launch_compact(sa, gx, s);
     if (e != hipSuccess) break;
     PlanArgs pa;

@@ -89,67 +89,79 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
 // [vcount b / B, vcount (b+1) / B) of the group; every vertex with at least one
 // entry becomes one head piece pointing at its input row, and the workgroup's
 // pieces form one run (their rows are back to back in the entry buffer). Also
-// clears mate and state and checks the offsets.
+// clears mate and state and checks the offsets. Vertices are striped over the
+// lanes (vertex c0 + jj * kBlock + lane) so that every load and store of a
+// round is coalesced; wave ballots rank the non-empty rows.
 __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
-  __shared__ unsigned s32[kWaves];
+  __shared__ unsigned s_cnt[kItems * kWaves];
   const int tid = threadIdx.x;
+  const int lane = lane_id(), wv = wave_id();
   const int b = blockIdx.x;
   const long long N = a.vcount;
   const long long vb = N * b / a.nblocks, ve = N * (b + 1) / a.nblocks;
   const long long eend = a.ebase + a.nnz;
+  const unsigned long long lt = lanemask_lt();
   unsigned err = 0;
-  // graph of this lane's first vertex (lanes own kItems consecutive vertices)
-  int g = 0;
+  int g = 0;  // graph of this lane's current vertex (group index)
+  if (a.graphs > 1 && vb + tid < ve) {
+    int lo = 0, hi = a.graphs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.vtx_off[mid] <= vb + tid) lo = mid;
+      else hi = mid - 1;
+    }
+    g = lo;
+  }
   unsigned cursor = 0;
   for (long long c0 = vb; c0 < ve; c0 += kCap) {
-    const long long v0 = c0 + (long long)tid * kItems;
-    if (a.graphs > 1 && v0 < ve) {
-      int lo = 0, hi = a.graphs - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.vtx_off[mid] <= v0) lo = mid;
-        else hi = mid - 1;
-      }
-      g = lo;
-    }
-    long long rp[kItems + 1];
-    unsigned cnt = 0;
+    long long r0[kItems], r1[kItems];
 #pragma unroll
-    for (int i = 0; i <= kItems; ++i) {
-      const long long v = v0 + i;
-      rp[i] = (v <= ve && v <= N) ? a.row_ptr[v] : 0;
+    for (int jj = 0; jj < kItems; ++jj) {
+      const long long v = c0 + (long long)jj * kBlock + tid;
+      r0[jj] = v < ve ? a.row_ptr[v] : 0;
+      r1[jj] = v < ve ? a.row_ptr[v + 1] : 0;
     }
+    unsigned rank[kItems];
+    unsigned okm = 0;
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const long long v = v0 + i;
+    for (int jj = 0; jj < kItems; ++jj) {
+      const long long v = c0 + (long long)jj * kBlock + tid;
+      const long long d = r1[jj] - r0[jj];
+      bool ok = false;
       if (v < ve) {
-        const long long d = rp[i + 1] - rp[i];
-        if (d < 0 || rp[i] < a.ebase || rp[i + 1] > eend) err |= kErrRowPtr;
+        if (d < 0 || r0[jj] < a.ebase || r1[jj] > eend) err |= kErrRowPtr;
         if (d > 0x7fff0000LL) err |= kErrDegree;
-        if (d > 0 && d <= 0x7fff0000LL && rp[i] >= a.ebase && rp[i + 1] <= eend) ++cnt;
+        ok = d > 0 && d <= 0x7fff0000LL && r0[jj] >= a.ebase && r1[jj] <= eend;
       }
+      const unsigned long long bal = __ballot(ok);
+      rank[jj] = (unsigned)__popcll(bal & lt);
+      if (lane == 0) s_cnt[jj * kWaves + wv] = (unsigned)__popcll(bal);
+      okm |= (ok ? 1u : 0u) << jj;
     }
-    unsigned tot;
-    unsigned ex = block_excl_sum<unsigned>(cnt, s32, tot);
-    unsigned at = cursor + ex;
+    __syncthreads();
+    const unsigned c = lane < kItems * kWaves ? s_cnt[lane] : 0u;
+    const unsigned incl = wave_incl_sum_u32(c);
+    const unsigned tot = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+    const unsigned excl = incl - c;
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const long long v = v0 + i;
+    for (int jj = 0; jj < kItems; ++jj) {
+      const long long v = c0 + (long long)jj * kBlock + tid;
+      const unsigned at = cursor + (unsigned)__builtin_amdgcn_readlane((int)excl, jj * kWaves + wv) + rank[jj];
       if (v < ve) {
         if (a.graphs > 1)
           while (a.vtx_off[g + 1] <= v) ++g;
         const long long vg = a.vfirst + v;
         a.c.mate[vg] = -1;
         a.c.state[vg] = 0;
-        const long long d = rp[i + 1] - rp[i];
-        if (d > 0 && d <= 0x7fff0000LL && rp[i] >= a.ebase && rp[i + 1] <= eend) {
+        if ((okm >> jj) & 1u) {
           const int slot = a.slot_of ? a.slot_of[g] : g;
-          a.rows_out[a.rows_base + vb + at] = make_int4((int)vg, (int)rp[i], (int)d, (slot & kGraphMask) | kHeadBit);
-          ++at;
+          a.rows_out[a.rows_base + vb + at] =
+              make_int4((int)vg, (int)r0[jj], (int)(r1[jj] - r0[jj]), (slot & kGraphMask) | kHeadBit);
         }
       }
     }
     cursor += tot;
+    __syncthreads();  // s_cnt is rewritten by the next round
   }
   if (tid == 0) {
     Run r;
@@ -329,33 +341,61 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
       const int r0 = (int)block_lower_bound(
           0, ctl.nruns, [&](long long r) { return (long long)a.in.rpre[r + 1] > p0; }, s_lb);
       int r = r0;
-      for (long long base = p0; base < p1; base += kBlock) {
-        const long long pi = base + threadIdx.x;
-        int g = -1;
-        if (pi < p1) {
-          while (r + 1 < ctl.nruns && (long long)a.in.rpre[r + 1] <= pi) ++r;
-          const int row = a.in.runs[r].row_begin + (int)(pi - a.in.rpre[r]);
-          const int4 rec = a.in.rows[row];
-          if (rec.w & kHeadBit) {
-            const int v = rec.x;
-            g = rec.w & kGraphMask;
-            const int u = a.census ? -1 : a.c.C[v];
-            if ((unsigned)u < (unsigned)a.c.n && a.c.C[u] == v) {
-              a.c.mate[v] = u - a.c.gbase[g];
-              a.c.state[v] = 1;
-              a.in.rows[row].w = rec.w | kMatchedBit;
-              ++cnt;
-            }
+      // kM pieces per lane per round; every load of a round is issued
+      // unconditionally (clamped indices) so that the dependent chain piece ->
+      // C[v] -> C[C[v]] is paid once per round, not once per piece
+      constexpr int kM = 4;
+      for (long long base = p0; base < p1; base += (long long)kBlock * kM) {
+        int row[kM];
+#pragma unroll
+        for (int i = 0; i < kM; ++i) {
+          const long long pi = base + (long long)i * kBlock + threadIdx.x;
+          row[i] = -1;
+          if (pi < p1) {
+            while (r + 1 < ctl.nruns && (long long)a.in.rpre[r + 1] <= pi) ++r;
+            row[i] = a.in.runs[r].row_begin + (int)(pi - a.in.rpre[r]);
+          }
+        }
+        int4 rec[kM];
+#pragma unroll
+        for (int i = 0; i < kM; ++i) rec[i] = a.in.rows[row[i] >= 0 ? row[i] : 0];
+        bool head[kM];
+        int cv[kM];
+#pragma unroll
+        for (int i = 0; i < kM; ++i) {
+          head[i] = row[i] >= 0 && (rec[i].w & kHeadBit) != 0;
+          cv[i] = a.c.C[head[i] ? rec[i].x : 0];
+        }
+        int cu[kM];
+        bool ok[kM];
+#pragma unroll
+        for (int i = 0; i < kM; ++i) {
+          ok[i] = head[i] && !a.census && (unsigned)cv[i] < (unsigned)a.c.n;
+          cu[i] = a.c.C[ok[i] ? cv[i] : 0];
+        }
+#pragma unroll
+        for (int i = 0; i < kM; ++i) {
+          if (ok[i] && cu[i] == rec[i].x) {
+            const int v = rec[i].x;
+            const int g = rec[i].w & kGraphMask;
+            a.c.mate[v] = cv[i] - a.c.gbase[g];
+            a.c.state[v] = 1;
+            a.in.rows[row[i]].w = rec[i].w | kMatchedBit;
+            ++cnt;
           }
         }
         if (a.c.gphase) {  // one atomic per distinct graph per wave
-          unsigned long long active = __ballot(g >= 0);
-          while (active) {
-            const int leader = __ffsll((long long)active) - 1;
-            const int gl = __shfl(g, leader, 64);
-            const unsigned long long same = __ballot(g == gl);
-            if (lane_id() == leader) atomicMax(&a.c.gphase[gl], a.t);
-            active &= ~same;
+#pragma unroll
+          for (int i = 0; i < kM; ++i) {
+            const int g = head[i] ? (rec[i].w & kGraphMask) : -1;
+            unsigned long long active = __ballot(g >= 0);
+            while (active) {
+              const int leader = __ffsll((long long)active) - 1;
+              const int gl = __shfl(g, leader, 64);
+              const unsigned long long same = __ballot(g == gl);
+              if (lane_id() == leader) atomicMax(&a.c.gphase[gl], a.t);
+              active &= ~same;
+            }
           }
         }
       }

@@ -347,7 +347,7 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
   const lm_tuning saved = sv.tun;
   double best_ms = 1e300;
   lm_status rs = LM_OK;
-  const int bes[] = {4096, 16384, 65536};
+  const int bes[] = {2048, 8192, 32768};
   for (int sm : bes) {
     for (int gp = 1; gp <= std::max(1, sv.bpc_stream); ++gp) {
       for (int pp : {4, 8}) {

@@ -141,7 +141,7 @@ lm_status Solver::init_device(int device, size_t budget) {
   if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
   bpc_stream = max_blocks_per_cu_stream();
-  tun.block_entries = 16384;
+  tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = bpc_stream;
   tun.phases_per_sync = 4;
   return LM_OK;
@@ -315,7 +315,6 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   for (;;) {
     const int chunk = first_check ? 2 : std::max(1, tun.phases_per_sync);
     for (int j = 0; j < chunk; ++j) {
-      const int64_t shrink = (int64_t)1 << std::min(j, 20);
       const LiveSet in = live(t);
       MutualArgs ma;
       ma.c = c;
@@ -323,7 +322,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
       ma.t = t;
       ma.mcount = (int*)mcount.p;
       ma.census = 0;
-      const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, (est_V / shrink) / kCap + 1));
+      const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, est_V / kCap + 1));
       HIPCHK(mark_begin(LM_K_MUTUAL));
       HIPCHK(launch_mutual(ma, gm, s));
       HIPCHK(mark_end());
@@ -338,7 +337,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
       sa.parts = (Part*)parts.p;
       sa.bstat = (BlockStat*)bstat.p;
       const int gx = (int)std::max<int64_t>(
-          1, std::min<int64_t>(pcap, (est_L / shrink) / std::max(kCap, tun.block_entries) + 1));
+          1, std::min<int64_t>(pcap, est_L / std::max(kCap, tun.block_entries) + 1));
       HIPCHK(mark_begin(LM_K_COMPACT));
       HIPCHK(launch_compact(sa, gx, s));
       HIPCHK(mark_end());
