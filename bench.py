@@ -30,6 +30,32 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+KERNEL_SOURCES = ["paper_1302_4587_amd/csrc/lm_kernels.hip", "paper_1302_4587_amd/csrc/lm_device.h",
+                  "paper_1302_4587_amd/csrc/lm_key.h", "paper_1302_4587_amd/csrc/lm_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rgg24_hbm_traffic.md")
+
+
+def _measured_traffic():
+    """HBM bytes per compaction launch from the committed counter summary,
+    or None once the kernel sources differ from the ones it was taken on."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    sha = tag = None
+    for line in text.splitlines():
+        if line.startswith("kernel_source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("compact_traffic_bytes_per_launch:"):
+            tag = float(line.split(":", 1)[1])
+    return tag if sha == h.hexdigest() else None
+
+
 def _percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -132,8 +158,11 @@ def main():
     if profile:
         dom = max(kms, key=lambda k: kms[k])
         achieved = kbytes[dom] / (kms[dom] / 1e3) / 1e9 if kms[dom] > 0 else 0.0
+        traffic = _measured_traffic() if dom == "compact" else None
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic, 1) if traffic is not None else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "bytes_per_launch": kbytes[dom] / max(klaunch[dom], 1),
                 "avg_launch_us": kms[dom] * 1e3 / max(klaunch[dom], 1),
                 "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in kms.items()},

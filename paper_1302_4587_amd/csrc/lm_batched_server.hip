@@ -138,7 +138,7 @@ lm_status BatchedState::init(ServerCore* core) {
   rows_cap = 2 * n_cap + 2 * kMaxBlocks + 16;
   pool.budget = core->opts.hbm_budget_bytes + ((size_t)64 << 20);
   pcap = std::max(1, std::min(kMaxBlocks / 2, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc))));
-  pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 4));
+  pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
   lm_status st = LM_OK;
 #define RES(buf, bytes)                 \
   do {                                  \

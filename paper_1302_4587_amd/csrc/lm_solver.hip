@@ -204,7 +204,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   } while (0)
 
   const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_stream))));
-  const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 4));
+  const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
   Ctl* dctl = (Ctl*)ctl.p;
   Totals* dtot = (Totals*)totals.p;
 
