@@ -76,6 +76,9 @@ typedef int32_t lm_status;
 #define LM_CHECK_GRAPH 0x4u  /* validate ids, self-loops, weights (and, for host
                                 inputs, symmetry and duplicates) before solving */
 #define LM_PROFILE 0x8u      /* time every kernel launch with HIP events */
+#define LM_GRAPH 0x10u       /* enqueue the set-up and the first phases as one captured
+                                HIP graph launch (one launch, no host round trip);
+                                ignored together with LM_PROFILE; same results */
 
 typedef struct lm_ctx lm_ctx;
 typedef struct lm_server lm_server;
@@ -112,6 +115,8 @@ typedef struct {
   double bytes_alg;       /* algorithmic HBM bytes of all kernels, from the log */
   lm_phase_rec* log;      /* caller buffer for per-phase records, or NULL */
   int32_t log_cap;        /* its capacity in records */
+  uint32_t profile_kinds; /* input: with LM_PROFILE, bit (1 << LM_K_*) selects the kinds
+                             to time (each timed launch adds two events); 0 = all */
   int32_t k_launches[LM_K_KINDS]; /* LM_PROFILE: launches per kernel kind */
   double k_ms[LM_K_KINDS];        /* LM_PROFILE: summed event time per kind */
   double k_bytes[LM_K_KINDS];     /* algorithmic bytes per kind */

@@ -17,7 +17,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _lib
-from ._lib import (KERNEL_KINDS, LM_CHECK_GRAPH, LM_IN_DEVICE, LM_OUT_DEVICE, LM_PROFILE, LM_SERVE_BATCHED,
+from ._lib import (KERNEL_KINDS, LM_CHECK_GRAPH, LM_GRAPH, LM_IN_DEVICE, LM_OUT_DEVICE, LM_PROFILE, LM_SERVE_BATCHED,
                    LM_SERVE_FIFO, LMError, check)
 
 __all__ = ["Context", "Server", "MatchStats", "LMError", "library_path", "LM_SERVE_BATCHED", "LM_SERVE_FIFO"]
@@ -116,9 +116,10 @@ class Context:
         check(self._lib.lm_set_tuning(self._h, ctypes.byref(t)), "lm_set_tuning")
 
     # -------------------------------------------------------------- solves
-    def _flags_stream(self, dev_in, dev_out, check_graph, profile, stream):
+    def _flags_stream(self, dev_in, dev_out, check_graph, profile, stream, hip_graph=False):
         flags = (LM_IN_DEVICE if dev_in else 0) | (LM_OUT_DEVICE if dev_out else 0)
         flags |= (LM_CHECK_GRAPH if check_graph else 0) | (LM_PROFILE if profile else 0)
+        flags |= LM_GRAPH if hip_graph else 0
         s = None
         if stream is not None:
             s = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", None)
@@ -128,8 +129,9 @@ class Context:
         return flags, s
 
     def match(self, row_ptr, col, w, seed: int = 1, mate=None, *, check_graph=False, profile=False, stream=None,
-              log_cap: int = 4096):
-        """Solves one graph. Returns (mate, MatchStats)."""
+              log_cap: int = 4096, hip_graph=False, profile_kinds=None):
+        """Solves one graph. Returns (mate, MatchStats). hip_graph=True enqueues the
+        set-up and first phases as one captured HIP graph (LM_GRAPH)."""
         n = int(row_ptr.shape[0]) - 1
         nnz = int(col.shape[0])
         rp, d0, k0 = _ptr(row_ptr, np.int64)
@@ -144,19 +146,23 @@ class Context:
             else:
                 mate = np.empty(max(n, 0), dtype=np.int32)
         mp, dm, km = _ptr(mate, np.int32)
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph)
         g = _lib.Csr(n, nnz, rp, cp, wp)
         logbuf = (_lib.PhaseRec * max(log_cap, 1))()
         st = _lib.Stats()
         st.log = logbuf
         st.log_cap = log_cap
+        if profile_kinds:  # names from KERNEL_KINDS: time only these kinds
+            st.profile_kinds = sum(1 << KERNEL_KINDS.index(k) for k in set(profile_kinds))
         check(self._lib.lm_match(self._h, ctypes.byref(g), seed & (2**64 - 1), mp, flags, s, ctypes.byref(st)),
               "lm_match")
         return mate, _stats_out(st, logbuf)
 
     def match_batch(self, vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1, mate=None, *, check_graph=False,
-                    profile=False, stream=None, log_cap: int = 4096, want_graph_phases=True):
-        """Solves a batch (disjoint union, local ids). Returns (mate, MatchStats, graph_phases)."""
+                    profile=False, stream=None, log_cap: int = 4096, want_graph_phases=True, hip_graph=True):
+        """Solves a batch (disjoint union, local ids) in one captured HIP graph
+        launch unless hip_graph=False or profile=True. Returns (mate, MatchStats,
+        graph_phases)."""
         vo = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
         G = len(vo) - 1
         N = int(vo[-1])
@@ -178,7 +184,7 @@ class Context:
         if seeds is not None:
             sk = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
             sp = sk.ctypes.data
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph)
         gph = np.zeros(G, dtype=np.int32) if want_graph_phases else None
         logbuf = (_lib.PhaseRec * max(log_cap, 1))()
         st = _lib.Stats()

@@ -228,7 +228,8 @@ LiveSet BatchedState::live(int tt) const {
 }
 
 void BatchedState::reset_live() {
-  (void)launch_zero((Ctl*)ctl.p, 3, (Totals*)totals.p, s);
+  (void)launch_zero((Ctl*)ctl.p, 3, (Totals*)totals.p, s);  // device phase counter back to 1
+  t = 1;
   L_now = pieces_now = nruns_now = 0;
   phys_end = rows_end = 0;
 }
@@ -360,7 +361,6 @@ lm_status BatchedState::step(int k) {
     MutualArgs ma;
     ma.c = c;
     ma.in = in;
-    ma.t = t;
     ma.mcount = (int*)mcount.p;
     ma.census = 0;
     const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, pieces_now / kCap + 1));
@@ -383,8 +383,7 @@ lm_status BatchedState::step(int k) {
     PlanArgs pa;
     std::memset(&pa, 0, sizeof(pa));
     pa.c = c;
-    pa.mode = kPlanFix | kPlanPrefix;
-    pa.t = t;
+    pa.mode = kPlanFix | kPlanPrefix | kPlanTick;
     pa.ctl_prev = in.ctl;
     pa.parts = (Part*)parts.p;
     pa.bstat = (BlockStat*)bstat.p;
@@ -404,7 +403,6 @@ lm_status BatchedState::step(int k) {
     MutualArgs ma;
     ma.c = c;
     ma.in = live(t);
-    ma.t = t;
     ma.mcount = (int*)mcount.p;
     ma.census = 1;
     e = launch_mutual(ma, (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, pieces_now / kCap + 1)), s);

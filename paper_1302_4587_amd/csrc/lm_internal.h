@@ -84,6 +84,8 @@ struct Totals {
   unsigned int err;
   int last_nonempty;
   unsigned long long matched;
+  int t;    // current phase (1-based): read by the mutual check, advanced by the plan kernel
+  int pad;
 };
 
 enum : unsigned {
@@ -134,15 +136,13 @@ struct StreamArgs {
 struct MutualArgs {
   Common c;
   LiveSet in;
-  int t;
   int* mcount;  // matched vertices per workgroup
   int census;   // only record gphase[g] = t for graphs with a live row (no matching)
 };
 
 struct PlanArgs {
   Common c;
-  int mode;          // kPlanFix | kPlanPrefix | kPlanLog
-  int t;             // phase whose compaction just ran (log index t-1)
+  int mode;          // kPlanFix | kPlanPrefix | kPlanLog | kPlanTick
   int first;         // fixup after the first argmax (no pieces written)
   // fixup of the compaction (or first argmax) that just ran
   const Ctl* ctl_prev;  // live set it consumed
@@ -162,7 +162,9 @@ struct PlanArgs {
   LogRec* log;
   int log_cap;
 };
-enum : int { kPlanFix = 1, kPlanPrefix = 2, kPlanLog = 4 };
+// kPlanLog writes the log record of the phase totals->t; kPlanTick then
+// advances totals->t (after the compaction of that phase).
+enum : int { kPlanFix = 1, kPlanPrefix = 2, kPlanLog = 4, kPlanTick = 8 };
 
 // Live-set construction for vertices [vfirst, vfirst + vcount) of the
 // vertex space: row_ptr (vcount + 1 offsets into the entry buffer, from ebase

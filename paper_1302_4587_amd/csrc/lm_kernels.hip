@@ -39,6 +39,8 @@ __global__ void k_zero(Ctl* ctl, int nctl, Totals* totals) {
     totals->err = 0;
     totals->last_nonempty = 0;
     totals->matched = 0;
+    totals->t = 1;
+    totals->pad = 0;
   }
 }
 
@@ -310,18 +312,20 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-      if (a.t >= 1 && a.t <= a.log_cap) {
+      const int t = a.c.totals->t;
+      if (t >= 1 && t <= a.log_cap) {
         LogRec r;
         r.live_entries = prev.L;
         r.live_rows = prev.heads;
         r.matched_edges = s_red[0] / 2;
         r.matched_entries = s_red[1];
-        a.log[a.t - 1] = r;
+        a.log[t - 1] = r;
       }
-      if (prev.heads > 0) a.c.totals->last_nonempty = a.t;
+      if (prev.heads > 0) a.c.totals->last_nonempty = t;
       a.c.totals->matched += (unsigned long long)s_red[0];
     }
   }
+  if ((a.mode & kPlanTick) && tid == 0) a.c.totals->t += 1;
 }
 
 // ---------------------------------------------------------------- mutual
@@ -332,6 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
   __shared__ unsigned s32[kWaves];
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
+  const int t = a.c.totals->t;
   for (int bb = blockIdx.x; bb < ctl.Pm; bb += gridDim.x) {
     const long long V = ctl.pieces;
     const long long p0 = V * bb / ctl.Pm, p1 = V * (bb + 1) / ctl.Pm;
@@ -393,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
               const int leader = __ffsll((long long)active) - 1;
               const int gl = __shfl(g, leader, 64);
               const unsigned long long same = __ballot(g == gl);
-              if (lane_id() == leader) atomicMax(&a.c.gphase[gl], a.t);
+              if (lane_id() == leader) atomicMax(&a.c.gphase[gl], t);
               active &= ~same;
             }
           }
@@ -623,6 +628,10 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   const int row_start = k0 + b;
   long long loaded_total = 0;  // lane 0 only
   bool first_batch = true;
+  int4 pf_rec = make_int4(-1, 0, 0, 0);  // prefetched piece of the next window
+  long long pf_gk = -1;
+  int pf_rr = 0;
+  bool pf_ok = false;
   for (;;) {
     const long long pos = sm.pos;
     if (pos >= E1) break;
@@ -645,8 +654,13 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     int4 rec = make_int4(-1, 0, 0, 0);
     bool mt = false;
     if (valid) {
-      const int row = gk < run_hi ? run_rb + (int)(gk - run_lo) : piece_row(a.in, gk, rr, ctl.nruns);
-      rec = a.in.rows[row];
+      if (pf_ok && pf_gk == gk) {  // loaded during the previous batch
+        rec = pf_rec;
+        rr = pf_rr;
+      } else {
+        const int row = gk < run_hi ? run_rb + (int)(gk - run_lo) : piece_row(a.in, gk, rr, ctl.nruns);
+        rec = a.in.rows[row];
+      }
       if (tid == 0) {
         rec.y += cur_o;
         rec.z -= cur_o;
@@ -693,6 +707,17 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     if (nt == 0) {  // nothing consumable: the live set is inconsistent; stop, never spin
       if (tid == 0) atomicOr(&a.c.totals->err, kErrInternal);
       break;
+    }
+    // prefetch the next batch's window so that its load overlaps this batch
+    {
+      pf_gk = (long long)cur_k + nt - (sm.last_partial ? 1 : 0) + tid;
+      pf_ok = pf_gk < ctl.pieces;
+      if (pf_ok) {
+        int r2 = rr;
+        const int row = pf_gk < run_hi ? run_rb + (int)(pf_gk - run_lo) : piece_row(a.in, pf_gk, r2, ctl.nruns);
+        pf_rec = a.in.rows[row];
+        pf_rr = r2;
+      }
     }
     const int NLD = sm.nld;
     const bool mine = tid < nt;

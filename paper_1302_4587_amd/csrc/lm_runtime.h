@@ -17,6 +17,7 @@
 namespace lm {
 
 constexpr int kLogCap = 1 << 16;  // device phase records kept per solve
+constexpr int kGraphPhases = 12;  // phases in the captured graph (LM_GRAPH)
 
 struct DevBuf {
   void* p = nullptr;
@@ -61,6 +62,7 @@ struct Solver {
   Ctl* h_ctl = nullptr;
   Totals* h_totals = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t e_order = nullptr;  // orders solves after the legacy default stream
   std::vector<hipEvent_t> evpool;
 
   lm_status init_device(int device, size_t budget);

@@ -37,10 +37,49 @@ static double ms_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
+void* PinnedPool::get(size_t bytes, size_t* cap) {
+  size_t c = (size_t)1 << 20;
+  while (c < bytes) c <<= 1;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = free.find(c);
+    if (it != free.end()) {
+      void* p = it->second;
+      free.erase(it);
+      cached -= c;
+      *cap = c;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, c) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  *cap = c;
+  return p;
+}
+
+void PinnedPool::put(void* p, size_t cap) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (cached + cap <= limit) {
+      free.emplace(cap, p);
+      cached += cap;
+      return;
+    }
+  }
+  (void)hipHostFree(p);
+}
+
+PinnedPool::~PinnedPool() {
+  for (auto& kv : free) (void)hipHostFree(kv.second);
+  free.clear();
+}
+
 Request::~Request() {
-  if (h_rp) (void)hipHostFree(h_rp);
-  if (h_col) (void)hipHostFree(h_col);
-  if (h_w) (void)hipHostFree(h_w);
+  if (pool) pool->put(block, block_cap);
 }
 
 void ServerCore::finish(const std::shared_ptr<Request>& r, lm_status st) {
@@ -129,7 +168,7 @@ static lm_status quick_check(const lm_csr* g) {
         std::memcpy(&bits, &x, 4);
         if (bits == 0x80000000u) bits = 0;
         const uint64_t lo = (uint64_t)std::min<int64_t>(v, u), hi = (uint64_t)std::max<int64_t>(v, u);
-        const uint64_t h = host_mix64(((lo << 32) | hi) ^ host_mix64((uint64_t)bits + kGoldenGamma));
+        const uint64_t h = host_mix64((((lo << 32) | hi) * kGoldenGamma) ^ ((uint64_t)bits << 17 | bits));
         if (v < u)
           a.up += h;
         else
@@ -215,10 +254,14 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
   r->seed = seed;
   r->footprint = fp;
   r->t_submit = Clock::now();
-  if (hipHostMalloc((void**)&r->h_rp, (size_t)(g->n + 1) * 8) != hipSuccess ||
-      hipHostMalloc((void**)&r->h_col, (size_t)std::max<int64_t>(g->nnz, 1) * 4) != hipSuccess ||
-      hipHostMalloc((void**)&r->h_w, (size_t)std::max<int64_t>(g->nnz, 1) * 4) != hipSuccess)
-    return LM_ENOMEM;
+  const size_t b_rp = ((size_t)(g->n + 1) * 8 + 255) & ~(size_t)255;
+  const size_t b_e = ((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 255) & ~(size_t)255;
+  r->pool = &S.pinned;
+  r->block = S.pinned.get(b_rp + 2 * b_e, &r->block_cap);
+  if (!r->block) return LM_ENOMEM;
+  r->h_rp = (int64_t*)r->block;
+  r->h_col = (int32_t*)((char*)r->block + b_rp);
+  r->h_w = (float*)((char*)r->block + b_rp + b_e);
   parallel_copy(r->h_rp, g->row_ptr, (size_t)(g->n + 1) * 8);
   if (g->nnz > 0) {
     parallel_copy(r->h_col, g->col, (size_t)g->nnz * 4);

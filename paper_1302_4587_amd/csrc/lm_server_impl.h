@@ -17,12 +17,28 @@
 
 namespace lm {
 
+// Reusable pinned host blocks (pinning is far slower than copying): blocks
+// are kept in power-of-two size classes up to a cached total.
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free;  // capacity -> block
+  size_t cached = 0;
+  size_t limit = (size_t)8 << 30;
+  void* get(size_t bytes, size_t* cap);
+  void put(void* p, size_t cap);
+  ~PinnedPool();
+};
+
 struct Request {
   uint64_t ticket = 0;
   int64_t n = 0, nnz = 0;
   uint64_t seed = 1;
   size_t footprint = 0;
-  int64_t* h_rp = nullptr;  // pinned copies of the request graph
+  // pinned copy of the request graph: row_ptr, col, w in one block
+  PinnedPool* pool = nullptr;
+  void* block = nullptr;
+  size_t block_cap = 0;
+  int64_t* h_rp = nullptr;
   int32_t* h_col = nullptr;
   float* h_w = nullptr;
   std::vector<int32_t> mate;
@@ -41,6 +57,7 @@ struct Request {
 struct BatchedState;  // lm_batched_server.hip
 
 struct ServerCore {
+  PinnedPool pinned;  // first member: outlives every request it lends to
   lm_ctx* ctx = nullptr;
   lm_server_opts opts{};
   std::mutex mu;

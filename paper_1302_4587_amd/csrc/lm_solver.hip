@@ -140,6 +140,7 @@ lm_status Solver::init_device(int device, size_t budget) {
   if (hipHostMalloc((void**)&h_ctl, 2 * sizeof(Ctl)) != hipSuccess) return LM_EDEVICE;
   if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
+  if (hipEventCreateWithFlags(&e_order, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
   bpc_stream = max_blocks_per_cu_stream();
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = bpc_stream;
@@ -159,6 +160,8 @@ void Solver::shutdown() {
   evpool.clear();
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  if (e_order) (void)hipEventDestroy(e_order);
+  e_order = nullptr;
   if (h_ctl) (void)hipHostFree(h_ctl);
   if (h_totals) (void)hipHostFree(h_totals);
   if (own) (void)hipStreamDestroy(own);
@@ -182,16 +185,21 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   const bool prof = (flags & LM_PROFILE) != 0;
   std::vector<std::pair<int, size_t>> marks;  // (kind, event index of start)
   size_t evn = 0;
+  const uint32_t kmask = (st && st->profile_kinds) ? st->profile_kinds : ((1u << LM_K_KINDS) - 1);
+  bool mark_open = false;
   auto mark_begin = [&](int kind) -> hipError_t {
-    if (!prof) return hipSuccess;
+    mark_open = false;
+    if (!prof || !((kmask >> kind) & 1u)) return hipSuccess;
     hipEvent_t e = event(evn);
     if (!e || !event(evn + 1)) return hipErrorOutOfMemory;
     marks.push_back({kind, evn});
     evn += 2;
+    mark_open = true;
     return hipEventRecord(e, s);
   };
   auto mark_end = [&]() -> hipError_t {
-    if (!prof) return hipSuccess;
+    if (!mark_open) return hipSuccess;
+    mark_open = false;
     return hipEventRecord(event(marks.back().second + 1), s);
   };
 #define HIPCHK(x)                          \
@@ -245,17 +253,24 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     return a;
   };
 
-  HIPCHK(hipEventRecord(e0, s));
-  HIPCHK(launch_zero(dctl, 2, dtot, s));
-  if (p.gphase) HIPCHK(launch_fill_i32(p.gphase, p.G, 0, s));
-  if (flags & LM_CHECK_GRAPH) {
-    CheckArgs ca{dtot, p.nnz, p.row_ptr, p.col, p.w, (int)p.N, (int)p.G, p.vtx_off};
-    const int grid = (int)std::min<int64_t>(pmcap, (p.N + kBlock - 1) / kBlock + 1);
-    HIPCHK(launch_check(ca, grid, s));
-  }
-  // live set R_1 from the input
-  const int pi = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, (p.N + 16383) / 16384));
-  {
+  int64_t est_L = p.nnz, est_V = p.N;
+  // Every launch returns its status; HIPCHK is not used between BeginCapture
+  // and EndCapture so that a failed launch never leaves the stream capturing.
+#define ENQ(x)                        \
+  do {                                \
+    hipError_t _e = (x);              \
+    if (_e != hipSuccess) return _e;  \
+  } while (0)
+  // live set R_1 from the input and the first argmax over it
+  auto enqueue_prologue = [&]() -> hipError_t {
+    ENQ(launch_zero(dctl, 2, dtot, s));
+    if (p.gphase) ENQ(launch_fill_i32(p.gphase, p.G, 0, s));
+    if (flags & LM_CHECK_GRAPH) {
+      CheckArgs ca{dtot, p.nnz, p.row_ptr, p.col, p.w, (int)p.N, (int)p.G, p.vtx_off};
+      const int grid = (int)std::min<int64_t>(pmcap, (p.N + kBlock - 1) / kBlock + 1);
+      ENQ(launch_check(ca, grid, s));
+    }
+    const int pi = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, (p.N + 16383) / 16384));
     InitArgs ia;
     ia.c = c;
     ia.row_ptr = p.row_ptr;
@@ -271,9 +286,9 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ia.runs_base = 0;
     ia.runs_out = (Run*)runs[0].p;
     ia.rows_out = (int4*)rows[0].p;
-    HIPCHK(mark_begin(LM_K_INIT));
-    HIPCHK(launch_init(ia, s));
-    HIPCHK(mark_end());
+    ENQ(mark_begin(LM_K_INIT));
+    ENQ(launch_init(ia, s));
+    ENQ(mark_end());
     PlanArgs pa = plan_base();
     pa.mode = kPlanPrefix;
     pa.ctl_prev = nullptr;
@@ -282,12 +297,9 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     pa.epre_new = (long long*)epre[0].p;
     pa.rpre_new = (int*)rpre[0].p;
     pa.ctl_new = dctl + 0;
-    HIPCHK(mark_begin(LM_K_PLAN));
-    HIPCHK(launch_plan(pa, s));
-    HIPCHK(mark_end());
-  }
-  // first argmax over R_1
-  {
+    ENQ(mark_begin(LM_K_PLAN));
+    ENQ(launch_plan(pa, s));
+    ENQ(mark_end());
     StreamArgs sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.c = c;
@@ -295,68 +307,104 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     sa.parts = (Part*)parts.p;
     sa.bstat = (BlockStat*)bstat.p;
     const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, p.nnz / std::max(kCap, tun.block_entries) + 1));
-    HIPCHK(mark_begin(LM_K_ARGMAX));
-    HIPCHK(launch_first_argmax(sa, gx, s));
-    HIPCHK(mark_end());
-    PlanArgs pa = plan_base();
-    pa.mode = kPlanFix;
-    pa.first = 1;
-    pa.ctl_prev = dctl + 0;
-    pa.parts = (Part*)parts.p;
-    HIPCHK(mark_begin(LM_K_PLAN));
-    HIPCHK(launch_plan(pa, s));
-    HIPCHK(mark_end());
-  }
-  // phase loop
+    ENQ(mark_begin(LM_K_ARGMAX));
+    ENQ(launch_first_argmax(sa, gx, s));
+    ENQ(mark_end());
+    PlanArgs pf = plan_base();
+    pf.mode = kPlanFix;
+    pf.first = 1;
+    pf.ctl_prev = dctl + 0;
+    pf.parts = (Part*)parts.p;
+    ENQ(mark_begin(LM_K_PLAN));
+    ENQ(launch_plan(pf, s));
+    ENQ(mark_end());
+    return hipSuccess;
+  };
+  // phase t: mutual check, compaction fused with the next argmax, plan
   int t = 1;
-  int64_t est_L = p.nnz, est_V = p.N;
-  int64_t last_live = -1;
-  bool first_check = true, stalled = false;
-  for (;;) {
-    const int chunk = first_check ? 2 : std::max(1, tun.phases_per_sync);
-    for (int j = 0; j < chunk; ++j) {
-      const LiveSet in = live(t);
-      MutualArgs ma;
-      ma.c = c;
-      ma.in = in;
-      ma.t = t;
-      ma.mcount = (int*)mcount.p;
-      ma.census = 0;
-      const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, est_V / kCap + 1));
-      HIPCHK(mark_begin(LM_K_MUTUAL));
-      HIPCHK(launch_mutual(ma, gm, s));
-      HIPCHK(mark_end());
-      const int lo = t & 1;
-      StreamArgs sa;
-      sa.c = c;
-      sa.in = in;
-      sa.runs_out = (Run*)runs[lo].p;
-      sa.rows_out = (int4*)rows[lo].p;
-      sa.dst_col = (int*)ecol[(t + 1) & 1].p;
-      sa.dst_w = (float*)ew[(t + 1) & 1].p;
-      sa.parts = (Part*)parts.p;
-      sa.bstat = (BlockStat*)bstat.p;
-      const int gx = (int)std::max<int64_t>(
-          1, std::min<int64_t>(pcap, est_L / std::max(kCap, tun.block_entries) + 1));
-      HIPCHK(mark_begin(LM_K_COMPACT));
-      HIPCHK(launch_compact(sa, gx, s));
-      HIPCHK(mark_end());
-      PlanArgs pa = plan_base();
-      pa.mode = kPlanFix | kPlanPrefix | kPlanLog;
-      pa.t = t;
-      pa.ctl_prev = in.ctl;
-      pa.parts = (Part*)parts.p;
-      pa.bstat = (BlockStat*)bstat.p;
-      pa.rows_out = (int4*)rows[lo].p;
-      pa.runs_new = (const Run*)runs[lo].p;
-      pa.epre_new = (long long*)epre[lo].p;
-      pa.rpre_new = (int*)rpre[lo].p;
-      pa.ctl_new = dctl + lo;
-      HIPCHK(mark_begin(LM_K_PLAN));
-      HIPCHK(launch_plan(pa, s));
-      HIPCHK(mark_end());
-      ++t;
+  auto enqueue_phase = [&]() -> hipError_t {
+    const LiveSet in = live(t);
+    MutualArgs ma;
+    ma.c = c;
+    ma.in = in;
+    ma.mcount = (int*)mcount.p;
+    ma.census = 0;
+    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, est_V / kCap + 1));
+    ENQ(mark_begin(LM_K_MUTUAL));
+    ENQ(launch_mutual(ma, gm, s));
+    ENQ(mark_end());
+    const int lo = t & 1;
+    StreamArgs sa;
+    sa.c = c;
+    sa.in = in;
+    sa.runs_out = (Run*)runs[lo].p;
+    sa.rows_out = (int4*)rows[lo].p;
+    sa.dst_col = (int*)ecol[(t + 1) & 1].p;
+    sa.dst_w = (float*)ew[(t + 1) & 1].p;
+    sa.parts = (Part*)parts.p;
+    sa.bstat = (BlockStat*)bstat.p;
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, est_L / std::max(kCap, tun.block_entries) + 1));
+    ENQ(mark_begin(LM_K_COMPACT));
+    ENQ(launch_compact(sa, gx, s));
+    ENQ(mark_end());
+    PlanArgs pa = plan_base();
+    pa.mode = kPlanFix | kPlanPrefix | kPlanLog | kPlanTick;
+    pa.ctl_prev = in.ctl;
+    pa.parts = (Part*)parts.p;
+    pa.bstat = (BlockStat*)bstat.p;
+    pa.rows_out = (int4*)rows[lo].p;
+    pa.runs_new = (const Run*)runs[lo].p;
+    pa.epre_new = (long long*)epre[lo].p;
+    pa.rpre_new = (int*)rpre[lo].p;
+    pa.ctl_new = dctl + lo;
+    ENQ(mark_begin(LM_K_PLAN));
+    ENQ(launch_plan(pa, s));
+    ENQ(mark_end());
+    ++t;
+    return hipSuccess;
+  };
+#undef ENQ
+
+  HIPCHK(hipEventRecord(e0, s));
+  // With LM_GRAPH the prologue and the first kGraphPhases phases are one
+  // captured HIP graph: one launch, no host round trip in between. Phases
+  // after the live set emptied are no-ops (every kernel reads the live-set
+  // size from the device), so overshooting is harmless.
+  const bool use_graph = (flags & LM_GRAPH) != 0 && !prof;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraph_t& g;
+    hipGraphExec_t& x;
+    ~GraphGuard() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
     }
+  } guard{graph, gexec};
+  bool first_check = true;
+  if (use_graph) {
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = enqueue_prologue();
+    for (int j = 0; j < kGraphPhases && ce == hipSuccess; ++j) ce = enqueue_phase();
+    const hipError_t ee = hipStreamEndCapture(s, &graph);
+    HIPCHK(ce);
+    HIPCHK(ee);
+    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphLaunch(gexec, s));
+    first_check = false;
+  } else {
+    HIPCHK(enqueue_prologue());
+  }
+  // phase loop: sync every few phases to see whether the live set is empty
+  int64_t last_live = -1;
+  bool stalled = false;
+  bool pending = use_graph;  // the graph's phases still need a check
+  for (;;) {
+    if (!pending) {
+      const int chunk = first_check ? 2 : std::max(1, tun.phases_per_sync);
+      for (int j = 0; j < chunk; ++j) HIPCHK(enqueue_phase());
+    }
+    pending = false;
     HIPCHK(hipMemcpyAsync(h_ctl, dctl + ((t - 1) & 1), sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(h_totals, dtot, sizeof(Totals), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -530,7 +578,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
                               const int64_t* row_ptr, const int32_t* col, const float* w, const uint64_t* seeds,
                               uint64_t seed0, int32_t* mate, uint32_t flags, void* stream, lm_stats* st,
                               int32_t* graph_phases) {
-  const uint32_t known = LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE;
+  const uint32_t known = LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE | LM_GRAPH;
   if (flags & ~known) return LM_EINVAL;
   if (N < 0 || nnz < 0 || G < 1) return LM_EINVAL;
   if (N >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 31) - 65536) return LM_ETOOBIG;
@@ -539,6 +587,16 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   Solver& S = c->s;
   if (hipSetDevice(S.dev) != hipSuccess) return LM_EDEVICE;
   hipStream_t s = stream ? (hipStream_t)stream : S.own;
+  if (!stream) {
+    // The caller named the legacy default stream (or none): order the solve
+    // after everything already queued there (for example the kernels that
+    // produced device inputs). The context's own stream does not block on
+    // the default stream by itself.
+    if (hipEventRecord(S.e_order, nullptr) != hipSuccess || hipStreamWaitEvent(s, S.e_order, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return LM_EDEVICE;
+    }
+  }
   const bool in_dev = (flags & LM_IN_DEVICE) != 0;
   const bool out_dev = (flags & LM_OUT_DEVICE) != 0;
   // host-side checks that need no device work

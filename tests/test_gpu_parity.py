@@ -241,3 +241,62 @@ def test_profile_stats(ctx, torch_dev):
     assert st.kernel_launches["mutual"] >= st.phases and st.kernel_launches["compact"] >= st.phases
     assert all(st.kernel_ms[k] > 0 for k in ("init", "argmax", "mutual", "compact"))
     assert st.bytes_alg > 8 * g.nnz
+
+
+def test_hip_graph_mode_matches_eager(ctx, torch_dev):
+    """LM_GRAPH captures the set-up and the first phases into one HIP graph per
+    call; the remaining phases (if any) run eagerly. Several graph solves in a
+    row, with eager solves and host syncs in between, must each equal the
+    eager result and the oracle."""
+    import torch
+    cases = [
+        ("er 4096", lmgen.er(4096, 32768, seed=1)),
+        ("rmat 13", lmgen.rmat(13, 16, seed=8)),
+        ("increasing path 301", lmgen.from_edges(302, [[i, i + 1] for i in range(301)], np.arange(1, 302))),
+        ("single edge", lmgen.from_edges(2, [[0, 1]], [0.5])),
+    ]
+    for rep in range(3):
+        for name, g in cases:
+            print(f"case: hip graph rep={rep} {name}", flush=True)
+            eager, st_e = _solve(ctx, torch_dev, g, 7)
+            torch.cuda.synchronize()
+            graphed, st_g = _solve(ctx, torch_dev, g, 7, hip_graph=True)
+            assert np.array_equal(eager, graphed), f"{name}: graph result differs from eager"
+            assert st_g.phases == st_e.phases and np.array_equal(st_g.log, st_e.log)
+            _assert_parity(g, 7, graphed, st_g, f"graph {name}")
+
+
+def test_batch_hip_graph_matches_eager(ctx, torch_dev):
+    import torch
+    b = lmgen.er_batch(128, seed=4, lg_lo=4.0, lg_hi=12.0)
+    rp, col, w = (torch.from_numpy(np.ascontiguousarray(x)).to(torch_dev) for x in (b.row_ptr, b.col, b.w))
+    ref_mate, ref_ph = oracle.local_max_batch(b.vtx_off, b.row_ptr, b.col, b.w, seed0=3)
+    for rep in range(3):
+        print(f"case: batch hip graph rep={rep}", flush=True)
+        m_e, _, ph_e = ctx.match_batch(b.vtx_off, rp, col, w, seed0=3, hip_graph=False)
+        m_g, _, ph_g = ctx.match_batch(b.vtx_off, rp, col, w, seed0=3, hip_graph=True)
+        assert np.array_equal(m_e.cpu().numpy(), ref_mate) and np.array_equal(m_g.cpu().numpy(), ref_mate)
+        assert np.array_equal(ph_e, ref_ph) and np.array_equal(ph_g, ref_ph)
+
+
+def test_autotune_batch_and_cache(ctx, torch_dev, tmp_path):
+    import torch
+    b = lmgen.er_batch(48, seed=9, lg_lo=6.0, lg_hi=11.0)
+    rp, col, w = (torch.from_numpy(np.ascontiguousarray(x)).to(torch_dev) for x in (b.row_ptr, b.col, b.w))
+    base = ctx.tuning()
+    cache = str(tmp_path / "tune.jsonl")
+    try:
+        print("case: autotune batch of 48", flush=True)
+        t1 = ctx.autotune_batch(b.vtx_off, rp, col, w, cache_path=cache)
+        assert 2048 <= t1["block_entries"] <= 4194304 and t1["grid_per_cu"] >= 1 and t1["phases_per_sync"] >= 1
+        assert ctx.tuning() == t1
+        lines = open(cache).read().strip().splitlines()
+        assert len(lines) == 1 and '"block_entries"' in lines[0]
+        ctx.set_tuning(**base)
+        t2 = ctx.autotune_batch(b.vtx_off, rp, col, w, cache_path=cache)  # answered from the cache
+        assert t2 == t1 and len(open(cache).read().strip().splitlines()) == 1
+        mate, _, gph = ctx.match_batch(b.vtx_off, rp, col, w, seed0=1)
+        ref_mate, ref_ph = oracle.local_max_batch(b.vtx_off, b.row_ptr, b.col, b.w, seed0=1)
+        assert np.array_equal(mate.cpu().numpy(), ref_mate) and np.array_equal(gph, ref_ph)
+    finally:
+        ctx.set_tuning(**base)
