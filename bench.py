@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["rgg", "rmat"], default="rgg",
+                    help="rgg: 2-D random geometric graph (the headline); rmat: R-MAT edge factor 16, unit weights")
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--avg-degree", type=float, default=10.0)
     ap.add_argument("--seed", type=int, default=1)
@@ -100,9 +102,14 @@ def main():
     dev = torch.device("cuda:0")
     n = 1 << args.log2n
     t0 = time.time()
-    g = lmgen.rgg(n, args.avg_degree, args.seed)
+    if args.workload == "rgg":
+        g = lmgen.rgg(n, args.avg_degree, args.seed)
+        workload = f"rgg2d n=2^{args.log2n} avg_degree={args.avg_degree:g} w=1-dist seed={args.seed}"
+    else:
+        g = lmgen.rmat(args.log2n, 16, seed=args.seed)
+        workload = f"rmat scale={args.log2n} edge_factor=16 (a,b,c,d)=(.57,.19,.19,.05) unit weights seed={args.seed}"
     gen_s = time.time() - t0
-    print(f"bench: generated rgg n={g.n} m={g.m} nnz={g.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    print(f"bench: generated {args.workload} n={g.n} m={g.m} nnz={g.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
     w = torch.from_numpy(g.w).to(dev)
@@ -215,7 +222,7 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": f"rgg2d n=2^{args.log2n} avg_degree={args.avg_degree:g} w=1-dist seed={args.seed}",
+        "config": {"workload": workload,
                    "n": g.n, "m": g.m, "nnz": g.nnz, "phases": phases, "parallelism": "single GPU"},
         "gbps_alg_whole_solve": round(bytes_alg / (np.median(dev_ms) / 1e3) / 1e9, 1),
         "device_ms_median": round(float(np.median(dev_ms)), 4),

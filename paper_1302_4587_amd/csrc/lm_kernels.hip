@@ -441,6 +441,7 @@ struct Carry {
 };
 
 constexpr int kLong = 32;                        // longer pieces are reduced by a whole wave
+constexpr int kTieLanes = 4;                     // more tied pieces per batch: striped tie-break
 constexpr int kLongMax = kCap / (kLong + 1) + 1;  // long pieces per batch at most
 
 struct StreamSmem {
@@ -460,6 +461,10 @@ struct StreamSmem {
   unsigned s_max[kWaves];
   unsigned s_cnt[kItems * kWaves];
   unsigned s_emit[kWaves];
+  unsigned long long p_hash[kWin];  // largest tie-break hash per tied piece
+  unsigned char p_tie[kWin];        // the piece's largest weight repeats
+  unsigned s_lmax[kWaves];
+  Key s_lkey[kWaves];
   int longlist[kLongMax];
   int lb[1];
   Carry carry;
@@ -514,7 +519,7 @@ __device__ __forceinline__ Key wave_max_key(Key k) {
 
 // Among the entries of one row piece whose ordered weight equals m (at
 // least two), the neighbour with the largest tie-break hash.
-__device__ __noinline__ int tie_break(const uint2* e, int n, unsigned m, unsigned vloc, unsigned long long S) {
+__device__ __forceinline__ int tie_break(const uint2* e, int n, unsigned m, unsigned vloc, unsigned long long S) {
   uint64_t hb = 0;
   int ub = -1;
   for (int i = 0; i < n; ++i) {
@@ -822,6 +827,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     }
     unsigned bw = 0u;
     int bu = -1;
+    bool tie = false;
     if (mine && ldt <= kLong) {
       // largest ordered weight, its first neighbour, and whether it repeats;
       // only a repeated largest weight needs the tie-break hash
@@ -835,14 +841,81 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         mu = gt ? (int)e.y : mu;
         m = gt ? e.x : m;
       }
-      if (m != 0u && ties > 0) mu = tie_break(sm.e_cw + my_vo, ldt, m, myvloc, mySeed);
+      tie = m != 0u && ties > 0;
       bw = m;
       bu = mu;
       sm.p_w[tid] = bw;
       sm.p_u[tid] = bu;
+      if (tie) sm.p_hash[tid] = 0ull;
     }
-    {
-      const int nlong = sm.nlong;
+    if (mine) sm.p_tie[tid] = tie ? 1 : 0;
+    // A repeated largest weight is settled by the tie-break hash. With few
+    // such pieces each lane rescans its own piece; with many (unit weights)
+    // all lanes hash the tied entries of the batch in striped order, keep the
+    // largest hash per piece with an LDS atomic max, and each piece's lane
+    // recovers the neighbour by inverting the hash.
+    const int ntie = __syncthreads_count(tie ? 1 : 0);
+    if (ntie > 0 && ntie <= kTieLanes) {
+      if (tie) {
+        bu = tie_break(sm.e_cw + my_vo, ldt, bw, myvloc, mySeed);
+        sm.p_u[tid] = bu;
+      }
+    } else if (ntie > kTieLanes) {
+#pragma unroll
+      for (int jj = 0; jj < kItems; ++jj) {
+        const int q = tid + kBlock * jj;
+        if (q < NLD) {
+          const int j = sm.rowof[q];
+          if (sm.p_tie[j]) {
+            const uint2 e = sm.e_cw[q];
+            if (e.x == sm.p_w[j]) {
+              const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+              const uint64_t h = edge_hash(S, (unsigned)(sm.p_v[j] - sm.p_base[j]), e.y);
+              atomicMax(&sm.p_hash[j], (unsigned long long)h);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (tie) {
+        bu = hash_neighbour(sm.p_hash[tid], mySeed, myvloc);
+        sm.p_u[tid] = bu;
+      }
+    }
+    const int nlong = sm.nlong;
+    if (nlong > 0 && nlong < kWaves) {
+      // few long pieces (a hub row fills most of the batch): the whole
+      // workgroup reduces each one, largest ordered weight first, then the
+      // largest tie-break hash among the entries that reach it
+      for (int li = 0; li < nlong; ++li) {
+        const int j = sm.longlist[li];
+        const int vo = sm.p_vo[j], ld = sm.p_ld[j];
+        unsigned m = 0u;
+        for (int i = tid; i < ld; i += kBlock) m = max(m, sm.e_cw[vo + i].x);
+        m = (unsigned)__builtin_amdgcn_readlane((int)wave_incl_max_u32(m), 63);
+        if (lane == 0) sm.s_lmax[wv] = m;
+        __syncthreads();
+        m = max(max(sm.s_lmax[0], sm.s_lmax[1]), max(sm.s_lmax[2], sm.s_lmax[3]));
+        Key k = key_ident();
+        if (m != 0u) {
+          const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+          const unsigned vloc = (unsigned)(sm.p_v[j] - sm.p_base[j]);
+          for (int i = tid; i < ld; i += kBlock) {
+            const uint2 e = sm.e_cw[vo + i];
+            if (e.x == m) k = key_max(k, full_key(m, (int)e.y, vloc, S));
+          }
+        }
+        k = wave_max_key(k);
+        if (lane == 0) sm.s_lkey[wv] = k;
+        __syncthreads();
+        if (tid == 0) {
+          Key best = sm.s_lkey[0];
+          for (int x = 1; x < kWaves; ++x) best = key_max(best, sm.s_lkey[x]);
+          sm.p_w[j] = best.w;
+          sm.p_u[j] = best.u;
+        }
+      }
+    } else {
       for (int li = wv; li < nlong; li += kWaves) {  // a wave per long piece
         const int j = sm.longlist[li];
         const int vo = sm.p_vo[j], ld = sm.p_ld[j];

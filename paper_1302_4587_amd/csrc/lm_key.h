@@ -24,6 +24,18 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 inline uint64_t host_mix64(uint64_t z) { return mix64(z); }
 
+// Inverse of mix64. Every step of the output function is a bijection on 64
+// bits: an xor with the value shifted right by s >= 27 is undone by xoring the
+// shifts by s and 2s, and the odd multipliers have inverses modulo 2^64.
+__host__ __device__ __forceinline__ uint64_t unmix64(uint64_t z) {
+  z = z ^ (z >> 31) ^ (z >> 62);
+  z *= 0x319642B2D24D8EC3ull;  // 0x94D049BB133111EB^-1 mod 2^64
+  z = z ^ (z >> 27) ^ (z >> 54);
+  z *= 0x96DE1B173F119089ull;  // 0xBF58476D1CE4E5B9^-1 mod 2^64
+  z = z ^ (z >> 30) ^ (z >> 60);
+  return z;
+}
+
 // Order-preserving image of a finite fp32 bit pattern; 0 is below all of them.
 __device__ __forceinline__ unsigned ord_weight_bits(unsigned b) {
   if (b == 0x80000000u) b = 0u;  // -0 == +0
@@ -34,6 +46,14 @@ __device__ __forceinline__ uint64_t edge_hash(uint64_t S, unsigned a, unsigned b
   const unsigned lo = a < b ? a : b;
   const unsigned hi = a < b ? b : a;
   return mix64(((uint64_t)lo << 32 | (uint64_t)hi) ^ S);
+}
+
+// The neighbour u of vertex vloc whose edge hash is h (the hash is a
+// bijection of the pair, so it names the edge).
+__device__ __forceinline__ int hash_neighbour(uint64_t h, uint64_t S, unsigned vloc) {
+  const uint64_t pair = unmix64(h) ^ S;
+  const unsigned lo = (unsigned)(pair >> 32), hi = (unsigned)pair;
+  return (int)(lo == vloc ? hi : lo);
 }
 
 // A candidate with its full key; u = -1 is the dummy below every edge.
