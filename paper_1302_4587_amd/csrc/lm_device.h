@@ -53,6 +53,20 @@ __device__ __forceinline__ unsigned wave_incl_max_u32(unsigned x) {
   return x;
 }
 
+// Largest 64-bit value of the wave, returned to every lane.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const unsigned lo = dpp_u32((unsigned)x, 0u, c);
+    const unsigned hi = dpp_u32((unsigned)(x >> 32), 0u, c);
+    const unsigned long long y = ((unsigned long long)hi << 32) | lo;
+    x = y > x ? y : x;
+  }
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_sum(T x);
 template <>
@@ -131,52 +145,6 @@ __device__ __forceinline__ unsigned block_excl_max(unsigned x, unsigned* sm) {
     if (i < wave_id()) pre = max(pre, sm[i]);
   __syncthreads();
   return max(pre, dpp_wave_shr1(incl, 0u));
-}
-
-// Segmented-scan element: f = a segment starts inside, k = running best.
-struct SegKey {
-  unsigned f;
-  Key k;
-};
-
-__device__ __forceinline__ SegKey seg_combine(const SegKey& a, const SegKey& b) {  // a precedes b
-  SegKey r;
-  r.f = a.f | b.f;
-  r.k = b.f ? b.k : key_max(a.k, b.k);
-  return r;
-}
-
-__device__ __forceinline__ SegKey dpp_seg(const SegKey& x, int c) {
-  SegKey y;
-  y.f = dpp_u32(x.f, 0u, c);
-  y.k.w = dpp_u32(x.k.w, 0u, c);
-  y.k.hhi = dpp_u32(x.k.hhi, 0u, c);
-  y.k.hlo = dpp_u32(x.k.hlo, 0u, c);
-  y.k.u = (int)dpp_u32((unsigned)x.k.u, 0xffffffffu, c);
-  return y;
-}
-
-// Exclusive segmented max-scan over the workgroup. A lane whose DPP source is
-// outside the pattern receives the identity (f = 0, empty key), which is
-// neutral for seg_combine.
-__device__ __forceinline__ SegKey block_excl_segscan(SegKey x, SegKey* sm) {
-  SegKey incl = x;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) incl = seg_combine(dpp_seg(incl, c), incl);
-  if (lane_id() == 63) sm[wave_id()] = incl;
-  __syncthreads();
-  SegKey carry;
-  carry.f = 0;
-  carry.k = key_ident();
-  for (int i = 0; i < wave_id(); ++i) carry = seg_combine(carry, sm[i]);
-  __syncthreads();
-  SegKey ex;
-  ex.f = dpp_wave_shr1(incl.f, 0u);
-  ex.k.w = dpp_wave_shr1(incl.k.w, 0u);
-  ex.k.hhi = dpp_wave_shr1(incl.k.hhi, 0u);
-  ex.k.hlo = dpp_wave_shr1(incl.k.hlo, 0u);
-  ex.k.u = (int)dpp_wave_shr1((unsigned)incl.k.u, 0xffffffffu);
-  return seg_combine(carry, ex);
 }
 
 // Smallest index i in [lo, hi) with pred(i) true, assuming pred is monotone

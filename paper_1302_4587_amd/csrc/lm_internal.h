@@ -29,7 +29,11 @@ constexpr int kBlock = 256;            // lanes per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kItems = 8;              // entries per lane per batch
 constexpr int kCap = kBlock * kItems;  // live entries loaded per batch
-constexpr int kWin = kBlock;           // pieces considered per batch (one per lane)
+#ifndef LM_WIN_LANES
+#define LM_WIN_LANES 1
+#endif
+constexpr int kWinLanes = LM_WIN_LANES;     // pieces per lane in a compaction batch
+constexpr int kWin = kBlock * kWinLanes;    // pieces considered per batch
 constexpr int kMaxBlocks = 4096;       // run table capacity
 constexpr int kPlanThreads = 1024;
 constexpr unsigned kDropBit = 0x80000000u;

@@ -440,6 +440,7 @@ struct Carry {
   int is_first;    // it is the segment that contains the range start
 };
 
+constexpr int kPPL = kWinLanes;                  // pieces per lane in a batch's window
 constexpr int kLong = 32;                        // longer pieces are reduced by a whole wave
 constexpr int kTieLanes = 4;                     // more tied pieces per batch: striped tie-break
 constexpr int kLongMax = kCap / (kLong + 1) + 1;  // long pieces per batch at most
@@ -633,10 +634,6 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   const int row_start = k0 + b;
   long long loaded_total = 0;  // lane 0 only
   bool first_batch = true;
-  int4 pf_rec = make_int4(-1, 0, 0, 0);  // prefetched piece of the next window
-  long long pf_gk = -1;
-  int pf_rr = 0;
-  bool pf_ok = false;
   for (;;) {
     const long long pos = sm.pos;
     if (pos >= E1) break;
@@ -653,86 +650,100 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       sm.nt = 0;
       sm.nlong = 0;
     }
-    // ---- 1. window: lane j looks at piece cur_k + j
-    const long long gk = (long long)cur_k + tid;
-    const bool valid = gk < ctl.pieces;
-    int4 rec = make_int4(-1, 0, 0, 0);
-    bool mt = false;
-    if (valid) {
-      if (pf_ok && pf_gk == gk) {  // loaded during the previous batch
-        rec = pf_rec;
-        rr = pf_rr;
-      } else {
+    // ---- 1. window: lane t looks at pieces cur_k + kPPL t + h
+    int4 rec[kPPL];
+    bool mt[kPPL], valid[kPPL];
+    int cov[kPPL], rrh[kPPL];
+    unsigned long long lanesum = 0;
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      const int j = tid * kPPL + h;
+      const long long gk = (long long)cur_k + j;
+      valid[h] = gk < ctl.pieces;
+      rec[h] = make_int4(-1, 0, 0, 0);
+      mt[h] = false;
+      if (valid[h]) {
         const int row = gk < run_hi ? run_rb + (int)(gk - run_lo) : piece_row(a.in, gk, rr, ctl.nruns);
-        rec = a.in.rows[row];
+        rec[h] = a.in.rows[row];
+        if (j == 0) {
+          rec[h].y += cur_o;
+          rec[h].z -= cur_o;
+        }
+        if (!FIRST) mt[h] = (rec[h].w & kHeadBit) ? (rec[h].w & kMatchedBit) != 0 : a.c.state[rec[h].x] != 0;
       }
-      if (tid == 0) {
-        rec.y += cur_o;
-        rec.z -= cur_o;
-      }
-      if (!FIRST) mt = (rec.w & kHeadBit) ? (rec.w & kMatchedBit) != 0 : a.c.state[rec.x] != 0;
+      rrh[h] = rr;
+      cov[h] = valid[h] ? rec[h].z : 0;
+      lanesum += ((unsigned long long)(unsigned)cov[h] << 32) | (mt[h] ? 0u : (unsigned)cov[h]);
     }
-    const long long cov = valid ? rec.z : 0;
     unsigned long long tot;
-    const unsigned long long ex = block_excl_sum_1b<unsigned long long>(
-        ((unsigned long long)cov << 32) | (mt ? 0ull : (unsigned long long)cov), sm.s_scan, tot);
+    const unsigned long long ex = block_excl_sum_1b<unsigned long long>(lanesum, sm.s_scan, tot);
     const long long Rrem = E1 - pos;
-    const long long cpre = (long long)(ex >> 32);  // virtual entries before the piece
-    const long long lpre = (long long)(ex & 0xffffffffull);  // loadable entries before the piece
     // Whole pieces are taken while the range and the load budget last; the
     // last one may be cut. Matched pieces are skipped without loading.
-    int take = 0;
-    if (valid && cpre < Rrem && lpre < kCap) {
-      long long tk = cov < Rrem - cpre ? cov : Rrem - cpre;
-      if (!mt && tk > kCap - lpre) tk = kCap - lpre;
-      take = (int)tk;
-    }
-    const int ldt = mt ? 0 : take;
-    if (take > 0) {
-      const bool next_taken = take == cov && tid + 1 < kWin && gk + 1 < ctl.pieces && cpre + cov < Rrem &&
-                              lpre + (mt ? 0 : cov) < kCap;
-      if (!next_taken) {  // this lane holds the batch's last piece
-        sm.nt = tid + 1;
-        sm.nld = (int)lpre + ldt;
-        sm.last_partial = take < cov;
-        sm.cur_r = rr;
+    long long cp = (long long)(ex >> 32);        // virtual entries before the piece
+    long long lp = (long long)(ex & 0xffffffffull);  // loadable entries before the piece
+    long long cpre[kPPL];
+    int lpre[kPPL], take[kPPL], ldt[kPPL];
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      cpre[h] = cp;
+      lpre[h] = (int)(lp < kCap ? lp : kCap);
+      take[h] = 0;
+      if (valid[h] && cp < Rrem && lp < kCap) {
+        long long tk = cov[h] < Rrem - cp ? (long long)cov[h] : Rrem - cp;
+        if (!mt[h] && tk > kCap - lp) tk = kCap - lp;
+        take[h] = (int)tk;
       }
-      const int g = rec.w & kGraphMask;
-      sm.p_delta[tid] = rec.y - (int)lpre;
-      sm.p_g[tid] = g;
-      sm.p_base[tid] = single ? 0 : a.c.gbase[g];
-      sm.p_vo[tid] = (unsigned short)lpre;
-      sm.p_ld[tid] = (unsigned short)ldt;
-      if (ldt > 0) sm.rowof[lpre] = (unsigned short)tid;
-      if (ldt > kLong) sm.longlist[atomicAdd(&sm.nlong, 1)] = tid;
+      ldt[h] = mt[h] ? 0 : take[h];
+      cp += cov[h];
+      lp += mt[h] ? 0 : cov[h];
     }
-    if (valid) sm.p_v[tid] = rec.x;
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      const int j = tid * kPPL + h;
+      if (take[h] > 0) {
+        bool next_taken;
+        if (h + 1 < kPPL)
+          next_taken = take[h + 1 < kPPL ? h + 1 : h] > 0;
+        else
+          next_taken = take[h] == cov[h] && j + 1 < kWin && (long long)cur_k + j + 1 < ctl.pieces && cp < Rrem &&
+                       lp < kCap;
+        if (!next_taken) {  // this lane holds the batch's last piece
+          sm.nt = j + 1;
+          sm.nld = lpre[h] + ldt[h];
+          sm.last_partial = take[h] < cov[h];
+          sm.cur_r = rrh[h];
+        }
+        const int g = rec[h].w & kGraphMask;
+        sm.p_delta[j] = rec[h].y - lpre[h];
+        sm.p_g[j] = g;
+        sm.p_base[j] = single ? 0 : a.c.gbase[g];
+        sm.p_vo[j] = (unsigned short)lpre[h];
+        sm.p_ld[j] = (unsigned short)ldt[h];
+        if (ldt[h] > 0) sm.rowof[lpre[h]] = (unsigned short)j;
+        if (ldt[h] > kLong) sm.longlist[atomicAdd(&sm.nlong, 1)] = j;
+      }
+      if (valid[h]) sm.p_v[j] = rec[h].x;
+    }
     __syncthreads();
     const int nt = sm.nt;
     if (nt == 0) {  // nothing consumable: the live set is inconsistent; stop, never spin
       if (tid == 0) atomicOr(&a.c.totals->err, kErrInternal);
       break;
     }
-    // prefetch the next batch's window so that its load overlaps this batch
-    {
-      pf_gk = (long long)cur_k + nt - (sm.last_partial ? 1 : 0) + tid;
-      pf_ok = pf_gk < ctl.pieces;
-      if (pf_ok) {
-        int r2 = rr;
-        const int row = pf_gk < run_hi ? run_rb + (int)(pf_gk - run_lo) : piece_row(a.in, pf_gk, r2, ctl.nruns);
-        pf_rec = a.in.rows[row];
-        pf_rr = r2;
-      }
-    }
     const int NLD = sm.nld;
-    const bool mine = tid < nt;
     // ---- 2. vertex continuity; piece of every loaded position (prefix max)
-    bool cont = false;
-    if (mine) {
-      cont = tid == 0 ? (carry.active && carry.v == rec.x) : (sm.p_v[tid - 1] == rec.x);
-      sm.p_cont[tid] = cont ? 1 : 0;
+    bool cont[kPPL];
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      const int j = tid * kPPL + h;
+      cont[h] = false;
+      if (j < nt) {
+        cont[h] = j == 0 ? (carry.active && carry.v == rec[h].x) : (sm.p_v[j - 1] == rec[h].x);
+        sm.p_cont[j] = cont[h] ? 1 : 0;
+      }
+      if (j == nt) sm.next_cont = (valid[h] && sm.p_v[nt - 1] == rec[h].x) ? 1 : 0;
     }
-    if (tid == nt) sm.next_cont = (valid && sm.p_v[nt - 1] == rec.x) ? 1 : 0;
     if (tid == 0 && nt == kWin) sm.next_cont = -1;  // the window ended: unknown, keep the segment open
     {
       const int q0 = tid * kItems;
@@ -816,77 +827,50 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       sm.kpre[0] = 0;
     }
     // ---- 4. best candidate per piece
-    const int my_vo = (int)lpre;
-    int mybase = 0;
-    unsigned long long mySeed = seed0;
-    unsigned myvloc = 0;
-    if (mine) {
-      mybase = single ? 0 : sm.p_base[tid];
-      if (!single) mySeed = a.c.gseed[rec.w & kGraphMask];
-      myvloc = (unsigned)(rec.x - mybase);
-    }
-    unsigned bw = 0u;
-    int bu = -1;
-    bool tie = false;
-    if (mine && ldt <= kLong) {
-      // largest ordered weight, its first neighbour, and whether it repeats;
-      // only a repeated largest weight needs the tie-break hash
-      unsigned m = 0u;
-      int mu = -1, ties = 0;
-#pragma unroll 4
-      for (int i = 0; i < ldt; ++i) {
-        const uint2 e = sm.e_cw[my_vo + i];
-        const bool gt = e.x > m;
-        ties = gt ? 0 : ties + (e.x == m ? 1 : 0);
-        mu = gt ? (int)e.y : mu;
-        m = gt ? e.x : m;
-      }
-      tie = m != 0u && ties > 0;
-      bw = m;
-      bu = mu;
-      sm.p_w[tid] = bw;
-      sm.p_u[tid] = bu;
-      if (tie) sm.p_hash[tid] = 0ull;
-    }
-    if (mine) sm.p_tie[tid] = tie ? 1 : 0;
-    // A repeated largest weight is settled by the tie-break hash. With few
-    // such pieces each lane rescans its own piece; with many (unit weights)
-    // all lanes hash the tied entries of the batch in striped order, keep the
-    // largest hash per piece with an LDS atomic max, and each piece's lane
-    // recovers the neighbour by inverting the hash.
-    const int ntie = __syncthreads_count(tie ? 1 : 0);
-    if (ntie > 0 && ntie <= kTieLanes) {
-      if (tie) {
-        bu = tie_break(sm.e_cw + my_vo, ldt, bw, myvloc, mySeed);
-        sm.p_u[tid] = bu;
-      }
-    } else if (ntie > kTieLanes) {
+    auto seed_of = [&](int h) -> unsigned long long {
+      return single ? seed0 : a.c.gseed[rec[h].w & kGraphMask];
+    };
+    auto vloc_of = [&](int h) -> unsigned {
+      return (unsigned)(rec[h].x - (single ? 0 : sm.p_base[tid * kPPL + h]));
+    };
+    unsigned bw[kPPL];
+    int bu[kPPL];
+    bool tie[kPPL];
+    bool anytie = false;
 #pragma unroll
-      for (int jj = 0; jj < kItems; ++jj) {
-        const int q = tid + kBlock * jj;
-        if (q < NLD) {
-          const int j = sm.rowof[q];
-          if (sm.p_tie[j]) {
-            const uint2 e = sm.e_cw[q];
-            if (e.x == sm.p_w[j]) {
-              const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
-              const uint64_t h = edge_hash(S, (unsigned)(sm.p_v[j] - sm.p_base[j]), e.y);
-              atomicMax(&sm.p_hash[j], (unsigned long long)h);
-            }
-          }
+    for (int h = 0; h < kPPL; ++h) {
+      const int j = tid * kPPL + h;
+      bw[h] = 0u;
+      bu[h] = -1;
+      tie[h] = false;
+      if (j < nt && ldt[h] <= kLong) {
+        // largest ordered weight, its first neighbour, and whether it repeats;
+        // only a repeated largest weight needs the tie-break hash
+        unsigned m = 0u;
+        int mu = -1, ties = 0;
+#pragma unroll 4
+        for (int i = 0; i < ldt[h]; ++i) {
+          const uint2 e = sm.e_cw[lpre[h] + i];
+          const bool gt = e.x > m;
+          ties = gt ? 0 : ties + (e.x == m ? 1 : 0);
+          mu = gt ? (int)e.y : mu;
+          m = gt ? e.x : m;
         }
+        tie[h] = m != 0u && ties > 0;
+        bw[h] = m;
+        bu[h] = mu;
+        sm.p_w[j] = m;
+        sm.p_u[j] = mu;
+        if (tie[h]) sm.p_hash[j] = 0ull;
       }
-      __syncthreads();
-      if (tie) {
-        bu = hash_neighbour(sm.p_hash[tid], mySeed, myvloc);
-        sm.p_u[tid] = bu;
-      }
+      if (j < nt && ldt[h] <= kLong) sm.p_tie[j] = tie[h] ? 1 : 0;  // long pieces: set below
+      anytie = anytie || tie[h];
     }
+    // Long pieces: largest ordered weight only (a wave per piece, or the whole
+    // workgroup when there are fewer long pieces than waves); their winner is
+    // found by the hash pass below like that of a tied short piece.
     const int nlong = sm.nlong;
     if (nlong > 0 && nlong < kWaves) {
-      // few long pieces (a hub row fills most of the batch): the whole
-      // workgroup reduces each one, largest ordered weight first, then the
-      // largest tie-break hash among the entries that reach it
       for (int li = 0; li < nlong; ++li) {
         const int j = sm.longlist[li];
         const int vo = sm.p_vo[j], ld = sm.p_ld[j];
@@ -895,25 +879,16 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         m = (unsigned)__builtin_amdgcn_readlane((int)wave_incl_max_u32(m), 63);
         if (lane == 0) sm.s_lmax[wv] = m;
         __syncthreads();
-        m = max(max(sm.s_lmax[0], sm.s_lmax[1]), max(sm.s_lmax[2], sm.s_lmax[3]));
-        Key k = key_ident();
-        if (m != 0u) {
-          const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
-          const unsigned vloc = (unsigned)(sm.p_v[j] - sm.p_base[j]);
-          for (int i = tid; i < ld; i += kBlock) {
-            const uint2 e = sm.e_cw[vo + i];
-            if (e.x == m) k = key_max(k, full_key(m, (int)e.y, vloc, S));
-          }
-        }
-        k = wave_max_key(k);
-        if (lane == 0) sm.s_lkey[wv] = k;
-        __syncthreads();
         if (tid == 0) {
-          Key best = sm.s_lkey[0];
-          for (int x = 1; x < kWaves; ++x) best = key_max(best, sm.s_lkey[x]);
-          sm.p_w[j] = best.w;
-          sm.p_u[j] = best.u;
+          unsigned mm = 0u;
+#pragma unroll
+          for (int x = 0; x < kWaves; ++x) mm = max(mm, sm.s_lmax[x]);
+          sm.p_w[j] = mm;
+          sm.p_u[j] = -1;
+          sm.p_tie[j] = mm != 0u ? 1 : 0;
+          sm.p_hash[j] = 0ull;
         }
+        __syncthreads();  // s_lmax is rewritten for the next piece
       }
     } else {
       for (int li = wv; li < nlong; li += kWaves) {  // a wave per long piece
@@ -922,27 +897,72 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         unsigned m = 0u;
         for (int i = lane; i < ld; i += 64) m = max(m, sm.e_cw[vo + i].x);
         m = (unsigned)__builtin_amdgcn_readlane((int)wave_incl_max_u32(m), 63);
-        Key k = key_ident();
-        if (m != 0u) {
-          const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
-          const unsigned vloc = (unsigned)(sm.p_v[j] - sm.p_base[j]);
-          for (int i = lane; i < ld; i += 64) {
-            const uint2 e = sm.e_cw[vo + i];
-            if (e.x == m) k = key_max(k, full_key(m, (int)e.y, vloc, S));
-          }
-          k = wave_max_key(k);
-        }
         if (lane == 0) {
-          sm.p_w[j] = k.w;
-          sm.p_u[j] = k.u;
+          sm.p_w[j] = m;
+          sm.p_u[j] = -1;
+          sm.p_tie[j] = m != 0u ? 1 : 0;
+          sm.p_hash[j] = 0ull;
+        }
+      }
+    }
+    // A largest weight that repeats in a short piece, and the largest weight of
+    // every long piece, is settled by the tie-break hash. With only a few tied
+    // short pieces and no long one each lane rescans its own pieces; otherwise
+    // all lanes hash the entries that reach their piece's largest weight in
+    // striped order, keep the largest hash per piece with an LDS atomic max,
+    // and each piece's lane recovers the neighbour by inverting the hash.
+    const int ntie = __syncthreads_count(anytie ? 1 : 0);
+    if (nlong == 0 && ntie > 0 && ntie <= kTieLanes) {
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h)
+        if (tie[h]) {
+          bu[h] = tie_break(sm.e_cw + lpre[h], ldt[h], bw[h], vloc_of(h), seed_of(h));
+          sm.p_u[tid * kPPL + h] = bu[h];
+        }
+    } else if (NLD > 0 && (nlong > 0 || ntie > 0)) {  // (both need loaded entries)
+      // each lane keeps the largest hash of its current piece while its
+      // rounds stay inside that piece (a hub row spans every round) and
+      // flushes it with an LDS atomic max when the piece changes
+      int cur_j = -1;
+      unsigned long long cur_h = 0ull;
+#pragma unroll
+      for (int jj = 0; jj < kItems; ++jj) {
+        const int q = min(tid + kBlock * jj, NLD - 1);
+        const int j = sm.rowof[q];
+        unsigned long long hh = 0ull;
+        if (tid + kBlock * jj < NLD && sm.p_tie[j]) {
+          const uint2 e = sm.e_cw[q];
+          if (e.x == sm.p_w[j]) {
+            const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+            hh = edge_hash(S, (unsigned)(sm.p_v[j] - sm.p_base[j]), e.y);
+          }
+        }
+        if (j != cur_j) {
+          if (cur_h != 0ull) atomicMax(&sm.p_hash[cur_j], cur_h);
+          cur_j = j;
+          cur_h = hh;
+        } else if (hh > cur_h) {
+          cur_h = hh;
+        }
+      }
+      if (__builtin_amdgcn_readfirstlane(cur_j) == __builtin_amdgcn_readlane(cur_j, 63)) {
+        cur_h = wave_max_u64(cur_h);  // the whole wave ends in one piece
+        if (lane == 0 && cur_h != 0ull) atomicMax(&sm.p_hash[cur_j], cur_h);
+      } else if (cur_h != 0ull) {
+        atomicMax(&sm.p_hash[cur_j], cur_h);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h) {
+        const int j = tid * kPPL + h;
+        if (j < nt && sm.p_tie[j]) {
+          if (ldt[h] > kLong) bw[h] = sm.p_w[j];
+          bu[h] = hash_neighbour(sm.p_hash[j], seed_of(h), vloc_of(h));
+          sm.p_u[j] = bu[h];
         }
       }
     }
     __syncthreads();
-    if (mine && ldt > kLong) {
-      bw = sm.p_w[tid];
-      bu = sm.p_u[tid];
-    }
     // ---- 5. vertex segments
     // The segment of piece j closes in this batch when piece j+1 starts another
     // vertex; the batch's last segment closes only when the next piece is known
@@ -950,38 +970,52 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     // piece 0 starts another vertex.
     const bool last_open = sm.last_partial || sm.next_cont != 0;
     const bool old_closes = carry.active && !sm.p_cont[0];
-    bool closes = false, seg_has_carry = false;
-    int seg_head = tid, seg_kept = 0;
-    unsigned sw = bw;
-    int su = bu;
-    if (mine) {
-      closes = (tid + 1 < nt) ? !sm.p_cont[tid + 1] : !last_open;
-      if (cont && (closes || tid == nt - 1)) {
-        // the vertex has several pieces here (its row was cut before): walk back
-        Key k = full_key(bw, bu, myvloc, mySeed);
-        int j = tid;
-        while (sm.p_cont[j]) {
-          if (j == 0) {
-            seg_has_carry = true;
-            break;
+    bool closes[kPPL], shc[kPPL], sfirst[kPPL], emit[kPPL];
+    int shead[kPPL], skept[kPPL];
+    unsigned sw[kPPL];
+    int su[kPPL];
+    unsigned ne = 0;
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      const int j = tid * kPPL + h;
+      closes[h] = false;
+      shc[h] = false;
+      shead[h] = j;
+      skept[h] = 0;
+      sw[h] = bw[h];
+      su[h] = bu[h];
+      if (j < nt) {
+        closes[h] = (j + 1 < nt) ? !sm.p_cont[j + 1] : !last_open;
+        if (cont[h] && (closes[h] || j == nt - 1)) {
+          // the vertex has several pieces here (its row was cut before): walk back
+          const unsigned long long S = seed_of(h);
+          const unsigned vl = vloc_of(h);
+          Key k = full_key(bw[h], bu[h], vl, S);
+          int jb = j;
+          while (sm.p_cont[jb]) {
+            if (jb == 0) {
+              shc[h] = true;
+              break;
+            }
+            --jb;
+            k = key_max(k, full_key(sm.p_w[jb], sm.p_u[jb], vl, S));
           }
-          --j;
-          k = key_max(k, full_key(sm.p_w[j], sm.p_u[j], myvloc, mySeed));
+          if (shc[h]) k = key_max(k, full_key(carry.w, carry.u, vl, S));
+          shead[h] = jb;
+          sw[h] = k.w;
+          su[h] = k.u;
         }
-        if (seg_has_carry) k = key_max(k, full_key(carry.w, carry.u, myvloc, mySeed));
-        seg_head = j;
-        sw = k.w;
-        su = k.u;
+        if (!FIRST)
+          skept[h] = (int)sm.kpre[lpre[h] + ldt[h]] - (int)sm.kpre[sm.p_vo[shead[h]]] + (shc[h] ? carry.kept : 0);
       }
-      if (!FIRST)
-        seg_kept = (int)sm.kpre[my_vo + ldt] - (int)sm.kpre[sm.p_vo[seg_head]] + (seg_has_carry ? carry.kept : 0);
+      sfirst[h] = shc[h] ? carry.is_first != 0 : (first_batch && shead[h] == 0);
+      emit[h] = !FIRST && j < nt && closes[h] && skept[h] > 0;
+      ne += emit[h] ? 1u : 0u;
     }
-    const bool seg_is_first = seg_has_carry ? carry.is_first != 0 : (first_batch && seg_head == 0);
-    const bool emit = !FIRST && mine && closes && seg_kept > 0;
     const bool emit_old = !FIRST && tid == 0 && old_closes && carry.kept > 0;
+    ne += emit_old ? 1u : 0u;
     unsigned epre = 0, etot = 0;
     if (!FIRST) {  // slots of the emitted piece records, in piece order
-      const unsigned ne = (emit ? 1u : 0u) + (emit_old ? 1u : 0u);
       const unsigned inc = wave_incl_sum_u32(ne);
       if (lane == 63) sm.s_emit[wv] = inc;
       __syncthreads();
@@ -999,41 +1033,66 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
                            single ? seed0 : a.c.gseed[carry.g], carry.kept, carry.out_start,
                            emit_old ? slot++ : -1);
     }
-    int seg_start = -1;
-    if (!FIRST && mine && (closes || tid == nt - 1)) {
-      const int bstart = out_base + (int)sm.kpre[sm.p_vo[seg_head]];
-      seg_start = seg_has_carry && carry.out_start >= 0
-                      ? carry.out_start
-                      : (seg_kept > (seg_has_carry ? carry.kept : 0) ? bstart : -1);
-    }
-    if (mine && closes) {
-      close_segment<FIRST>(a, sm, seg_is_first && open_left, rec.x, rec.w & kGraphMask, mybase, sw, su, mySeed,
-                           seg_kept, seg_start, emit ? slot : -1);
+    int sstart[kPPL];
+#pragma unroll
+    for (int h = 0; h < kPPL; ++h) {
+      const int j = tid * kPPL + h;
+      sstart[h] = -1;
+      if (!FIRST && j < nt && (closes[h] || j == nt - 1)) {
+        const int bstart = out_base + (int)sm.kpre[sm.p_vo[shead[h]]];
+        sstart[h] = shc[h] && carry.out_start >= 0 ? carry.out_start
+                                                    : (skept[h] > (shc[h] ? carry.kept : 0) ? bstart : -1);
+      }
+      if (j < nt && closes[h]) {
+        close_segment<FIRST>(a, sm, sfirst[h] && open_left, rec[h].x, rec[h].w & kGraphMask,
+                             single ? 0 : sm.p_base[j], sw[h], su[h], seed_of(h), skept[h], sstart[h],
+                             emit[h] ? slot++ : -1);
+      }
     }
     // ---- 6. carry and advance (lane of the last piece)
-    if (tid == nt - 1) {
+    if (tid == (nt - 1) / kPPL) {
+      const int hl = (nt - 1) - tid * kPPL;
+      int4 rl = rec[0];
+      int takel = take[0], covl = cov[0], skl = skept[0], ssl = sstart[0], rrl = rrh[0];
+      long long cprel = cpre[0];
+      unsigned swl = sw[0];
+      int sul = su[0];
+      bool sfl = sfirst[0];
+#pragma unroll
+      for (int h = 1; h < kPPL; ++h)
+        if (hl == h) {
+          rl = rec[h];
+          takel = take[h];
+          covl = cov[h];
+          skl = skept[h];
+          ssl = sstart[h];
+          rrl = rrh[h];
+          cprel = cpre[h];
+          swl = sw[h];
+          sul = su[h];
+          sfl = sfirst[h];
+        }
       Carry nc;
       nc.active = 0;
-      nc.v = rec.x;
+      nc.v = rl.x;
       if (last_open) {
         nc.active = 1;
-        nc.g = rec.w & kGraphMask;
-        nc.base = mybase;
-        nc.w = sw;
-        nc.u = su;
-        nc.kept = seg_kept;
-        nc.out_start = seg_start;
-        nc.is_first = seg_is_first ? 1 : 0;
+        nc.g = rl.w & kGraphMask;
+        nc.base = single ? 0 : sm.p_base[nt - 1];
+        nc.w = swl;
+        nc.u = sul;
+        nc.kept = skl;
+        nc.out_start = ssl;
+        nc.is_first = sfl ? 1 : 0;
       }
       sm.carry = nc;
       sm.out_cursor = out_base + (int)ktot;
       sm.row_cursor = row_base + (int)etot;
-      const long long consumed = cpre + take;
-      sm.pos = pos + consumed;
+      sm.pos = pos + cprel + takel;
       int nk, no;
-      if (take < cov) {
+      if (takel < covl) {
         nk = cur_k + nt - 1;
-        no = (nt == 1 ? cur_o : 0) + take;
+        no = (nt == 1 ? cur_o : 0) + takel;
       } else {
         nk = cur_k + nt;
         no = 0;
@@ -1041,7 +1100,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       sm.cur_k = nk;
       sm.cur_o = no;
       if (nk >= run_hi && nk < ctl.pieces) {
-        int r2 = rr;
+        int r2 = rrl;
         (void)piece_row(a.in, nk, r2, ctl.nruns);
         sm.cur_r = r2;
         sm.run_rb = a.in.runs[r2].row_begin;
@@ -1114,7 +1173,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
 }
 
 template <bool FIRST>
-__global__ __launch_bounds__(kBlock, 4) void k_stream(StreamArgs a) {
+__global__ __launch_bounds__(kBlock, kWinLanes > 1 ? 3 : 4) void k_stream(StreamArgs a) {
   __shared__ StreamSmem sm;
   __shared__ unsigned s_err;
   if (block_failed(a.c.totals, &s_err)) return;
