@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <deque>
 #include <cstring>
 #include <iterator>
 #include <map>
@@ -27,17 +28,19 @@ namespace lm {
 
 using Clock = std::chrono::steady_clock;
 
-// Capacity of the resident set for an HBM budget: 60 % for the two entry
-// buffers (col + w, 16 B per entry), 40 % for per-vertex state (C 4, state 1,
-// mate 4, two piece buffers of 2 records per vertex 64, row staging 8 B).
-void server_caps(size_t budget, int64_t* n_cap, int64_t* e_cap) {
+// Capacity of the resident set for an HBM budget: 50 % for the two entry
+// buffers (col + w, 16 B per entry), 35 % for per-vertex state (C 4, state 1,
+// mate 4, two piece buffers of 2 records per vertex 64, row staging 8 B) and
+// 15 % for the staging area that receives requests while others compute.
+void server_caps(size_t budget, int64_t* n_cap, int64_t* e_cap, int64_t* stage_cap) {
   const double b = (double)budget;
-  int64_t e = (int64_t)(b * 0.6 / 16.0);
-  int64_t n = (int64_t)(b * 0.4 / 81.0);
+  int64_t e = (int64_t)(b * 0.50 / 16.0);
+  int64_t n = (int64_t)(b * 0.35 / 81.0);
   e = std::min<int64_t>(e, ((int64_t)1 << 31) - 65536 - 1);
   n = std::min<int64_t>(n, (int64_t)1 << 29);
   *e_cap = std::max<int64_t>(e, 0);
   *n_cap = std::max<int64_t>(n, 0);
+  *stage_cap = (int64_t)(b * 0.15) & ~(int64_t)255;
 }
 
 namespace {
@@ -65,9 +68,16 @@ struct BatchedState {
   ServerCore* S = nullptr;
   int dev = 0, num_cus = 1, bpc = 1;
   lm_tuning tun{};
-  hipStream_t s = nullptr;
+  hipStream_t s = nullptr;   // phase launches and admission
+  hipStream_t cs = nullptr;  // host-to-device staging of queued requests
   Pool pool;
-  int64_t n_cap = 0, e_cap = 0, rows_cap = 0;
+  int64_t n_cap = 0, e_cap = 0, rows_cap = 0, stage_cap = 0;
+  DevBuf stage;
+  // staged requests in arrival order and their byte ranges in `stage` (a ring)
+  std::deque<std::shared_ptr<Request>> staged;
+  std::deque<std::pair<int64_t, int64_t>> stage_ranges;
+  size_t stage_release = 0;  // ranges freed at the next sync (admitted requests)
+  std::vector<hipEvent_t> free_events;
   int s_cap = 0;
   DevBuf C, state, mate, rows[2], ecol[2], ew[2], runs[2], epre[2], rpre[2];
   DevBuf ctl, epre_t, rpre_t, parts, bstat, mcount, gbase, gseed, gphase, totals, st_rp, st_vo, st_slot, st_init;
@@ -88,6 +98,8 @@ struct BatchedState {
   int resident = 0;
   int pcap = 1, pmcap = 1;
 
+  bool stage_alloc(int64_t bytes, int64_t* off);
+  hipEvent_t take_event();
   lm_status init(ServerCore* core);
   void shutdown();
   Common common() const;
@@ -124,6 +136,45 @@ static void vgive(std::map<int64_t, int64_t>& fr, int64_t at, int64_t len) {
   fr[at] = len;
 }
 
+// Ring allocation in arrival order; ranges are released in the same order.
+bool BatchedState::stage_alloc(int64_t bytes, int64_t* off) {
+  if (bytes > stage_cap) return false;
+  int64_t at;
+  if (stage_ranges.empty()) {
+    at = 0;
+  } else {
+    const int64_t first = stage_ranges.front().first;
+    const int64_t end = stage_ranges.back().first + stage_ranges.back().second;
+    if (end > first) {  // not wrapped: free space is [end, cap) and [0, first)
+      if (end + bytes <= stage_cap)
+        at = end;
+      else if (bytes <= first)
+        at = 0;
+      else
+        return false;
+    } else {  // wrapped: free space is [end, first)
+      if (end + bytes <= first)
+        at = end;
+      else
+        return false;
+    }
+  }
+  stage_ranges.push_back({at, bytes});
+  *off = at;
+  return true;
+}
+
+hipEvent_t BatchedState::take_event() {
+  if (!free_events.empty()) {
+    hipEvent_t e = free_events.back();
+    free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
 lm_status BatchedState::init(ServerCore* core) {
   S = core;
   Solver& sv = solver_of(core->ctx);
@@ -133,7 +184,8 @@ lm_status BatchedState::init(ServerCore* core) {
   tun = sv.tun;
   if (hipSetDevice(dev) != hipSuccess) return LM_EDEVICE;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return LM_EDEVICE;
-  server_caps(core->opts.hbm_budget_bytes, &n_cap, &e_cap);
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LM_EDEVICE;
+  server_caps(core->opts.hbm_budget_bytes, &n_cap, &e_cap, &stage_cap);
   s_cap = std::max(2, core->opts.max_resident);
   rows_cap = 2 * n_cap + 2 * kMaxBlocks + 16;
   pool.budget = core->opts.hbm_budget_bytes + ((size_t)64 << 20);
@@ -170,6 +222,7 @@ lm_status BatchedState::init(ServerCore* core) {
   RES(st_vo, ((size_t)s_cap + 1) * 8);
   RES(st_slot, (size_t)s_cap * 4);
   RES(st_init, (size_t)s_cap * sizeof(SlotInit));
+  RES(stage, (size_t)std::max<int64_t>(stage_cap, 256));
 #undef RES
   if (hipHostMalloc((void**)&h_ctl, 3 * sizeof(Ctl)) != hipSuccess ||
       hipHostMalloc((void**)&h_tot, sizeof(Totals)) != hipSuccess ||
@@ -187,7 +240,13 @@ lm_status BatchedState::init(ServerCore* core) {
 }
 
 void BatchedState::shutdown() {
+  if (cs) (void)hipStreamSynchronize(cs);
   if (s) (void)hipStreamSynchronize(s);
+  for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+  free_events.clear();
+  pool.release(stage);
+  if (cs) (void)hipStreamDestroy(cs);
+  cs = nullptr;
   DevBuf* all[] = {&C,       &state,   &mate,    &rows[0], &rows[1], &ecol[0], &ecol[1], &ew[0],  &ew[1],
                    &runs[0], &runs[1], &epre[0], &epre[1], &rpre[0], &rpre[1], &ctl,     &epre_t, &rpre_t,
                    &parts,   &bstat,   &mcount,  &gbase,   &gseed,   &gphase,  &totals,  &st_rp,  &st_vo,
@@ -251,12 +310,16 @@ lm_status BatchedState::admit(std::vector<std::shared_ptr<Request>>& group, int6
   };
   for (int i = 0; i < G; ++i) {
     Request& r = *group[(size_t)i];
-    hipError_t e = hipMemcpyAsync(drp + xo, r.h_rp, (size_t)(r.n + 1) * 8, hipMemcpyHostToDevice, s);
+    // the request's graph is already in the staging area (copy stream):
+    // wait for that copy, then move it into place on the device
+    const char* src = (const char*)stage.p + r.stage_off;
+    hipError_t e = hipStreamWaitEvent(s, r.stage_ev, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(drp + xo, src, (size_t)(r.n + 1) * 8, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = launch_add_i64(drp + xo, r.n + 1, ebase + eo, s);
     if (e == hipSuccess && r.nnz > 0)
-      e = hipMemcpyAsync(dcol + ebase + eo, r.h_col, (size_t)r.nnz * 4, hipMemcpyHostToDevice, s);
+      e = hipMemcpyAsync(dcol + ebase + eo, src + r.off_col, (size_t)r.nnz * 4, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && r.nnz > 0)
-      e = hipMemcpyAsync(dw + ebase + eo, r.h_w, (size_t)r.nnz * 4, hipMemcpyHostToDevice, s);
+      e = hipMemcpyAsync(dw + ebase + eo, src + r.off_w, (size_t)r.nnz * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return fail(e);
     h_vo[i] = xo;
     h_slot[i] = r.slot;
@@ -455,6 +518,8 @@ lm_status BatchedState::sync_and_retire() {
     vgive(free_v, r->vbase, r->n);
     n_res -= r->n;
     --resident;
+    if (r->stage_ev) free_events.push_back(r->stage_ev);
+    r->stage_ev = nullptr;
     S->finish(r, st);
   }
   if (resident == 0) {
@@ -471,6 +536,9 @@ lm_status BatchedState::sync_and_retire() {
 }
 
 void BatchedState::fail_all(lm_status st) {
+  (void)hipStreamSynchronize(cs);
+  (void)hipStreamSynchronize(s);
+  (void)hipGetLastError();
   for (int sl = 0; sl < s_cap; ++sl) {
     std::shared_ptr<Request> r = slot_req[(size_t)sl];
     if (!r) continue;
@@ -479,10 +547,24 @@ void BatchedState::fail_all(lm_status st) {
     vgive(free_v, r->vbase, r->n);
     n_res -= r->n;
     --resident;
+    if (r->stage_ev) free_events.push_back(r->stage_ev);
+    r->stage_ev = nullptr;
     S->finish(r, st);
   }
-  (void)hipStreamSynchronize(s);
-  (void)hipGetLastError();
+  // staged requests that were not admitted yet fail too (their copies may
+  // have failed); the staging area starts over
+  for (auto& r : staged) {
+    if (r->stage_ev) free_events.push_back(r->stage_ev);
+    r->stage_ev = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->running[r->ticket] = r;
+    }
+    S->finish(r, st);
+  }
+  staged.clear();
+  stage_ranges.clear();
+  stage_release = 0;
   reset_live();
 }
 
@@ -491,15 +573,41 @@ static void batch_loop(ServerCore* S) {
   (void)hipSetDevice(B.dev);
   const int k = std::max(1, S->opts.phases_per_step);
   for (;;) {
-    std::vector<std::shared_ptr<Request>> group;
-    int64_t v0 = -1;
+    std::vector<std::shared_ptr<Request>> fresh;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (B.resident == 0)
+      if (B.resident == 0 && B.staged.empty())
         S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
-      if (S->stopping && S->queue.empty() && B.resident == 0) return;
-      // admit in arrival order while slots, one contiguous vertex range, the
-      // entry buffer and the piece buffer have room
+      if (S->stopping && S->queue.empty() && B.staged.empty() && B.resident == 0) return;
+      // start the host-to-device copies of queued requests while the staging
+      // area has room; they overlap the phases of the resident graphs
+      while (!S->queue.empty()) {
+        auto& r = S->queue.front();
+        int64_t off = 0;
+        if (!B.stage_alloc((int64_t)r->block_used, &off)) break;
+        r->stage_off = off;
+        fresh.push_back(r);
+        B.staged.push_back(r);
+        S->queue.pop_front();
+      }
+    }
+    lm_status st = LM_OK;
+    for (auto& r : fresh) {
+      r->stage_ev = B.take_event();
+      if (!r->stage_ev ||
+          hipMemcpyAsync((char*)B.stage.p + r->stage_off, r->block, r->block_used, hipMemcpyHostToDevice, B.cs) !=
+              hipSuccess ||
+          hipEventRecord(r->stage_ev, B.cs) != hipSuccess) {
+        (void)hipGetLastError();
+        st = LM_EDEVICE;
+      }
+    }
+    // admit staged requests in arrival order once their copy has landed (the
+    // first one regardless when nothing is resident), while slots, one
+    // contiguous vertex range, the entry buffer and the piece buffer have room
+    std::vector<std::shared_ptr<Request>> group;
+    int64_t v0 = -1;
+    if (st == LM_OK) {
       int64_t best_at = -1, best_len = 0;
       for (auto& fr : B.free_v)
         if (fr.second > best_len) {
@@ -507,22 +615,29 @@ static void batch_loop(ServerCore* S) {
           best_len = fr.second;
         }
       int64_t nsum = 0, esum = 0;
-      while (!S->queue.empty() && (int)group.size() < (int)B.free_slots.size()) {
-        auto& r = S->queue.front();
+      while (!B.staged.empty() && group.size() < B.free_slots.size()) {
+        auto& r = B.staged.front();
+        const hipError_t q = hipEventQuery(r->stage_ev);
+        if (q != hipSuccess) (void)hipGetLastError();  // not ready yet
+        if (q != hipSuccess && !(B.resident == 0 && group.empty())) break;
         if (r->n > 0 && nsum + r->n > best_len) break;
         if (B.phys_end + esum + r->nnz > B.e_cap) break;
         if (B.rows_end + nsum + r->n > B.rows_cap) break;
         nsum += r->n;
         esum += r->nnz;
-        r->t_admit = Clock::now();
-        S->running[r->ticket] = r;
         group.push_back(r);
-        S->queue.pop_front();
+        B.staged.pop_front();
       }
-      if (!group.empty()) v0 = nsum > 0 ? vtake_at(B.free_v, best_at, nsum) : 0;
+      if (!group.empty()) {
+        v0 = nsum > 0 ? vtake_at(B.free_v, best_at, nsum) : 0;
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto& r : group) {
+          r->t_admit = Clock::now();
+          S->running[r->ticket] = r;
+        }
+      }
     }
-    lm_status st = LM_OK;
-    if (!group.empty()) {
+    if (st == LM_OK && !group.empty()) {
       for (auto& r : group) {
         r->slot = B.free_slots.back();
         B.free_slots.pop_back();
@@ -530,11 +645,18 @@ static void batch_loop(ServerCore* S) {
         B.n_res += r->n;
         ++B.resident;
       }
+      B.stage_release += group.size();
       st = B.admit(group, v0);
     }
     if (st == LM_OK && B.resident > 0) st = B.step(k);
-    if (st == LM_OK && B.resident > 0) st = B.sync_and_retire();
-    if (st != LM_OK) B.fail_all(st);
+    if (st == LM_OK && (B.resident > 0 || B.stage_release > 0)) st = B.sync_and_retire();
+    if (st != LM_OK) {
+      B.fail_all(st);
+    } else {
+      // the admitted requests' staging ranges are free once the stream has
+      // passed their device-to-device copies (sync_and_retire waited for it)
+      for (; B.stage_release > 0; --B.stage_release) B.stage_ranges.pop_front();
+    }
   }
 }
 

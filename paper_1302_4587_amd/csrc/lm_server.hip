@@ -242,9 +242,11 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
   const size_t fp = request_footprint(g->n, g->nnz);
   if (fp > S.opts.hbm_budget_bytes) return LM_ETOOBIG;
   if (S.opts.mode == LM_SERVE_BATCHED) {
-    int64_t ncap = 0, ecap = 0;
-    server_caps(S.opts.hbm_budget_bytes, &ncap, &ecap);
-    if (g->n > ncap || g->nnz > ecap) return LM_ETOOBIG;
+    int64_t ncap = 0, ecap = 0, scap = 0;
+    server_caps(S.opts.hbm_budget_bytes, &ncap, &ecap, &scap);
+    const int64_t staged = (int64_t)(((size_t)(g->n + 1) * 8 + 255) & ~(size_t)255) +
+                           2 * (int64_t)(((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 255) & ~(size_t)255);
+    if (g->n > ncap || g->nnz > ecap || staged > scap) return LM_ETOOBIG;
   }
   const lm_status qc = quick_check(g);
   if (qc != LM_OK) return qc;
@@ -262,6 +264,9 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
   r->h_rp = (int64_t*)r->block;
   r->h_col = (int32_t*)((char*)r->block + b_rp);
   r->h_w = (float*)((char*)r->block + b_rp + b_e);
+  r->off_col = b_rp;
+  r->off_w = b_rp + b_e;
+  r->block_used = b_rp + 2 * b_e;
   parallel_copy(r->h_rp, g->row_ptr, (size_t)(g->n + 1) * 8);
   if (g->nnz > 0) {
     parallel_copy(r->h_col, g->col, (size_t)g->nnz * 4);

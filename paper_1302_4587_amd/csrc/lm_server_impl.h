@@ -51,6 +51,11 @@ struct Request {
   int slot = -1;        // graph index in the resident tables
   int64_t vbase = 0;    // first vertex of the request in the server's vertex space
   int first_phase = 0;  // server phase in which the request was injected
+  // layout of the pinned block: row_ptr at 0, col at off_col, w at off_w
+  size_t off_col = 0, off_w = 0, block_used = 0;
+  // staging copy on the device (batched mode)
+  int64_t stage_off = -1;
+  hipEvent_t stage_ev = nullptr;
   ~Request();
 };
 
@@ -77,9 +82,10 @@ inline size_t request_footprint(int64_t n, int64_t nnz) {
   return (size_t)n * (4 + 1 + 4 + 2 * 16) + (size_t)nnz * (2 * 8 + 8) + 4096;
 }
 
-// Resident-set capacity (vertices, entries) of the batched server for an HBM
-// budget; a request larger than either can never be admitted.
-void server_caps(size_t budget, int64_t* n_cap, int64_t* e_cap);
+// Resident-set capacity of the batched server for an HBM budget: vertices,
+// entries and bytes of the device staging area for incoming requests; a
+// request larger than any of them can never be admitted.
+void server_caps(size_t budget, int64_t* n_cap, int64_t* e_cap, int64_t* stage_cap);
 
 lm_status start_batched(ServerCore* s);
 void stop_batched(ServerCore* s);
