@@ -297,24 +297,29 @@ def bench_serve(ctx, rates, requests, pool=48, seed=1):
         for name, mode in (("batched", lm.LM_SERVE_BATCHED), ("fifo", lm.LM_SERVE_FIFO)):
             tickets = [None] * requests
             with lm.Server(ctx, hbm_budget_bytes=64 << 30, max_resident=256, mode=mode) as srv:
+                sub_s = []
+
                 def submitter(part, parts):
                     for i in range(part, requests, parts):
                         dt = arr[i] - (time.perf_counter() - t_start)
                         if dt > 0:
                             time.sleep(dt)
                         g = graphs[i % pool]
+                        t_sub = time.perf_counter()
                         tickets[i] = srv.submit(g.row_ptr, g.col, g.w, seed=1)
+                        sub_s.append(time.perf_counter() - t_sub)
 
                 t_start = time.perf_counter()
                 ths = [threading.Thread(target=submitter, args=(p, 4)) for p in range(4)]
                 for th in ths:
                     th.start()
-                lat, edges, bad = [], 0, 0
+                lat, qms, edges, bad = [], [], 0, 0
                 for i in range(requests):
                     while tickets[i] is None:
                         time.sleep(0.0002)
                     mate, info = srv.wait(tickets[i], -1)
                     lat.append(info["latency_ms"])
+                    qms.append(info["queue_ms"])
                     g = graphs[i % pool]
                     edges += g.nnz // 2
                     k = i % pool
@@ -326,6 +331,8 @@ def bench_serve(ctx, rates, requests, pool=48, seed=1):
                 for th in ths:
                     th.join()
             point[name] = {"p50_ms": round(_percentile(lat, 50), 3), "p99_ms": round(_percentile(lat, 99), 3),
+                           "queue_p50_ms": round(_percentile(qms, 50), 3), "queue_p99_ms": round(_percentile(qms, 99), 3),
+                           "submit_ms_mean": round(1e3 * sum(sub_s) / max(len(sub_s), 1), 3),
                            "edges_per_s": round(edges / makespan, 1), "requests_per_s": round(requests / makespan, 2),
                            "mismatches": bad}
             print(f"bench: serve rate={rate} {name}: {point[name]}", file=sys.stderr, flush=True)

@@ -29,11 +29,7 @@ constexpr int kBlock = 256;            // lanes per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kItems = 8;              // entries per lane per batch
 constexpr int kCap = kBlock * kItems;  // live entries loaded per batch
-#ifndef LM_WIN_LANES
-#define LM_WIN_LANES 1
-#endif
-constexpr int kWinLanes = LM_WIN_LANES;     // pieces per lane in a compaction batch
-constexpr int kWin = kBlock * kWinLanes;    // pieces considered per batch
+constexpr int kWinLanes = 1;                // pieces per lane in a compaction batch
 constexpr int kMaxBlocks = 4096;       // run table capacity
 constexpr int kPlanThreads = 1024;
 constexpr unsigned kDropBit = 0x80000000u;
@@ -211,7 +207,7 @@ hipError_t launch_plan(const PlanArgs& a, hipStream_t s);
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s);
 hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s);
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s);
-int max_blocks_per_cu_stream();
+int max_blocks_per_cu_stream(bool first);
 
 uint64_t premix_seed(uint64_t seed);
 

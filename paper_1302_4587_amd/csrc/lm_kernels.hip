@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
 // ---------------------------------------------------------------- stream
 
 // Compaction (and first argmax) over one virtual range [E0, E1) of the live
-// set, in batches of at most kWin pieces and kCap loaded entries:
+// set, in batches of at most kBlock * stream_ppl pieces and kCap loaded entries:
 //   1. lane j takes piece cur_k + j; a prefix scan decides which pieces fit;
 //   2. continuity flags (a piece continuing the previous piece's vertex) and,
 //      for every loaded position, the piece it belongs to;
@@ -440,21 +440,21 @@ struct Carry {
   int is_first;    // it is the segment that contains the range start
 };
 
-constexpr int kPPL = kWinLanes;                  // pieces per lane in a batch's window
 constexpr int kLong = 32;                        // longer pieces are reduced by a whole wave
 constexpr int kTieLanes = 4;                     // more tied pieces per batch: striped tie-break
 constexpr int kLongMax = kCap / (kLong + 1) + 1;  // long pieces per batch at most
 
+template <int W>  // pieces in a batch window
 struct StreamSmem {
-  int p_v[kWin];
-  int p_delta[kWin];            // entry-buffer offset minus batch position of the piece's first entry
-  int p_g[kWin];
-  int p_base[kWin];             // first vertex of the piece's graph
-  unsigned short p_vo[kWin];    // batch position of the piece's first loaded entry
-  unsigned short p_ld[kWin];    // loaded entries of the piece
-  unsigned p_w[kWin];           // best ordered weight of the piece (0 = none)
-  int p_u[kWin];                // best neighbour of the piece (local id) or -1
-  unsigned char p_cont[kWin];   // the piece continues the previous piece's vertex
+  int p_v[W];
+  int p_delta[W];            // entry-buffer offset minus batch position of the piece's first entry
+  int p_g[W];
+  int p_base[W];             // first vertex of the piece's graph
+  unsigned short p_vo[W];    // batch position of the piece's first loaded entry
+  unsigned short p_ld[W];    // loaded entries of the piece
+  unsigned p_w[W];           // best ordered weight of the piece (0 = none)
+  int p_u[W];                // best neighbour of the piece (local id) or -1
+  unsigned char p_cont[W];   // the piece continues the previous piece's vertex
   unsigned short rowof[kCap];   // piece of every loaded position
   unsigned short kpre[kCap + 2];  // survivors before every loaded position; [NLD] = total
   uint2 e_cw[kCap];             // {ordered weight or 0 when dropped, local neighbour id}
@@ -462,8 +462,8 @@ struct StreamSmem {
   unsigned s_max[kWaves];
   unsigned s_cnt[kItems * kWaves];
   unsigned s_emit[kWaves];
-  unsigned long long p_hash[kWin];  // largest tie-break hash per tied piece
-  unsigned char p_tie[kWin];        // the piece's largest weight repeats
+  unsigned long long p_hash[W];  // largest tie-break hash per tied piece
+  unsigned char p_tie[W];        // the piece's largest weight repeats
   unsigned s_lmax[kWaves];
   Key s_lkey[kWaves];
   int longlist[kLongMax];
@@ -534,8 +534,8 @@ __device__ __forceinline__ int tie_break(const uint2* e, int n, unsigned m, unsi
   return ub;
 }
 
-template <bool FIRST>
-__device__ __forceinline__ void close_segment(const StreamArgs& a, StreamSmem& sm, bool cut_left, int v, int g,
+template <bool FIRST, typename Smem>
+__device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, bool cut_left, int v, int g,
                                               int base, unsigned w, int u, unsigned long long S, int kept,
                                               int start, int slot) {
   if (cut_left) {  // the row began in the previous range: the plan kernel merges the parts
@@ -558,9 +558,18 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, StreamSmem& s
   if (!FIRST && slot >= 0) a.rows_out[slot] = make_int4(v, start, kept, (g & kGraphMask) | kHeadBit);
 }
 
+// The first argmax looks at one piece per lane: every piece is loaded and
+// rows average ~10 entries, so the entry budget fills first. The compaction
+// skips matched rows (most rows in early phases) and rows shrink, so it
+// looks at kWinLanes pieces per lane.
 template <bool FIRST>
-__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem& sm,
+constexpr int stream_ppl() { return FIRST ? 1 : kWinLanes; }
+
+template <bool FIRST>
+__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * stream_ppl<FIRST>()>& sm,
                              unsigned long long seed0) {
+  constexpr int kPPL = stream_ppl<FIRST>();
+  constexpr int kW = kBlock * kPPL;  // pieces in a batch window
   const int tid = threadIdx.x;
   const int lane = lane_id(), wv = wave_id();
   const bool single = a.c.graphs == 1;
@@ -706,7 +715,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         if (h + 1 < kPPL)
           next_taken = take[h + 1 < kPPL ? h + 1 : h] > 0;
         else
-          next_taken = take[h] == cov[h] && j + 1 < kWin && (long long)cur_k + j + 1 < ctl.pieces && cp < Rrem &&
+          next_taken = take[h] == cov[h] && j + 1 < kW && (long long)cur_k + j + 1 < ctl.pieces && cp < Rrem &&
                        lp < kCap;
         if (!next_taken) {  // this lane holds the batch's last piece
           sm.nt = j + 1;
@@ -744,7 +753,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       }
       if (j == nt) sm.next_cont = (valid[h] && sm.p_v[nt - 1] == rec[h].x) ? 1 : 0;
     }
-    if (tid == 0 && nt == kWin) sm.next_cont = -1;  // the window ended: unknown, keep the segment open
+    if (tid == 0 && nt == kW) sm.next_cont = -1;  // the window ended: unknown, keep the segment open
     {
       const int q0 = tid * kItems;
       unsigned runv = 0, vals[kItems];
@@ -1173,8 +1182,8 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
 }
 
 template <bool FIRST>
-__global__ __launch_bounds__(kBlock, kWinLanes > 1 ? 3 : 4) void k_stream(StreamArgs a) {
-  __shared__ StreamSmem sm;
+__global__ __launch_bounds__(kBlock, stream_ppl<FIRST>() > 1 ? 3 : 4) void k_stream(StreamArgs a) {
+  __shared__ StreamSmem<kBlock * stream_ppl<FIRST>()> sm;
   __shared__ unsigned s_err;
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
@@ -1226,9 +1235,11 @@ hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-int max_blocks_per_cu_stream() {
+int max_blocks_per_cu_stream(bool first) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false>, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  const hipError_t e = first ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<true>, kBlock, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false>, kBlock, 0);
+  if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }
 

@@ -50,7 +50,8 @@ struct Solver {
   hipStream_t own = nullptr;
   Pool pool;
   lm_tuning tun{};
-  int bpc_stream = 1;
+  int bpc_stream = 1;  // resident compaction workgroups per CU
+  int bpc_first = 1;   // resident first-argmax workgroups per CU
   bool busy_server = false;
   int last_phases = 0;
 

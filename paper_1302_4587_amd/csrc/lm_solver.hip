@@ -141,7 +141,8 @@ lm_status Solver::init_device(int device, size_t budget) {
   if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreateWithFlags(&e_order, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
-  bpc_stream = max_blocks_per_cu_stream();
+  bpc_stream = max_blocks_per_cu_stream(false);
+  bpc_first = max_blocks_per_cu_stream(true);
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = bpc_stream;
   tun.phases_per_sync = 4;
@@ -212,6 +213,8 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   } while (0)
 
   const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_stream))));
+  // the first argmax keeps a smaller window and fits more workgroups per CU
+  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, bpc_first)));
   const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
   Ctl* dctl = (Ctl*)ctl.p;
   Totals* dtot = (Totals*)totals.p;
@@ -291,6 +294,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ENQ(mark_end());
     PlanArgs pa = plan_base();
     pa.mode = kPlanPrefix;
+    pa.pcap = pcap_first;
     pa.ctl_prev = nullptr;
     pa.runs_new = (const Run*)runs[0].p;
     pa.nruns_new = pi;
@@ -306,7 +310,8 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     sa.in = live(1);
     sa.parts = (Part*)parts.p;
     sa.bstat = (BlockStat*)bstat.p;
-    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, p.nnz / std::max(kCap, tun.block_entries) + 1));
+    const int gx =
+        (int)std::max<int64_t>(1, std::min<int64_t>(pcap_first, p.nnz / std::max(kCap, tun.block_entries) + 1));
     ENQ(mark_begin(LM_K_ARGMAX));
     ENQ(launch_first_argmax(sa, gx, s));
     ENQ(mark_end());
