@@ -426,7 +426,7 @@ lm_status BatchedState::step(int k) {
     ma.in = in;
     ma.mcount = (int*)mcount.p;
     ma.census = 0;
-    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, pieces_now / kCap + 1));
+    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, pieces_now / kMutualRound + 1));
     e = launch_mutual(ma, gm, s);
     if (e != hipSuccess) break;
     const int lo = t & 1;
@@ -468,7 +468,7 @@ lm_status BatchedState::step(int k) {
     ma.in = live(t);
     ma.mcount = (int*)mcount.p;
     ma.census = 1;
-    e = launch_mutual(ma, (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, pieces_now / kCap + 1)), s);
+    e = launch_mutual(ma, (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, pieces_now / kMutualRound + 1)), s);
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();

@@ -29,7 +29,8 @@ constexpr int kBlock = 256;            // lanes per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kItems = 8;              // entries per lane per batch
 constexpr int kCap = kBlock * kItems;  // live entries loaded per batch
-constexpr int kWinLanes = 1;                // pieces per lane in a compaction batch
+constexpr int kLatePPL = 2;                 // pieces per lane in compactions after the first
+constexpr int kMutualRound = kBlock * 4;    // pieces per mutual-check round of a workgroup
 constexpr int kMaxBlocks = 4096;       // run table capacity
 constexpr int kPlanThreads = 1024;
 constexpr unsigned kDropBit = 0x80000000u;
@@ -87,6 +88,21 @@ struct Totals {
   int t;    // current phase (1-based): read by the mutual check, advanced by the plan kernel
   int pad;
 };
+
+// What the host loop needs after each plan, written by the plan kernel into
+// mapped pinned host memory: the host reads it once an event recorded after
+// that plan has completed, with no copy on the stream. Slot R_t & (kMirrorSlots - 1).
+struct PhaseMirror {
+  long long L;                 // live entries of the live set just planned
+  unsigned long long matched;  // matched entries so far (both directions)
+  int pieces;                  // its pieces
+  int t;                       // its index t (R_t)
+  unsigned gen;                // solve that wrote the record
+  unsigned err;                // error flags so far
+  int last_nonempty;           // last phase that had live rows
+  int pad;
+};
+constexpr int kMirrorSlots = 64;
 
 enum : unsigned {
   kErrRowPtr = 1u,
@@ -157,10 +173,13 @@ struct PlanArgs {
   Ctl* ctl_new;
   int pcap, pmcap;       // workgroup caps for the next phase
   int min_per_block;     // virtual entries per compaction workgroup at least
+  int pieces_per_block;  // pieces per compaction workgroup at least (0: no bound)
   // log
   const int* mcount;
   LogRec* log;
   int log_cap;
+  PhaseMirror* mirror;  // optional (kPlanPrefix): record of the live set just planned
+  unsigned gen;
 };
 // kPlanLog writes the log record of the phase totals->t; kPlanTick then
 // advances totals->t (after the compaction of that phase).
@@ -205,9 +224,10 @@ hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s);
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s);
-hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s);
+hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false);
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s);
-int max_blocks_per_cu_stream(bool first);
+enum class StreamKind { kFirst, kCompact, kLateCompact };
+int max_blocks_per_cu_stream(StreamKind kind);
 
 uint64_t premix_seed(uint64_t seed);
 

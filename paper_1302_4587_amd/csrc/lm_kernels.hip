@@ -12,6 +12,7 @@
 // The live-set layout (pieces grouped into runs) is described in
 // lm_internal.h.
 #include <algorithm>
+#include <climits>
 
 #include "lm_device.h"
 #include "lm_internal.h"
@@ -292,9 +293,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
       c.nruns = nr;
       c.pieces = tr;
       c.heads = tr - s_extra;
+      // enough workgroups that each one sees a few full batches at most:
+      // short rows fill a batch's piece window before its entry budget
       long long P = (te + a.min_per_block - 1) / a.min_per_block;
+      if (a.pieces_per_block > 0) P = std::max<long long>(P, ((long long)tr + a.pieces_per_block - 1) / a.pieces_per_block);
       c.P = (int)std::max<long long>(te > 0 ? 1 : 0, std::min<long long>(P, a.pcap));
-      long long Pm = ((long long)tr + kCap - 1) / kCap;
+      long long Pm = ((long long)tr + kMutualRound - 1) / kMutualRound;
       c.Pm = (int)std::max<long long>(tr > 0 ? 1 : 0, std::min<long long>(Pm, a.pmcap));
       c.pad = 0;
       *a.ctl_new = c;
@@ -325,7 +329,55 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
       a.c.totals->matched += (unsigned long long)s_red[0];
     }
   }
+  if (a.mirror && (a.mode & kPlanPrefix) && tid == 0) {
+    PhaseMirror m;
+    m.L = a.ctl_new->L;
+    m.matched = a.c.totals->matched;
+    m.pieces = a.ctl_new->pieces;
+    m.t = a.c.totals->t + ((a.mode & kPlanTick) ? 1 : 0);  // the live set for the next phase
+    m.gen = a.gen;
+    m.err = a.c.totals->err;
+    m.last_nonempty = a.c.totals->last_nonempty;
+    m.pad = 0;
+    a.mirror[m.t & (kMirrorSlots - 1)] = m;
+  }
   if ((a.mode & kPlanTick) && tid == 0) a.c.totals->t += 1;
+}
+
+// ---------------------------------------------------------------- run lookup
+
+// rpre[c0 .. c0 + kBlock] and the first rows of runs c0 .. c0 + kBlock - 1,
+// copied to LDS so that lanes find the run of a piece by a binary search in
+// LDS instead of walking the run table in global memory (late live sets have
+// many short runs).
+struct RunCache {
+  int rp[kBlock + 1];
+  int rb[kBlock];
+  int c0;
+};
+
+// Every lane of the workgroup; the caller synchronises before the first lookup.
+__device__ __forceinline__ void run_cache_fill(const LiveSet& in, int nruns, int c0, RunCache& rc) {
+  const int i = threadIdx.x;
+  const int r = c0 + i;
+  rc.rp[i] = r <= nruns ? in.rpre[r] : INT_MAX;
+  rc.rb[i] = r < nruns ? in.runs[r].row_begin : 0;
+  if (i == 0) {
+    rc.rp[kBlock] = c0 + kBlock <= nruns ? in.rpre[c0 + kBlock] : INT_MAX;
+    rc.c0 = c0;
+  }
+}
+
+// Run r and row record of piece k when the cached runs hold it.
+__device__ __forceinline__ bool run_cache_find(const RunCache& rc, long long k, int& r, int& row) {
+  if (k < rc.rp[0] || k >= rc.rp[kBlock]) return false;
+  int lo = 0;  // largest lo with rp[lo] <= k; then rp[lo + 1] > k, so run lo holds k
+#pragma unroll
+  for (int step = kBlock / 2; step > 0; step >>= 1)
+    if (rc.rp[lo + step] <= k) lo += step;
+  r = rc.c0 + lo;
+  row = rc.rb[lo] + (int)(k - rc.rp[lo]);
+  return true;
 }
 
 // ---------------------------------------------------------------- mutual
@@ -334,6 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
   __shared__ unsigned s_err;
   __shared__ int s_lb[1];
   __shared__ unsigned s32[kWaves];
+  __shared__ RunCache rc;
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
   const int t = a.c.totals->t;
@@ -345,18 +398,21 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
       // run containing piece p0: first r with rpre[r+1] > p0
       const int r0 = (int)block_lower_bound(
           0, ctl.nruns, [&](long long r) { return (long long)a.in.rpre[r + 1] > p0; }, s_lb);
+      run_cache_fill(a.in, ctl.nruns, r0, rc);
+      __syncthreads();
       int r = r0;
       // kM pieces per lane per round; every load of a round is issued
       // unconditionally (clamped indices) so that the dependent chain piece ->
       // C[v] -> C[C[v]] is paid once per round, not once per piece
-      constexpr int kM = 4;
+      constexpr int kM = kMutualRound / kBlock;
       for (long long base = p0; base < p1; base += (long long)kBlock * kM) {
         int row[kM];
 #pragma unroll
         for (int i = 0; i < kM; ++i) {
           const long long pi = base + (long long)i * kBlock + threadIdx.x;
           row[i] = -1;
-          if (pi < p1) {
+          if (pi < p1 && !run_cache_find(rc, pi, r, row[i])) {
+            r = max(r, r0 + kBlock);  // past the cached runs: rpre[r0 + kBlock] <= pi
             while (r + 1 < ctl.nruns && (long long)a.in.rpre[r + 1] <= pi) ++r;
             row[i] = a.in.runs[r].row_begin + (int)(pi - a.in.rpre[r]);
           }
@@ -414,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
 // ---------------------------------------------------------------- stream
 
 // Compaction (and first argmax) over one virtual range [E0, E1) of the live
-// set, in batches of at most kBlock * stream_ppl pieces and kCap loaded entries:
+// set, in batches of at most kBlock * PPL pieces and kCap loaded entries:
 //   1. lane j takes piece cur_k + j; a prefix scan decides which pieces fit;
 //   2. continuity flags (a piece continuing the previous piece's vertex) and,
 //      for every loaded position, the piece it belongs to;
@@ -467,6 +523,7 @@ struct StreamSmem {
   unsigned s_lmax[kWaves];
   Key s_lkey[kWaves];
   int longlist[kLongMax];
+  RunCache rc;  // runs after the window's first run, when the window reaches them
   int lb[1];
   Carry carry;
   Part pf;  // the range's first segment when its row began before E0
@@ -558,17 +615,14 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
   if (!FIRST && slot >= 0) a.rows_out[slot] = make_int4(v, start, kept, (g & kGraphMask) | kHeadBit);
 }
 
-// The first argmax looks at one piece per lane: every piece is loaded and
-// rows average ~10 entries, so the entry budget fills first. The compaction
-// skips matched rows (most rows in early phases) and rows shrink, so it
-// looks at kWinLanes pieces per lane.
-template <bool FIRST>
-constexpr int stream_ppl() { return FIRST ? 1 : kWinLanes; }
-
-template <bool FIRST>
-__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * stream_ppl<FIRST>()>& sm,
+// A batch looks at PPL pieces per lane. The first argmax and the first
+// compaction take one: rows are long there, so the entry budget fills first.
+// Later compactions see short rows and many pieces of rows matched in the
+// phase (skipped without loading), and take kLatePPL.
+template <bool FIRST, int PPL>
+__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL>& sm,
                              unsigned long long seed0) {
-  constexpr int kPPL = stream_ppl<FIRST>();
+  constexpr int kPPL = PPL;
   constexpr int kW = kBlock * kPPL;  // pieces in a batch window
   const int tid = threadIdx.x;
   const int lane = lane_id(), wv = wave_id();
@@ -660,6 +714,11 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       sm.nlong = 0;
     }
     // ---- 1. window: lane t looks at pieces cur_k + kPPL t + h
+    const bool span = (long long)cur_k + kW > run_hi && run_hi < ctl.pieces;  // beyond run cur_r
+    if (span) {
+      run_cache_fill(a.in, ctl.nruns, rr + 1, sm.rc);
+      __syncthreads();
+    }
     int4 rec[kPPL];
     bool mt[kPPL], valid[kPPL];
     int cov[kPPL], rrh[kPPL];
@@ -672,7 +731,13 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       rec[h] = make_int4(-1, 0, 0, 0);
       mt[h] = false;
       if (valid[h]) {
-        const int row = gk < run_hi ? run_rb + (int)(gk - run_lo) : piece_row(a.in, gk, rr, ctl.nruns);
+        int row;
+        if (gk < run_hi) {
+          row = run_rb + (int)(gk - run_lo);
+        } else if (!run_cache_find(sm.rc, gk, rr, row)) {  // (span holds here)
+          rr = max(rr, sm.rc.c0 + kBlock);  // past the cached runs: rpre[c0 + kBlock] <= gk
+          row = piece_row(a.in, gk, rr, ctl.nruns);
+        }
         rec[h] = a.in.rows[row];
         if (j == 0) {
           rec[h].y += cur_o;
@@ -1181,15 +1246,15 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   }
 }
 
-template <bool FIRST>
-__global__ __launch_bounds__(kBlock, stream_ppl<FIRST>() > 1 ? 3 : 4) void k_stream(StreamArgs a) {
-  __shared__ StreamSmem<kBlock * stream_ppl<FIRST>()> sm;
+template <bool FIRST, int PPL>
+__global__ __launch_bounds__(kBlock, PPL > 1 ? 3 : 4) void k_stream(StreamArgs a) {
+  __shared__ StreamSmem<kBlock * PPL> sm;
   __shared__ unsigned s_err;
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
   const unsigned long long seed0 = a.c.gseed[0];
   for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) {
-    stream_range<FIRST>(a, ctl, b, sm, seed0);
+    stream_range<FIRST, PPL>(a, ctl, b, sm, seed0);
     __syncthreads();
   }
 }
@@ -1223,11 +1288,14 @@ hipError_t launch_plan(const PlanArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_stream<true>, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((k_stream<true, 1>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_stream<false>, dim3(grid), dim3(kBlock), 0, s, a);
+hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late) {
+  if (late)
+    hipLaunchKernelGGL((k_stream<false, kLatePPL>), dim3(grid), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_stream<false, 1>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s) {
@@ -1235,10 +1303,15 @@ hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-int max_blocks_per_cu_stream(bool first) {
+int max_blocks_per_cu_stream(StreamKind kind) {
   int nb = 0;
-  const hipError_t e = first ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<true>, kBlock, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false>, kBlock, 0);
+  hipError_t e;
+  if (kind == StreamKind::kFirst)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<true, 1>, kBlock, 0);
+  else if (kind == StreamKind::kCompact)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, 1>, kBlock, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, kLatePPL>, kBlock, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

@@ -52,16 +52,24 @@ struct Solver {
   lm_tuning tun{};
   int bpc_stream = 1;  // resident compaction workgroups per CU
   int bpc_first = 1;   // resident first-argmax workgroups per CU
+  int bpc_late = 1;    // resident late-compaction workgroups per CU
   bool busy_server = false;
   int last_phases = 0;
 
   DevBuf C, state, rows[2], ecol[2], ew[2], runs[2], epre[2], rpre[2];
   DevBuf ctl, parts, bstat, mcount;
-  DevBuf gbase, gseed, vtxoff, gphase, totals, log;
+  DevBuf gbase, gseed, vtxoff, gphase, totals;
   DevBuf in_rp, in_col, in_w, out_mate;
 
-  Ctl* h_ctl = nullptr;
   Totals* h_totals = nullptr;
+  // mapped pinned host memory the plan kernel writes: one record per live set
+  // (the host loop reads it after the plan's event) and the phase log
+  PhaseMirror* h_mir = nullptr;
+  PhaseMirror* d_mir = nullptr;
+  LogRec* h_log = nullptr;
+  LogRec* d_log = nullptr;
+  unsigned gen = 0;  // solves so far: tells this solve's mirror records from older ones
+  hipEvent_t ev_ring[kMirrorSlots] = {};  // after the plan that produced R_t, slot t
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipEvent_t e_order = nullptr;  // orders solves after the legacy default stream
   std::vector<hipEvent_t> evpool;

@@ -86,7 +86,7 @@ size_t solve_footprint(int64_t N, int64_t nnz, int64_t G) {
   b += 2 * ((size_t)kMaxBlocks * (sizeof(Run) + 8 + 4) + 1024);
   b += (size_t)kMaxBlocks * (2 * sizeof(Part) + sizeof(BlockStat) + 4) + 1024;
   b += (size_t)G * 16 + (size_t)(G + 1) * 8 + 1024;
-  b += 2 * sizeof(Ctl) + sizeof(Totals) + sizeof(LogRec) * (size_t)kLogCap + 1024;
+  b += 2 * sizeof(Ctl) + sizeof(Totals) + 1024;
   return b;
 }
 
@@ -118,7 +118,6 @@ lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
   RES(vtxoff, (size_t)(G + 1) * 8);
   if (want_gphase) RES(gphase, (size_t)G * 4);
   RES(totals, sizeof(Totals));
-  RES(log, sizeof(LogRec) * (size_t)kLogCap);
 #undef RES
   return LM_OK;
 }
@@ -137,15 +136,23 @@ lm_status Solver::init_device(int device, size_t budget) {
   num_cus = prop.multiProcessorCount;
   dev_name = prop.gcnArchName;
   if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return LM_EDEVICE;
-  if (hipHostMalloc((void**)&h_ctl, 2 * sizeof(Ctl)) != hipSuccess) return LM_EDEVICE;
   if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreateWithFlags(&e_order, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
-  bpc_stream = max_blocks_per_cu_stream(false);
-  bpc_first = max_blocks_per_cu_stream(true);
+  for (hipEvent_t& e : ev_ring)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
+  const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
+  if (hipHostMalloc((void**)&h_mir, sizeof(PhaseMirror) * kMirrorSlots, mapped) != hipSuccess) return LM_EDEVICE;
+  if (hipHostMalloc((void**)&h_log, sizeof(LogRec) * (size_t)kLogCap, mapped) != hipSuccess) return LM_EDEVICE;
+  std::memset(h_mir, 0, sizeof(PhaseMirror) * kMirrorSlots);
+  if (hipHostGetDevicePointer((void**)&d_mir, h_mir, 0) != hipSuccess) return LM_EDEVICE;
+  if (hipHostGetDevicePointer((void**)&d_log, h_log, 0) != hipSuccess) return LM_EDEVICE;
+  bpc_stream = max_blocks_per_cu_stream(StreamKind::kCompact);
+  bpc_first = max_blocks_per_cu_stream(StreamKind::kFirst);
+  bpc_late = max_blocks_per_cu_stream(StreamKind::kLateCompact);
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = bpc_stream;
-  tun.phases_per_sync = 4;
+  tun.phases_per_sync = 2;  // phases queued past the live set the host checks
   return LM_OK;
 }
 
@@ -154,8 +161,8 @@ void Solver::shutdown() {
   if (own) (void)hipStreamSynchronize(own);
   DevBuf* all[] = {&C,       &state,   &rows[0], &rows[1], &ecol[0], &ecol[1], &ew[0],   &ew[1],
                    &runs[0], &runs[1], &epre[0], &epre[1], &rpre[0], &rpre[1], &ctl,     &parts,
-                   &bstat,   &mcount,  &gbase,   &gseed,   &vtxoff,  &gphase,  &totals,  &log,
-                   &in_rp,   &in_col,  &in_w,    &out_mate};
+                   &bstat,   &mcount,  &gbase,   &gseed,   &vtxoff,  &gphase,  &totals,  &in_rp,
+                   &in_col,  &in_w,    &out_mate};
   for (DevBuf* b : all) pool.release(*b);
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   evpool.clear();
@@ -163,11 +170,17 @@ void Solver::shutdown() {
   if (e1) (void)hipEventDestroy(e1);
   if (e_order) (void)hipEventDestroy(e_order);
   e_order = nullptr;
-  if (h_ctl) (void)hipHostFree(h_ctl);
   if (h_totals) (void)hipHostFree(h_totals);
+  if (h_mir) (void)hipHostFree(h_mir);
+  if (h_log) (void)hipHostFree(h_log);
+  h_mir = d_mir = nullptr;
+  h_log = d_log = nullptr;
+  for (hipEvent_t& e : ev_ring) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (own) (void)hipStreamDestroy(own);
   own = nullptr;
-  h_ctl = nullptr;
   h_totals = nullptr;
   e0 = e1 = nullptr;
 }
@@ -184,6 +197,7 @@ hipEvent_t Solver::event(size_t i) {
 // Runs the phase loop over a problem whose inputs are already on the device.
 lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st) {
   const bool prof = (flags & LM_PROFILE) != 0;
+  if (++gen == 0) gen = 1;  // 0 marks a never-written mirror slot
   std::vector<std::pair<int, size_t>> marks;  // (kind, event index of start)
   size_t evn = 0;
   const uint32_t kmask = (st && st->profile_kinds) ? st->profile_kinds : ((1u << LM_K_KINDS) - 1);
@@ -213,8 +227,10 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   } while (0)
 
   const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_stream))));
-  // the first argmax keeps a smaller window and fits more workgroups per CU
-  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, bpc_first)));
+  // R_1 feeds the first argmax and the first compaction; later live sets feed
+  // compactions with the wider piece window, which fit fewer workgroups per CU
+  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(bpc_first, bpc_stream))));
+  const int pcap_late = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_late))));
   const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
   Ctl* dctl = (Ctl*)ctl.p;
   Totals* dtot = (Totals*)totals.p;
@@ -249,9 +265,12 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     a.pcap = pcap;
     a.pmcap = pmcap;
     a.min_per_block = std::max(kCap, tun.block_entries);
+    a.pieces_per_block = kBlock * kLatePPL;
     a.nruns_new = -1;
-    a.log = (LogRec*)log.p;
+    a.log = d_log;
     a.log_cap = kLogCap;
+    a.mirror = d_mir;
+    a.gen = gen;
     a.mcount = (const int*)mcount.p;
     return a;
   };
@@ -295,6 +314,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     PlanArgs pa = plan_base();
     pa.mode = kPlanPrefix;
     pa.pcap = pcap_first;
+    pa.pieces_per_block = kBlock;
     pa.ctl_prev = nullptr;
     pa.runs_new = (const Run*)runs[0].p;
     pa.nruns_new = pi;
@@ -334,7 +354,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ma.in = in;
     ma.mcount = (int*)mcount.p;
     ma.census = 0;
-    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, est_V / kCap + 1));
+    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, est_V / kMutualRound + 1));
     ENQ(mark_begin(LM_K_MUTUAL));
     ENQ(launch_mutual(ma, gm, s));
     ENQ(mark_end());
@@ -348,11 +368,16 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     sa.dst_w = (float*)ew[(t + 1) & 1].p;
     sa.parts = (Part*)parts.p;
     sa.bstat = (BlockStat*)bstat.p;
-    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(pcap, est_L / std::max(kCap, tun.block_entries) + 1));
+    const bool late = t > 1;
+    const int gx = (int)std::max<int64_t>(
+        1, std::min<int64_t>(late ? pcap_late : pcap_first,
+                             std::max<int64_t>(est_L / std::max(kCap, tun.block_entries),
+                                               est_V / (kBlock * (late ? kLatePPL : 1))) + 1));
     ENQ(mark_begin(LM_K_COMPACT));
-    ENQ(launch_compact(sa, gx, s));
+    ENQ(launch_compact(sa, gx, s, late));
     ENQ(mark_end());
-    PlanArgs pa = plan_base();
+    PlanArgs pa = plan_base();  // sizes the next compaction, a late one
+    pa.pcap = pcap_late;
     pa.mode = kPlanFix | kPlanPrefix | kPlanLog | kPlanTick;
     pa.ctl_prev = in.ctl;
     pa.parts = (Part*)parts.p;
@@ -386,7 +411,10 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
       if (g) (void)hipGraphDestroy(g);
     }
   } guard{graph, gexec};
-  bool first_check = true;
+  constexpr int kRing = kMirrorSlots - 1;
+  // rc: the live set R_rc the host checks next; ev_ring[rc & kRing] follows the
+  // plan that produced it, and that plan left its record in h_mir.
+  int rc = 1;
   if (use_graph) {
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t ce = enqueue_prologue();
@@ -396,54 +424,69 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     HIPCHK(ee);
     HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     HIPCHK(hipGraphLaunch(gexec, s));
-    first_check = false;
+    rc = t;  // the graph's last plan produced R_t
   } else {
     HIPCHK(enqueue_prologue());
   }
-  // phase loop: sync every few phases to see whether the live set is empty
+  HIPCHK(hipEventRecord(ev_ring[rc & kRing], s));
+  // Phase loop: phases rc .. rc + ahead - 1 stay queued while the host waits for
+  // the record of R_rc, so the device never idles on the host; the phases
+  // queued past the empty live set are no-ops.
+  const int ahead = std::max(1, std::min(tun.phases_per_sync, kMirrorSlots / 2));
   int64_t last_live = -1;
-  bool stalled = false;
-  bool pending = use_graph;  // the graph's phases still need a check
+  bool stalled = false, no_record = false;
+  PhaseMirror fin{};
   for (;;) {
-    if (!pending) {
-      const int chunk = first_check ? 2 : std::max(1, tun.phases_per_sync);
-      for (int j = 0; j < chunk; ++j) HIPCHK(enqueue_phase());
+    while (t < rc + ahead) {
+      HIPCHK(enqueue_phase());  // phase t - 1 is queued; its plan produces R_t
+      HIPCHK(hipEventRecord(ev_ring[t & kRing], s));
     }
-    pending = false;
-    HIPCHK(hipMemcpyAsync(h_ctl, dctl + ((t - 1) & 1), sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h_totals, dtot, sizeof(Totals), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    first_check = false;
-    if (h_totals->err) break;
-    const int64_t live_now = h_ctl->L;
-    if (live_now == 0) break;
+    HIPCHK(hipEventSynchronize(ev_ring[rc & kRing]));
+    PhaseMirror m;  // complete once the event is: the plan wrote it before finishing
+    std::memcpy(&m, &h_mir[rc & kRing], sizeof(m));
+    if (m.gen != gen || m.t != rc) {  // the plan stopped on an error flag before writing
+      no_record = true;
+      break;
+    }
+    fin = m;
+    if (m.err || m.L == 0) break;
     // every phase of a well-formed graph matches its globally heaviest live
-    // edge; no progress over a whole chunk means asymmetric input
-    if (live_now == last_live) {
+    // edge; a phase without progress means asymmetric input
+    if (m.L == last_live) {
       stalled = true;
       break;
     }
-    last_live = live_now;
-    est_L = live_now;
-    est_V = h_ctl->pieces;
+    last_live = m.L;
+    est_L = m.L;
+    est_V = m.pieces;
+    ++rc;
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
-  const unsigned err = h_totals->err;
-  if (stalled) return LM_EGRAPH;
+  Totals tot{};
+  if (no_record) {
+    HIPCHK(hipMemcpy(h_totals, dtot, sizeof(Totals), hipMemcpyDeviceToHost));
+    tot = *h_totals;
+  } else {
+    tot.err = fin.err;
+    tot.matched = fin.matched;
+    tot.last_nonempty = fin.last_nonempty;
+  }
+  const unsigned err = tot.err;
   if (err) {
     if (err & kErrWeight) return LM_EWEIGHT;
     if (err & (kErrRowPtr | kErrColRange | kErrSelfLoop)) return LM_EGRAPH;
     if (err & kErrDegree) return LM_ETOOBIG;
     return LM_EDEVICE;
   }
-  const int phases = h_totals->last_nonempty;
+  if (stalled || no_record) return stalled ? LM_EGRAPH : LM_EDEVICE;
+  const int phases = tot.last_nonempty;
   last_phases = phases;
   if (st) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     st->phases = phases;
-    st->matched_edges = (int64_t)(h_totals->matched / 2);
+    st->matched_edges = (int64_t)(tot.matched / 2);
     st->device_ms = ms;
     for (int k = 0; k < LM_K_KINDS; ++k) {
       st->k_launches[k] = 0;
@@ -458,7 +501,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     }
     const int nrec = std::min(phases, kLogCap);
     std::vector<LogRec> recs((size_t)nrec + 1);
-    if (nrec > 0) HIPCHK(hipMemcpy(recs.data(), log.p, sizeof(LogRec) * (size_t)nrec, hipMemcpyDeviceToHost));
+    if (nrec > 0) std::memcpy(recs.data(), h_log, sizeof(LogRec) * (size_t)nrec);
     recs[(size_t)nrec] = LogRec{0, 0, 0, 0};
     st->log_len = 0;
     if (st->log && st->log_cap > 0) {
