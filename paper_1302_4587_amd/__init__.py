@@ -102,6 +102,16 @@ class Context:
     def handle(self):
         return self._h
 
+    def _logbuf(self, log_cap: int):
+        """Phase-log buffer of log_cap records, kept across solves (the stats
+        copy what they return)."""
+        cap = max(int(log_cap), 1)
+        buf = getattr(self, "_logbufs", {}).get(cap)
+        if buf is None:
+            buf = (_lib.PhaseRec * cap)()
+            self._logbufs = {cap: buf}
+        return buf
+
     # -------------------------------------------------------------- tuning
     def tuning(self) -> dict:
         t = _lib.Tuning()
@@ -148,7 +158,7 @@ class Context:
         mp, dm, km = _ptr(mate, np.int32)
         flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph)
         g = _lib.Csr(n, nnz, rp, cp, wp)
-        logbuf = (_lib.PhaseRec * max(log_cap, 1))()
+        logbuf = self._logbuf(log_cap)
         st = _lib.Stats()
         st.log = logbuf
         st.log_cap = log_cap
@@ -186,7 +196,7 @@ class Context:
             sp = sk.ctypes.data
         flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph)
         gph = np.zeros(G, dtype=np.int32) if want_graph_phases else None
-        logbuf = (_lib.PhaseRec * max(log_cap, 1))()
+        logbuf = self._logbuf(log_cap)
         st = _lib.Stats()
         st.log = logbuf
         st.log_cap = log_cap
