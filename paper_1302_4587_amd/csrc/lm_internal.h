@@ -90,8 +90,9 @@ struct Totals {
 };
 
 // What the host loop needs after each plan, written by the plan kernel into
-// mapped pinned host memory: the host reads it once an event recorded after
-// that plan has completed, with no copy on the stream. Slot R_t & (kMirrorSlots - 1).
+// mapped coherent pinned host memory: the record is stored, made visible to
+// the system, and only then marked ready (ready = gen), so the host polls the
+// slot of R_t (t & (kMirrorSlots - 1)) with no event or copy on the stream.
 struct PhaseMirror {
   long long L;                 // live entries of the live set just planned
   unsigned long long matched;  // matched entries so far (both directions)
@@ -100,7 +101,7 @@ struct PhaseMirror {
   unsigned gen;                // solve that wrote the record
   unsigned err;                // error flags so far
   int last_nonempty;           // last phase that had live rows
-  int pad;
+  unsigned ready;              // gen once the record is complete
 };
 constexpr int kMirrorSlots = 64;
 
@@ -221,11 +222,14 @@ hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s);
 hipError_t launch_fill_i32(int* p, long long n, int value, hipStream_t s);
 hipError_t launch_add_i64(long long* p, long long n, long long delta, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s);
-hipError_t launch_init(const InitArgs& a, hipStream_t s);
-hipError_t launch_plan(const PlanArgs& a, hipStream_t s);
-hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s);
-hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false);
-hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s);
+// Optional ev[2] = {start, stop} timing events: recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so timing a launch adds no marker packet and no
+// bubble to the stream.
+hipError_t launch_init(const InitArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
+hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
+hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
+hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false, hipEvent_t* ev = nullptr);
+hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 enum class StreamKind { kFirst, kCompact, kLateCompact };
 int max_blocks_per_cu_stream(StreamKind kind);
 

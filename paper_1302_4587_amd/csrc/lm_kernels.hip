@@ -11,6 +11,8 @@
 //            phase's argmax is computed in the same pass.
 // The live-set layout (pieces grouped into runs) is described in
 // lm_internal.h.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <climits>
 
@@ -338,8 +340,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
     m.gen = a.gen;
     m.err = a.c.totals->err;
     m.last_nonempty = a.c.totals->last_nonempty;
-    m.pad = 0;
-    a.mirror[m.t & (kMirrorSlots - 1)] = m;
+    m.ready = 0u;
+    PhaseMirror* slot = &a.mirror[m.t & (kMirrorSlots - 1)];
+    *slot = m;
+    __threadfence_system();  // the record reaches host memory before it is marked ready
+    *(volatile unsigned*)&slot->ready = a.gen;
   }
   if ((a.mode & kPlanTick) && tid == 0) a.c.totals->t += 1;
 }
@@ -1279,28 +1284,33 @@ hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_check, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_init(const InitArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(a.nblocks), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_plan(const PlanArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_stream<true, 1>), dim3(grid), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late) {
-  if (late)
-    hipLaunchKernelGGL((k_stream<false, kLatePPL>), dim3(grid), dim3(kBlock), 0, s, a);
+// With ev = {start, stop} the launch goes through hipExtLaunchKernelGGL and
+// the dispatch itself stamps both events; otherwise a plain launch (the one
+// HIP graph capture records).
+template <typename K, typename A>
+static hipError_t launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t* ev, const A& a) {
+  if (ev)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev[0], ev[1], 0, a);
   else
-    hipLaunchKernelGGL((k_stream<false, 1>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_mutual, dim3(grid), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+
+hipError_t launch_init(const InitArgs& a, hipStream_t s, hipEvent_t* ev) {
+  return launch_timed(k_init, dim3(a.nblocks), dim3(kBlock), s, ev, a);
+}
+hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev) {
+  return launch_timed(k_plan, dim3(1), dim3(kPlanThreads), s, ev, a);
+}
+hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
+  return launch_timed(k_stream<true, 1>, dim3(grid), dim3(kBlock), s, ev, a);
+}
+hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late, hipEvent_t* ev) {
+  if (late) return launch_timed(k_stream<false, kLatePPL>, dim3(grid), dim3(kBlock), s, ev, a);
+  return launch_timed(k_stream<false, 1>, dim3(grid), dim3(kBlock), s, ev, a);
+}
+hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
+  return launch_timed(k_mutual, dim3(grid), dim3(kBlock), s, ev, a);
 }
 
 int max_blocks_per_cu_stream(StreamKind kind) {

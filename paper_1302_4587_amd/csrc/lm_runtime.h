@@ -69,7 +69,6 @@ struct Solver {
   LogRec* h_log = nullptr;
   LogRec* d_log = nullptr;
   unsigned gen = 0;  // solves so far: tells this solve's mirror records from older ones
-  hipEvent_t ev_ring[kMirrorSlots] = {};  // after the plan that produced R_t, slot t
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipEvent_t e_order = nullptr;  // orders solves after the legacy default stream
   std::vector<hipEvent_t> evpool;

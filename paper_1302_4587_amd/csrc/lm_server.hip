@@ -398,7 +398,7 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
   const int bes[] = {2048, 8192, 32768};
   for (int sm : bes) {
     for (int gp = 1; gp <= std::max(1, sv.bpc_stream); ++gp) {
-      for (int pp : {2, 4}) {  // phases queued past the checked live set
+      for (int pp : {1, 2}) {  // phases queued past the checked live set
         lm_tuning t{sm, gp, pp};
         sv.tun = t;
         std::vector<double> ms;

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -139,8 +140,6 @@ lm_status Solver::init_device(int device, size_t budget) {
   if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreateWithFlags(&e_order, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
-  for (hipEvent_t& e : ev_ring)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
   const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
   if (hipHostMalloc((void**)&h_mir, sizeof(PhaseMirror) * kMirrorSlots, mapped) != hipSuccess) return LM_EDEVICE;
   if (hipHostMalloc((void**)&h_log, sizeof(LogRec) * (size_t)kLogCap, mapped) != hipSuccess) return LM_EDEVICE;
@@ -152,7 +151,7 @@ lm_status Solver::init_device(int device, size_t budget) {
   bpc_late = max_blocks_per_cu_stream(StreamKind::kLateCompact);
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = bpc_stream;
-  tun.phases_per_sync = 2;  // phases queued past the live set the host checks
+  tun.phases_per_sync = 1;  // phases queued past the live set the host checks
   return LM_OK;
 }
 
@@ -175,10 +174,7 @@ void Solver::shutdown() {
   if (h_log) (void)hipHostFree(h_log);
   h_mir = d_mir = nullptr;
   h_log = d_log = nullptr;
-  for (hipEvent_t& e : ev_ring) {
-    if (e) (void)hipEventDestroy(e);
-    e = nullptr;
-  }
+
   if (own) (void)hipStreamDestroy(own);
   own = nullptr;
   h_totals = nullptr;
@@ -201,21 +197,21 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   std::vector<std::pair<int, size_t>> marks;  // (kind, event index of start)
   size_t evn = 0;
   const uint32_t kmask = (st && st->profile_kinds) ? st->profile_kinds : ((1u << LM_K_KINDS) - 1);
-  bool mark_open = false;
-  auto mark_begin = [&](int kind) -> hipError_t {
-    mark_open = false;
-    if (!prof || !((kmask >> kind) & 1u)) return hipSuccess;
-    hipEvent_t e = event(evn);
-    if (!e || !event(evn + 1)) return hipErrorOutOfMemory;
+  // Timing events {start, stop} for one launch of a profiled kind, stamped by
+  // the dispatch itself; nullptr when the kind is not timed.
+  hipEvent_t tev[2] = {nullptr, nullptr};
+  bool tev_fail = false;
+  auto timing = [&](int kind) -> hipEvent_t* {
+    if (!prof || !((kmask >> kind) & 1u)) return nullptr;
+    tev[0] = event(evn);
+    tev[1] = event(evn + 1);
+    if (!tev[0] || !tev[1]) {
+      tev_fail = true;
+      return nullptr;
+    }
     marks.push_back({kind, evn});
     evn += 2;
-    mark_open = true;
-    return hipEventRecord(e, s);
-  };
-  auto mark_end = [&]() -> hipError_t {
-    if (!mark_open) return hipSuccess;
-    mark_open = false;
-    return hipEventRecord(event(marks.back().second + 1), s);
+    return tev;
   };
 #define HIPCHK(x)                          \
   do {                                     \
@@ -308,9 +304,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ia.runs_base = 0;
     ia.runs_out = (Run*)runs[0].p;
     ia.rows_out = (int4*)rows[0].p;
-    ENQ(mark_begin(LM_K_INIT));
-    ENQ(launch_init(ia, s));
-    ENQ(mark_end());
+    ENQ(launch_init(ia, s, timing(LM_K_INIT)));
     PlanArgs pa = plan_base();
     pa.mode = kPlanPrefix;
     pa.pcap = pcap_first;
@@ -321,9 +315,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     pa.epre_new = (long long*)epre[0].p;
     pa.rpre_new = (int*)rpre[0].p;
     pa.ctl_new = dctl + 0;
-    ENQ(mark_begin(LM_K_PLAN));
-    ENQ(launch_plan(pa, s));
-    ENQ(mark_end());
+    ENQ(launch_plan(pa, s, timing(LM_K_PLAN)));
     StreamArgs sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.c = c;
@@ -332,17 +324,13 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     sa.bstat = (BlockStat*)bstat.p;
     const int gx =
         (int)std::max<int64_t>(1, std::min<int64_t>(pcap_first, p.nnz / std::max(kCap, tun.block_entries) + 1));
-    ENQ(mark_begin(LM_K_ARGMAX));
-    ENQ(launch_first_argmax(sa, gx, s));
-    ENQ(mark_end());
+    ENQ(launch_first_argmax(sa, gx, s, timing(LM_K_ARGMAX)));
     PlanArgs pf = plan_base();
     pf.mode = kPlanFix;
     pf.first = 1;
     pf.ctl_prev = dctl + 0;
     pf.parts = (Part*)parts.p;
-    ENQ(mark_begin(LM_K_PLAN));
-    ENQ(launch_plan(pf, s));
-    ENQ(mark_end());
+    ENQ(launch_plan(pf, s, timing(LM_K_PLAN)));
     return hipSuccess;
   };
   // phase t: mutual check, compaction fused with the next argmax, plan
@@ -355,9 +343,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ma.mcount = (int*)mcount.p;
     ma.census = 0;
     const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, est_V / kMutualRound + 1));
-    ENQ(mark_begin(LM_K_MUTUAL));
-    ENQ(launch_mutual(ma, gm, s));
-    ENQ(mark_end());
+    ENQ(launch_mutual(ma, gm, s, timing(LM_K_MUTUAL)));
     const int lo = t & 1;
     StreamArgs sa;
     sa.c = c;
@@ -373,9 +359,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
         1, std::min<int64_t>(late ? pcap_late : pcap_first,
                              std::max<int64_t>(est_L / std::max(kCap, tun.block_entries),
                                                est_V / (kBlock * (late ? kLatePPL : 1))) + 1));
-    ENQ(mark_begin(LM_K_COMPACT));
-    ENQ(launch_compact(sa, gx, s, late));
-    ENQ(mark_end());
+    ENQ(launch_compact(sa, gx, s, late, timing(LM_K_COMPACT)));
     PlanArgs pa = plan_base();  // sizes the next compaction, a late one
     pa.pcap = pcap_late;
     pa.mode = kPlanFix | kPlanPrefix | kPlanLog | kPlanTick;
@@ -387,9 +371,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     pa.epre_new = (long long*)epre[lo].p;
     pa.rpre_new = (int*)rpre[lo].p;
     pa.ctl_new = dctl + lo;
-    ENQ(mark_begin(LM_K_PLAN));
-    ENQ(launch_plan(pa, s));
-    ENQ(mark_end());
+    ENQ(launch_plan(pa, s, timing(LM_K_PLAN)));
     ++t;
     return hipSuccess;
   };
@@ -412,8 +394,8 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     }
   } guard{graph, gexec};
   constexpr int kRing = kMirrorSlots - 1;
-  // rc: the live set R_rc the host checks next; ev_ring[rc & kRing] follows the
-  // plan that produced it, and that plan left its record in h_mir.
+  // rc: the live set R_rc the host checks next; the plan that produced it
+  // leaves its record in h_mir[rc & kRing].
   int rc = 1;
   if (use_graph) {
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -428,23 +410,39 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   } else {
     HIPCHK(enqueue_prologue());
   }
-  HIPCHK(hipEventRecord(ev_ring[rc & kRing], s));
-  // Phase loop: phases rc .. rc + ahead - 1 stay queued while the host waits for
+  // Phase loop: phases rc .. rc + ahead - 1 stay queued while the host polls
   // the record of R_rc, so the device never idles on the host; the phases
-  // queued past the empty live set are no-ops.
+  // queued past the empty live set are no-ops. No event is recorded between
+  // phases: each one would put a bubble of a few microseconds on the stream.
   const int ahead = std::max(1, std::min(tun.phases_per_sync, kMirrorSlots / 2));
+  // 1: record of R_idx read; 0: the stream drained without it (an error flag
+  // stopped the plan); -1: the stream failed
+  auto wait_record = [&](int idx, PhaseMirror& m) -> int {
+    const volatile PhaseMirror* slot = &h_mir[idx & kRing];
+    auto take = [&]() -> bool {
+      if (slot->ready != gen) return false;
+      std::atomic_thread_fence(std::memory_order_acquire);
+      std::memcpy(&m, (const void*)slot, sizeof(m));
+      return m.t == idx;
+    };
+    for (unsigned spin = 1;; ++spin) {
+      if (take()) return 1;
+      if ((spin & 255u) == 0u) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipSuccess) return take() ? 1 : 0;
+        if (q != hipErrorNotReady) return -1;
+      }
+    }
+  };
   int64_t last_live = -1;
   bool stalled = false, no_record = false;
   PhaseMirror fin{};
   for (;;) {
-    while (t < rc + ahead) {
-      HIPCHK(enqueue_phase());  // phase t - 1 is queued; its plan produces R_t
-      HIPCHK(hipEventRecord(ev_ring[t & kRing], s));
-    }
-    HIPCHK(hipEventSynchronize(ev_ring[rc & kRing]));
-    PhaseMirror m;  // complete once the event is: the plan wrote it before finishing
-    std::memcpy(&m, &h_mir[rc & kRing], sizeof(m));
-    if (m.gen != gen || m.t != rc) {  // the plan stopped on an error flag before writing
+    while (t < rc + ahead) HIPCHK(enqueue_phase());  // phase t - 1 queued: its plan produces R_t
+    PhaseMirror m;
+    const int got = wait_record(rc, m);
+    if (got < 0) HIPCHK(hipStreamSynchronize(s));
+    if (got <= 0) {
       no_record = true;
       break;
     }
@@ -480,6 +478,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     return LM_EDEVICE;
   }
   if (stalled || no_record) return stalled ? LM_EGRAPH : LM_EDEVICE;
+  if (tev_fail) return LM_ENOMEM;  // a timing event could not be created
   const int phases = tot.last_nonempty;
   last_phases = phases;
   if (st) {
