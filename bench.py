@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="50,150",
                     help="Poisson arrival rates (requests/s) for --serve")
     ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--weight-array", action="store_true",
+                    help="rmat: pass the all-ones weight array instead of no array (unweighted solve)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -107,12 +109,16 @@ def main():
         workload = f"rgg2d n=2^{args.log2n} avg_degree={args.avg_degree:g} w=1-dist seed={args.seed}"
     else:
         g = lmgen.rmat(args.log2n, 16, seed=args.seed)
-        workload = f"rmat scale={args.log2n} edge_factor=16 (a,b,c,d)=(.57,.19,.19,.05) unit weights seed={args.seed}"
+        rep = "as an all-ones weight array" if args.weight_array else "as an unweighted graph (no weight array)"
+        workload = (f"rmat scale={args.log2n} edge_factor=16 (a,b,c,d)=(.57,.19,.19,.05) unit weights "
+                    f"{rep} seed={args.seed}")
     gen_s = time.time() - t0
     print(f"bench: generated {args.workload} n={g.n} m={g.m} nnz={g.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
-    w = torch.from_numpy(g.w).to(dev)
+    # unit weights carry no information: by default they are passed as no
+    # weight array (w=None), the library's unweighted mode, which reads none
+    w = None if (args.workload == "rmat" and not args.weight_array) else torch.from_numpy(g.w).to(dev)
     mate = torch.empty(g.n, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
 

@@ -88,7 +88,10 @@ typedef struct {
   int64_t nnz;            /* directed entries = 2 * undirected edges = row_ptr[n] */
   const int64_t* row_ptr; /* n+1 */
   const int32_t* col;     /* nnz */
-  const float* w;         /* nnz */
+  const float* w;         /* nnz, or NULL for an unweighted graph: every edge weighs 1
+                             (the unweighted setting of Section 1), so the order of
+                             the edges is the tie-break hash alone. The kernels then
+                             neither read nor write weights. */
 } lm_csr;
 
 /* One record per phase t = 1, 2, ... */

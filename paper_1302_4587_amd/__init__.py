@@ -31,10 +31,11 @@ def _is_torch(x) -> bool:
     return hasattr(x, "data_ptr") and hasattr(x, "is_cuda")
 
 
-def _ptr(x, dtype):
-    """(pointer, on_device, keepalive) for a torch tensor or numpy array."""
+def _ptr(x, dtype, on_device=False):
+    """(pointer, on_device, keepalive) for a torch tensor or numpy array; None
+    (an absent weight array: unweighted graph) takes the residence given."""
     if x is None:
-        return None, False, None
+        return None, on_device, None
     if _is_torch(x):
         import torch
         want = {np.int64: torch.int64, np.int32: torch.int32, np.float32: torch.float32}[dtype]
@@ -146,7 +147,7 @@ class Context:
         nnz = int(col.shape[0])
         rp, d0, k0 = _ptr(row_ptr, np.int64)
         cp, d1, k1 = _ptr(col, np.int32)
-        wp, d2, k2 = _ptr(w, np.float32)
+        wp, d2, k2 = _ptr(w, np.float32, d0)  # w=None: unweighted (every edge weighs 1)
         if not (d0 == d1 == d2):
             raise ValueError("row_ptr, col, w must all be on the device or all on the host")
         if mate is None:
@@ -179,7 +180,7 @@ class Context:
         nnz = int(col.shape[0])
         rp, d0, k0 = _ptr(row_ptr, np.int64)
         cp, d1, k1 = _ptr(col, np.int32)
-        wp, d2, k2 = _ptr(w, np.float32)
+        wp, d2, k2 = _ptr(w, np.float32, d0)  # w=None: unweighted (every edge weighs 1)
         if not (d0 == d1 == d2):
             raise ValueError("row_ptr, col, w must all be on the device or all on the host")
         if mate is None:
@@ -209,7 +210,7 @@ class Context:
         vo = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
         rp, d0, k0 = _ptr(row_ptr, np.int64)
         cp, d1, k1 = _ptr(col, np.int32)
-        wp, d2, k2 = _ptr(w, np.float32)
+        wp, d2, k2 = _ptr(w, np.float32, d0)
         t = _lib.Tuning()
         flags = LM_IN_DEVICE if d0 else 0
         check(self._lib.lm_autotune_batch(self._h, len(vo) - 1, vo.ctypes.data, int(col.shape[0]), rp, cp, wp, flags,

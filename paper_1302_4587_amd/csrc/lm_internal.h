@@ -227,8 +227,12 @@ hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s);
 // bubble to the stream.
 hipError_t launch_init(const InitArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
-hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
-hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false, hipEvent_t* ev = nullptr);
+// unweighted: the graph has no weight array (every edge weighs 1); the
+// kernels then neither load nor store weights.
+hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted = false,
+                               hipEvent_t* ev = nullptr);
+hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false, bool unweighted = false,
+                          hipEvent_t* ev = nullptr);
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 enum class StreamKind { kFirst, kCompact, kLateCompact };
 int max_blocks_per_cu_stream(StreamKind kind);

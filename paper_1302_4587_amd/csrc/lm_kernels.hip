@@ -81,8 +81,10 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
       const int u = a.col[k];
       if (u < 0 || u >= lim) err |= kErrColRange;
       if (u == v - base) err |= kErrSelfLoop;
-      const float x = a.w[k];
-      if (!(x == x) || x == __int_as_float(0x7f800000) || x == __int_as_float(0xff800000)) err |= kErrWeight;
+      if (a.w) {
+        const float x = a.w[k];
+        if (!(x == x) || x == __int_as_float(0x7f800000) || x == __int_as_float(0xff800000)) err |= kErrWeight;
+      }
     }
   }
   if (err) atomicOr(&a.totals->err, err);
@@ -525,6 +527,7 @@ struct StreamSmem {
   unsigned s_emit[kWaves];
   unsigned long long p_hash[W];  // largest tie-break hash per tied piece
   unsigned char p_tie[W];        // the piece's largest weight repeats
+  unsigned char p_hit[W];        // the hash pass saw a candidate of the piece (UNW)
   unsigned s_lmax[kWaves];
   Key s_lkey[kWaves];
   int longlist[kLongMax];
@@ -624,9 +627,13 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // compaction take one: rows are long there, so the entry budget fills first.
 // Later compactions see short rows and many pieces of rows matched in the
 // phase (skipped without loading), and take kLatePPL.
-template <bool FIRST, int PPL>
+// UNW: an unweighted graph (no weight array; every edge weighs 1). Weights are
+// neither loaded nor stored, every loaded piece is tied, the weight scans are
+// skipped and the hash pass decides every piece.
+template <bool FIRST, int PPL, bool UNW>
 __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL>& sm,
                              unsigned long long seed0) {
+  constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f (0x3f800000 | sign bit)
   constexpr int kPPL = PPL;
   constexpr int kW = kBlock * kPPL;  // pieces in a batch window
   const int tid = threadIdx.x;
@@ -852,7 +859,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       for (int jj = 0; jj < kItems; ++jj) {
         const int addr = min(tid + kBlock * jj, NLD - 1) + sm.p_delta[jp[jj]];
         cc[jj] = a.in.col[addr];
-        ww[jj] = a.in.w[addr];
+        ww[jj] = UNW ? 1.0f : a.in.w[addr];
       }
       bool ok[kItems];
       unsigned ug[kItems];
@@ -875,7 +882,8 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       for (int jj = 0; jj < kItems; ++jj) {
         const int q = tid + kBlock * jj;
         const bool kp = ok[jj] && (FIRST || st[jj] == 0);
-        if (q < NLD) sm.e_cw[q] = make_uint2(kp ? ord_weight_bits(__float_as_uint(ww[jj])) : 0u, (unsigned)cc[jj]);
+        const unsigned x = kp ? (UNW ? kUnitOrd : ord_weight_bits(__float_as_uint(ww[jj]))) : 0u;
+        if (q < NLD) sm.e_cw[q] = make_uint2(x, (unsigned)cc[jj]);
         if (!FIRST) {
           const unsigned long long bal = __ballot(kp);
           rank[jj] = (unsigned)__popcll(bal & lt);
@@ -897,7 +905,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
           if (q < NLD) sm.kpre[q] = (unsigned short)kq;
           if ((kpm >> jj) & 1u) {
             a.dst_col[out_base + (int)kq] = cc[jj];
-            a.dst_w[out_base + (int)kq] = ww[jj];
+            if (!UNW) a.dst_w[out_base + (int)kq] = ww[jj];
           }
         }
         if (tid == 0) sm.kpre[NLD] = (unsigned short)ktot;
@@ -922,7 +930,17 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       bw[h] = 0u;
       bu[h] = -1;
       tie[h] = false;
-      if (j < nt && ldt[h] <= kLong) {
+      if (UNW) {
+        if (j < nt) {
+          tie[h] = ldt[h] > 0;
+          bw[h] = tie[h] ? kUnitOrd : 0u;
+          sm.p_w[j] = bw[h];
+          sm.p_u[j] = -1;
+          sm.p_tie[j] = tie[h] ? 1 : 0;
+          sm.p_hash[j] = 0ull;
+          sm.p_hit[j] = 0;
+        }
+      } else if (j < nt && ldt[h] <= kLong) {
         // largest ordered weight, its first neighbour, and whether it repeats;
         // only a repeated largest weight needs the tie-break hash
         unsigned m = 0u;
@@ -942,14 +960,16 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         sm.p_u[j] = mu;
         if (tie[h]) sm.p_hash[j] = 0ull;
       }
-      if (j < nt && ldt[h] <= kLong) sm.p_tie[j] = tie[h] ? 1 : 0;  // long pieces: set below
+      if (!UNW && j < nt && ldt[h] <= kLong) sm.p_tie[j] = tie[h] ? 1 : 0;  // long pieces: set below
       anytie = anytie || tie[h];
     }
     // Long pieces: largest ordered weight only (a wave per piece, or the whole
     // workgroup when there are fewer long pieces than waves); their winner is
     // found by the hash pass below like that of a tied short piece.
     const int nlong = sm.nlong;
-    if (nlong > 0 && nlong < kWaves) {
+    if (UNW) {
+      // nothing: every loaded piece is tied at weight 1
+    } else if (nlong > 0 && nlong < kWaves) {
       for (int li = 0; li < nlong; ++li) {
         const int j = sm.longlist[li];
         const int vo = sm.p_vo[j], ld = sm.p_ld[j];
@@ -996,8 +1016,70 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       for (int h = 0; h < kPPL; ++h)
         if (tie[h]) {
           bu[h] = tie_break(sm.e_cw + lpre[h], ldt[h], bw[h], vloc_of(h), seed_of(h));
+          if (UNW && bu[h] < 0) bw[h] = 0u;  // every entry of the piece was dropped
           sm.p_u[tid * kPPL + h] = bu[h];
         }
+    } else if (UNW) {
+      if (NLD > 0) {
+        // as below, but a piece may have no candidate left (all its entries
+        // dropped), so the lanes also mark the pieces they saw a candidate of
+        int cur_j = -1;
+        unsigned long long cur_h = 0ull;
+        bool cur_s = false;
+#pragma unroll
+        for (int jj = 0; jj < kItems; ++jj) {
+          const int q = min(tid + kBlock * jj, NLD - 1);
+          const int j = sm.rowof[q];
+          unsigned long long hh = 0ull;
+          bool hs = false;
+          if (tid + kBlock * jj < NLD) {
+            const uint2 e = sm.e_cw[q];
+            if (e.x != 0u) {
+              const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+              hh = edge_hash(S, (unsigned)(sm.p_v[j] - (single ? 0 : sm.p_base[j])), e.y);
+              hs = true;
+            }
+          }
+          if (j != cur_j) {
+            if (cur_s) {
+              atomicMax(&sm.p_hash[cur_j], cur_h);
+              sm.p_hit[cur_j] = 1;
+            }
+            cur_j = j;
+            cur_h = hh;
+            cur_s = hs;
+          } else if (hs && (!cur_s || hh > cur_h)) {
+            cur_h = hh;
+            cur_s = true;
+          }
+        }
+        if (__builtin_amdgcn_readfirstlane(cur_j) == __builtin_amdgcn_readlane(cur_j, 63)) {
+          const bool any = __ballot(cur_s) != 0ull;  // the whole wave ends in one piece
+          cur_h = wave_max_u64(cur_s ? cur_h : 0ull);
+          if (lane == 0 && any) {
+            atomicMax(&sm.p_hash[cur_j], cur_h);
+            sm.p_hit[cur_j] = 1;
+          }
+        } else if (cur_s) {
+          atomicMax(&sm.p_hash[cur_j], cur_h);
+          sm.p_hit[cur_j] = 1;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < kPPL; ++h) {
+        const int j = tid * kPPL + h;
+        if (j < nt && tie[h]) {
+          if (sm.p_hit[j]) {
+            bu[h] = hash_neighbour(sm.p_hash[j], seed_of(h), vloc_of(h));
+          } else {
+            bw[h] = 0u;
+            bu[h] = -1;
+          }
+          sm.p_u[j] = bu[h];
+          sm.p_w[j] = bw[h];
+        }
+      }
     } else if (NLD > 0 && (nlong > 0 || ntie > 0)) {  // (both need loaded entries)
       // each lane keeps the largest hash of its current piece while its
       // rounds stay inside that piece (a hub row spans every round) and
@@ -1251,7 +1333,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   }
 }
 
-template <bool FIRST, int PPL>
+template <bool FIRST, int PPL, bool UNW>
 __global__ __launch_bounds__(kBlock, PPL > 1 ? 3 : 4) void k_stream(StreamArgs a) {
   __shared__ StreamSmem<kBlock * PPL> sm;
   __shared__ unsigned s_err;
@@ -1259,7 +1341,7 @@ __global__ __launch_bounds__(kBlock, PPL > 1 ? 3 : 4) void k_stream(StreamArgs a
   const Ctl ctl = *a.in.ctl;
   const unsigned long long seed0 = a.c.gseed[0];
   for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) {
-    stream_range<FIRST, PPL>(a, ctl, b, sm, seed0);
+    stream_range<FIRST, PPL, UNW>(a, ctl, b, sm, seed0);
     __syncthreads();
   }
 }
@@ -1302,12 +1384,17 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s, hipEvent_t* ev) {
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_timed(k_plan, dim3(1), dim3(kPlanThreads), s, ev, a);
 }
-hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
-  return launch_timed(k_stream<true, 1>, dim3(grid), dim3(kBlock), s, ev, a);
+hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev) {
+  if (unweighted) return launch_timed(k_stream<true, 1, true>, dim3(grid), dim3(kBlock), s, ev, a);
+  return launch_timed(k_stream<true, 1, false>, dim3(grid), dim3(kBlock), s, ev, a);
 }
-hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late, hipEvent_t* ev) {
-  if (late) return launch_timed(k_stream<false, kLatePPL>, dim3(grid), dim3(kBlock), s, ev, a);
-  return launch_timed(k_stream<false, 1>, dim3(grid), dim3(kBlock), s, ev, a);
+hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late, bool unweighted, hipEvent_t* ev) {
+  if (unweighted) {
+    if (late) return launch_timed(k_stream<false, kLatePPL, true>, dim3(grid), dim3(kBlock), s, ev, a);
+    return launch_timed(k_stream<false, 1, true>, dim3(grid), dim3(kBlock), s, ev, a);
+  }
+  if (late) return launch_timed(k_stream<false, kLatePPL, false>, dim3(grid), dim3(kBlock), s, ev, a);
+  return launch_timed(k_stream<false, 1, false>, dim3(grid), dim3(kBlock), s, ev, a);
 }
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
   return launch_timed(k_mutual, dim3(grid), dim3(kBlock), s, ev, a);
@@ -1317,11 +1404,11 @@ int max_blocks_per_cu_stream(StreamKind kind) {
   int nb = 0;
   hipError_t e;
   if (kind == StreamKind::kFirst)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<true, 1>, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<true, 1, false>, kBlock, 0);
   else if (kind == StreamKind::kCompact)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, 1>, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, 1, false>, kBlock, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, kLatePPL>, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, kLatePPL, false>, kBlock, 0);
   if (e != hipSuccess || nb < 1) nb = 1;
   return nb;
 }

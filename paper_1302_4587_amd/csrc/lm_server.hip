@@ -159,7 +159,7 @@ static lm_status quick_check(const lm_csr* g) {
           a.st = LM_EGRAPH;
           break;
         }
-        const float x = g->w[k];
+        const float x = g->w ? g->w[k] : 1.0f;  // no weight array: unweighted
         if (!(x == x) || x == 1.0f / 0.0f || x == -1.0f / 0.0f) {
           a.st = LM_EWEIGHT;
           break;
@@ -235,7 +235,7 @@ lm_status lm_server_create(lm_ctx* c, const lm_server_opts* o, lm_server** out) 
 
 lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_t* ticket) {
   if (!s || !g || !ticket) return LM_EINVAL;
-  if (g->n < 0 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && (!g->col || !g->w))) return LM_EINVAL;
+  if (g->n < 0 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && !g->col)) return LM_EINVAL;
   if (g->n >= ((int64_t)1 << 31) || g->nnz >= ((int64_t)1 << 31) - 65536) return LM_ETOOBIG;
   if (g->row_ptr[0] != 0 || g->row_ptr[g->n] != g->nnz) return LM_EINVAL;
   ServerCore& S = s->core;
@@ -270,7 +270,10 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
   parallel_copy(r->h_rp, g->row_ptr, (size_t)(g->n + 1) * 8);
   if (g->nnz > 0) {
     parallel_copy(r->h_col, g->col, (size_t)g->nnz * 4);
-    parallel_copy(r->h_w, g->w, (size_t)g->nnz * 4);
+    if (g->w)
+      parallel_copy(r->h_w, g->w, (size_t)g->nnz * 4);
+    else
+      std::fill(r->h_w, r->h_w + g->nnz, 1.0f);  // an unweighted request is served with unit weights
   }
   std::lock_guard<std::mutex> lk(S.mu);
   if (S.stopping) return LM_EINVAL;

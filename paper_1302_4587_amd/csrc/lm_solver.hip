@@ -194,6 +194,7 @@ hipEvent_t Solver::event(size_t i) {
 lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st) {
   const bool prof = (flags & LM_PROFILE) != 0;
   if (++gen == 0) gen = 1;  // 0 marks a never-written mirror slot
+  const bool unweighted = p.w == nullptr;  // no weight array: every edge weighs 1
   std::vector<std::pair<int, size_t>> marks;  // (kind, event index of start)
   size_t evn = 0;
   const uint32_t kmask = (st && st->profile_kinds) ? st->profile_kinds : ((1u << LM_K_KINDS) - 1);
@@ -324,7 +325,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     sa.bstat = (BlockStat*)bstat.p;
     const int gx =
         (int)std::max<int64_t>(1, std::min<int64_t>(pcap_first, p.nnz / std::max(kCap, tun.block_entries) + 1));
-    ENQ(launch_first_argmax(sa, gx, s, timing(LM_K_ARGMAX)));
+    ENQ(launch_first_argmax(sa, gx, s, unweighted, timing(LM_K_ARGMAX)));
     PlanArgs pf = plan_base();
     pf.mode = kPlanFix;
     pf.first = 1;
@@ -359,7 +360,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
         1, std::min<int64_t>(late ? pcap_late : pcap_first,
                              std::max<int64_t>(est_L / std::max(kCap, tun.block_entries),
                                                est_V / (kBlock * (late ? kLatePPL : 1))) + 1));
-    ENQ(launch_compact(sa, gx, s, late, timing(LM_K_COMPACT)));
+    ENQ(launch_compact(sa, gx, s, late, unweighted, timing(LM_K_COMPACT)));
     PlanArgs pa = plan_base();  // sizes the next compaction, a late one
     pa.pcap = pcap_late;
     pa.mode = kPlanFix | kPlanPrefix | kPlanLog | kPlanTick;
@@ -512,13 +513,14 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     const double V1 = nrec > 0 ? (double)recs[0].live_rows : 0.0;
     const double L1 = nrec > 0 ? (double)recs[0].live_entries : 0.0;
     st->k_bytes[LM_K_INIT] = 8.0 * (double)(p.N + 1) + 5.0 * (double)p.N + 16.0 * V1;
-    st->k_bytes[LM_K_ARGMAX] = 16.0 * V1 + 8.0 * L1 + 4.0 * V1;
+    const double eb = unweighted ? 4.0 : 8.0;  // bytes of one entry: col (+ w)
+    st->k_bytes[LM_K_ARGMAX] = 16.0 * V1 + eb * L1 + 4.0 * V1;
     for (int i = 0; i < nrec; ++i) {
       const double L = (double)recs[i].live_entries, V = (double)recs[i].live_rows;
       const double mv = 2.0 * (double)recs[i].matched_edges, md = (double)recs[i].matched_entries;
       const double L2 = (double)recs[i + 1].live_entries, V2 = (double)recs[i + 1].live_rows;
       st->k_bytes[LM_K_MUTUAL] += 24.0 * V + 9.0 * mv;
-      st->k_bytes[LM_K_COMPACT] += 16.0 * V + 9.0 * (L - md) + 8.0 * L2 + 20.0 * V2;
+      st->k_bytes[LM_K_COMPACT] += 16.0 * V + (eb + 1.0) * (L - md) + eb * L2 + 20.0 * V2;
     }
     st->bytes_alg = 0.0;
     for (int k = 0; k < LM_K_KINDS; ++k) st->bytes_alg += st->k_bytes[k];
@@ -541,7 +543,7 @@ static bool csr_shape_ok(const lm_csr* g) {
   if (g->n < 0 || g->nnz < 0) return false;
   if (g->n >= (int64_t)1 << 31) return false;
   if (!g->row_ptr) return false;
-  if (g->nnz > 0 && (!g->col || !g->w)) return false;
+  if (g->nnz > 0 && !g->col) return false;  // w may be null: unweighted
   return true;
 }
 
@@ -560,7 +562,7 @@ lm_status lm::host_check(int64_t n, const int64_t* rp, const int32_t* col, const
     for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
       const int32_t u = col[k];
       if (u < 0 || u >= n || u == v) return LM_EGRAPH;
-      const float x = w[k];
+      const float x = w ? w[k] : 1.0f;  // no weight array: unweighted
       if (!(x == x) || x == 1.0f / 0.0f || x == -1.0f / 0.0f) return LM_EWEIGHT;
       es.push_back(E{(int32_t)std::min<int64_t>(v, u), (int32_t)std::max<int64_t>(v, u), x});
     }
@@ -630,7 +632,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   if (N < 0 || nnz < 0 || G < 1) return LM_EINVAL;
   if (N >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 31) - 65536) return LM_ETOOBIG;
   if (N > 0 && (!row_ptr || !mate)) return LM_EINVAL;
-  if (nnz > 0 && (!col || !w)) return LM_EINVAL;
+  if (nnz > 0 && !col) return LM_EINVAL;  // w == nullptr: unweighted graph
   Solver& S = c->s;
   if (hipSetDevice(S.dev) != hipSuccess) return LM_EDEVICE;
   hipStream_t s = stream ? (hipStream_t)stream : S.own;
@@ -655,7 +657,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
         const int64_t e0 = row_ptr[a];
         std::vector<int64_t> rp((size_t)(b - a + 1));
         for (int64_t v = 0; v <= b - a; ++v) rp[(size_t)v] = row_ptr[a + v] - e0;
-        lm_status hs = host_check(b - a, rp.data(), col + e0, w + e0, rp[(size_t)(b - a)]);
+        lm_status hs = host_check(b - a, rp.data(), col + e0, w ? w + e0 : nullptr, rp[(size_t)(b - a)]);
         if (hs != LM_OK) return hs;
       }
     }
@@ -672,7 +674,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   if (N == 0) return LM_OK;
   // memory: footprint plus staging of host inputs / outputs
   size_t need = solve_footprint(N, nnz, G);
-  if (!in_dev) need += (size_t)(N + 1) * 8 + (size_t)nnz * 8 + 1024;
+  if (!in_dev) need += (size_t)(N + 1) * 8 + (size_t)nnz * (w ? 8 : 4) + 1024;
   if (!out_dev) need += (size_t)N * 4 + 256;
   if (need > S.pool.budget) return LM_ETOOBIG;
   lm_status rs = S.prepare(N, nnz, G, graph_phases != nullptr);
@@ -683,14 +685,14 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   if (!in_dev) {
     if ((rs = S.pool.reserve(S.in_rp, (size_t)(N + 1) * 8)) != LM_OK) return rs;
     if ((rs = S.pool.reserve(S.in_col, (size_t)nnz * 4)) != LM_OK) return rs;
-    if ((rs = S.pool.reserve(S.in_w, (size_t)nnz * 4)) != LM_OK) return rs;
+    if (w && (rs = S.pool.reserve(S.in_w, (size_t)nnz * 4)) != LM_OK) return rs;
     if (hipMemcpyAsync(S.in_rp.p, row_ptr, (size_t)(N + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         (nnz > 0 && hipMemcpyAsync(S.in_col.p, col, (size_t)nnz * 4, hipMemcpyHostToDevice, s) != hipSuccess) ||
-        (nnz > 0 && hipMemcpyAsync(S.in_w.p, w, (size_t)nnz * 4, hipMemcpyHostToDevice, s) != hipSuccess))
+        (w && nnz > 0 && hipMemcpyAsync(S.in_w.p, w, (size_t)nnz * 4, hipMemcpyHostToDevice, s) != hipSuccess))
       return LM_EDEVICE;
     d_rp = (const int64_t*)S.in_rp.p;
     d_col = (const int32_t*)S.in_col.p;
-    d_w = (const float*)S.in_w.p;
+    d_w = w ? (const float*)S.in_w.p : nullptr;
   }
   int32_t* d_mate = mate;
   if (!out_dev) {

@@ -115,6 +115,60 @@ def test_hubs_and_long_rows(ctx, torch_dev):
             _assert_parity(g, seed, mate, st, name)
 
 
+def _unit(g):
+    return lmgen.Graph(g.n, g.row_ptr, g.col, np.ones(g.nnz, np.float32))
+
+
+def test_unweighted_equals_unit_weights(ctx, torch_dev):
+    """w=None (an unweighted graph: every edge weighs 1, Section 1) takes the
+    kernels that neither load nor store weights; the result must equal the
+    oracle on the same graph with unit weights, and the weighted path fed an
+    all-ones array."""
+    import torch
+    rng = np.random.default_rng(21)
+    cases = [("rmat 14", lmgen.rmat(14, 16, seed=3)), ("rmat 13 seed 8", lmgen.rmat(13, 16, seed=8)),
+             ("star 5000", _unit(_star(5000, unit=True))), ("star 2049", _unit(_star(2049, unit=True))),
+             ("rgg 30000", _unit(lmgen.rgg(30000, 10.0, seed=9))),
+             ("er 20000", lmgen.er(20000, 160000, seed=7, weights="unit"))]
+    for it in range(24):
+        n = int(rng.integers(1, 3000))
+        m = int(rng.integers(0, min(n * (n - 1) // 2, 12 * n) + 1))
+        cases.append((f"er it={it} n={n} m={m}", lmgen.er(n, m, int(rng.integers(1, 2**62)), weights="unit")))
+    for name, g in cases:
+        for seed in (1, 12345):
+            print(f"case: unweighted {name} seed={seed}", flush=True)
+            rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr)).to(torch_dev)
+            col = torch.from_numpy(np.ascontiguousarray(g.col)).to(torch_dev)
+            mate, st = ctx.match(rp, col, None, seed=seed)
+            _assert_parity(g, seed, mate.cpu().numpy(), st, f"unweighted {name}")
+    # host inputs, validation and the captured-graph mode without a weight array
+    g = lmgen.rmat(12, 16, seed=5)
+    print("case: unweighted host inputs, checks, hip graph", flush=True)
+    mate, st = ctx.match(g.row_ptr, g.col, None, seed=7, check_graph=True)
+    _assert_parity(g, 7, np.asarray(mate), st, "unweighted host")
+    rp = torch.from_numpy(g.row_ptr).to(torch_dev)
+    col = torch.from_numpy(g.col).to(torch_dev)
+    mate, st = ctx.match(rp, col, None, seed=7, hip_graph=True)
+    _assert_parity(g, 7, mate.cpu().numpy(), st, "unweighted hip graph")
+    # tuning shapes cut rows at other workgroup boundaries
+    base = ctx.tuning()
+    try:
+        for be in (4096, 65536):
+            ctx.set_tuning(block_entries=be, grid_per_cu=1)
+            print(f"case: unweighted tuning be={be}", flush=True)
+            mate, st = ctx.match(rp, col, None, seed=7)
+            _assert_parity(g, 7, mate.cpu().numpy(), st, f"unweighted tuning {be}")
+    finally:
+        ctx.set_tuning(**base)
+    # a batch without a weight array
+    b = lmgen.er_batch(64, seed=5, lg_lo=5.0, lg_hi=11.0, weights="unit")
+    print("case: unweighted batch of 64", flush=True)
+    mate, st, gph = ctx.match_batch(b.vtx_off, b.row_ptr, b.col, None, seed0=3)
+    ref_mate, ref_ph = oracle.local_max_batch(b.vtx_off, b.row_ptr, b.col, b.w, seed0=3)
+    assert np.array_equal(np.asarray(mate), ref_mate)
+    assert np.array_equal(gph, ref_ph)
+
+
 @pytest.mark.parametrize("block_entries", [2048, 4096, 65536])
 def test_tuning_invariance(ctx, torch_dev, block_entries):
     """Range sizes and launch shapes change where rows are cut between
