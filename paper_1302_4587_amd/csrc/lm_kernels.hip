@@ -808,6 +808,10 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         sm.p_ld[j] = (unsigned short)ldt[h];
         if (ldt[h] > 0) sm.rowof[lpre[h]] = (unsigned short)j;
         if (ldt[h] > kLong) sm.longlist[atomicAdd(&sm.nlong, 1)] = j;
+        if (UNW) {
+          sm.p_hash[j] = 0ull;
+          sm.p_hit[j] = 0;
+        }
       }
       if (valid[h]) sm.p_v[j] = rec[h].x;
     }
@@ -878,12 +882,55 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       unsigned rank[kItems];
       unsigned kpm = 0;
       const unsigned long long lt = lanemask_lt();
+      if (UNW) {
+        // Unweighted: every kept entry is a candidate of its piece, so the
+        // lane hashes its kept entries here, keeps the largest hash while its
+        // positions stay in one piece (a hub row spans every round), and
+        // flushes it with an LDS atomic max when the piece changes; p_hit
+        // marks the pieces that had a candidate at all.
+        int cur_j = -1;
+        unsigned long long cur_h = 0ull;
+        bool cur_s = false;
+#pragma unroll
+        for (int jj = 0; jj < kItems; ++jj) {
+          const int j = jp[jj];
+          const bool hs = ok[jj] && (FIRST || st[jj] == 0);
+          unsigned long long hh = 0ull;
+          if (hs) {
+            const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+            hh = edge_hash(S, (unsigned)(sm.p_v[j] - (single ? 0 : sm.p_base[j])), (unsigned)cc[jj]);
+          }
+          if (j != cur_j) {
+            if (cur_s) {
+              atomicMax(&sm.p_hash[cur_j], cur_h);
+              sm.p_hit[cur_j] = 1;
+            }
+            cur_j = j;
+            cur_h = hh;
+            cur_s = hs;
+          } else if (hs && (!cur_s || hh > cur_h)) {
+            cur_h = hh;
+            cur_s = true;
+          }
+        }
+        if (__builtin_amdgcn_readfirstlane(cur_j) == __builtin_amdgcn_readlane(cur_j, 63)) {
+          const bool any = __ballot(cur_s) != 0ull;  // the whole wave ends in one piece
+          cur_h = wave_max_u64(cur_s ? cur_h : 0ull);
+          if (lane == 0 && any) {
+            atomicMax(&sm.p_hash[cur_j], cur_h);
+            sm.p_hit[cur_j] = 1;
+          }
+        } else if (cur_s) {
+          atomicMax(&sm.p_hash[cur_j], cur_h);
+          sm.p_hit[cur_j] = 1;
+        }
+      }
 #pragma unroll
       for (int jj = 0; jj < kItems; ++jj) {
         const int q = tid + kBlock * jj;
         const bool kp = ok[jj] && (FIRST || st[jj] == 0);
-        const unsigned x = kp ? (UNW ? kUnitOrd : ord_weight_bits(__float_as_uint(ww[jj]))) : 0u;
-        if (q < NLD) sm.e_cw[q] = make_uint2(x, (unsigned)cc[jj]);
+        if (!UNW && q < NLD)  // (unweighted pieces were decided above)
+          sm.e_cw[q] = make_uint2(kp ? ord_weight_bits(__float_as_uint(ww[jj])) : 0u, (unsigned)cc[jj]);
         if (!FIRST) {
           const unsigned long long bal = __ballot(kp);
           rank[jj] = (unsigned)__popcll(bal & lt);
@@ -931,14 +978,14 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       bu[h] = -1;
       tie[h] = false;
       if (UNW) {
+        // the hashes of step 3 are complete (barrier after step 3)
+        if (j < nt && ldt[h] > 0 && sm.p_hit[j]) {
+          bw[h] = kUnitOrd;
+          bu[h] = hash_neighbour(sm.p_hash[j], seed_of(h), vloc_of(h));
+        }
         if (j < nt) {
-          tie[h] = ldt[h] > 0;
-          bw[h] = tie[h] ? kUnitOrd : 0u;
           sm.p_w[j] = bw[h];
-          sm.p_u[j] = -1;
-          sm.p_tie[j] = tie[h] ? 1 : 0;
-          sm.p_hash[j] = 0ull;
-          sm.p_hit[j] = 0;
+          sm.p_u[j] = bu[h];
         }
       } else if (j < nt && ldt[h] <= kLong) {
         // largest ordered weight, its first neighbour, and whether it repeats;
@@ -1010,76 +1057,16 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     // all lanes hash the entries that reach their piece's largest weight in
     // striped order, keep the largest hash per piece with an LDS atomic max,
     // and each piece's lane recovers the neighbour by inverting the hash.
-    const int ntie = __syncthreads_count(anytie ? 1 : 0);
-    if (nlong == 0 && ntie > 0 && ntie <= kTieLanes) {
+    const int ntie = UNW ? 0 : __syncthreads_count(anytie ? 1 : 0);
+    if (UNW) {
+      // decided in step 4's first loop
+    } else if (nlong == 0 && ntie > 0 && ntie <= kTieLanes) {
 #pragma unroll
       for (int h = 0; h < kPPL; ++h)
         if (tie[h]) {
           bu[h] = tie_break(sm.e_cw + lpre[h], ldt[h], bw[h], vloc_of(h), seed_of(h));
-          if (UNW && bu[h] < 0) bw[h] = 0u;  // every entry of the piece was dropped
           sm.p_u[tid * kPPL + h] = bu[h];
         }
-    } else if (UNW) {
-      if (NLD > 0) {
-        // as below, but a piece may have no candidate left (all its entries
-        // dropped), so the lanes also mark the pieces they saw a candidate of
-        int cur_j = -1;
-        unsigned long long cur_h = 0ull;
-        bool cur_s = false;
-#pragma unroll
-        for (int jj = 0; jj < kItems; ++jj) {
-          const int q = min(tid + kBlock * jj, NLD - 1);
-          const int j = sm.rowof[q];
-          unsigned long long hh = 0ull;
-          bool hs = false;
-          if (tid + kBlock * jj < NLD) {
-            const uint2 e = sm.e_cw[q];
-            if (e.x != 0u) {
-              const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
-              hh = edge_hash(S, (unsigned)(sm.p_v[j] - (single ? 0 : sm.p_base[j])), e.y);
-              hs = true;
-            }
-          }
-          if (j != cur_j) {
-            if (cur_s) {
-              atomicMax(&sm.p_hash[cur_j], cur_h);
-              sm.p_hit[cur_j] = 1;
-            }
-            cur_j = j;
-            cur_h = hh;
-            cur_s = hs;
-          } else if (hs && (!cur_s || hh > cur_h)) {
-            cur_h = hh;
-            cur_s = true;
-          }
-        }
-        if (__builtin_amdgcn_readfirstlane(cur_j) == __builtin_amdgcn_readlane(cur_j, 63)) {
-          const bool any = __ballot(cur_s) != 0ull;  // the whole wave ends in one piece
-          cur_h = wave_max_u64(cur_s ? cur_h : 0ull);
-          if (lane == 0 && any) {
-            atomicMax(&sm.p_hash[cur_j], cur_h);
-            sm.p_hit[cur_j] = 1;
-          }
-        } else if (cur_s) {
-          atomicMax(&sm.p_hash[cur_j], cur_h);
-          sm.p_hit[cur_j] = 1;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int h = 0; h < kPPL; ++h) {
-        const int j = tid * kPPL + h;
-        if (j < nt && tie[h]) {
-          if (sm.p_hit[j]) {
-            bu[h] = hash_neighbour(sm.p_hash[j], seed_of(h), vloc_of(h));
-          } else {
-            bw[h] = 0u;
-            bu[h] = -1;
-          }
-          sm.p_u[j] = bu[h];
-          sm.p_w[j] = bw[h];
-        }
-      }
     } else if (NLD > 0 && (nlong > 0 || ntie > 0)) {  // (both need loaded entries)
       // each lane keeps the largest hash of its current piece while its
       // rounds stay inside that piece (a hub row spans every round) and
