@@ -15,6 +15,7 @@
 #include <cstring>
 #include <deque>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -123,43 +124,140 @@ static void fifo_loop(ServerCore* S) {
   }
 }
 
-// Runs fn(lo, hi) over [0, n) on up to 16 threads when n is large.
-template <typename F>
-static void parallel_ranges(int64_t n, int64_t grain, F fn) {
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int64_t parts = std::min<int64_t>({(int64_t)std::min(hw, 16u), (n + grain - 1) / grain});
-  if (parts <= 1) {
-    fn((int64_t)0, n, 0);
-    return;
+// Persistent host workers for the per-request work of submit (copy into
+// pinned memory and the graph check): spawning threads per call costs more
+// than the work for mid-size requests, and several submitters share them.
+class HostPool {
+ public:
+  HostPool() {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int n = (int)std::min(hw, 16u) - 1;  // the calling thread works too
+    for (int i = 0; i < n; ++i) th_.emplace_back([this] { work(); });
   }
-  std::vector<std::thread> th;
-  for (int64_t i = 0; i < parts; ++i) th.emplace_back(fn, n * i / parts, n * (i + 1) / parts, (int)i);
-  for (auto& x : th) x.join();
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  int width() const { return (int)th_.size() + 1; }
+  // fn(i) for every i in [0, parts), on the workers and the caller; returns
+  // when all have finished.
+  void run(int parts, const std::function<void(int)>& fn) {
+    Job job{&fn, parts};
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      jobs_.push_back(&job);
+    }
+    cv_.notify_all();
+    for (;;) {
+      int i;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!take(&job, &i)) break;
+      }
+      fn(i);
+      finish(&job);
+    }
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_done_.wait(lk, [&] { return job.done == job.parts; });
+  }
+
+ private:
+  struct Job {
+    const std::function<void(int)>* fn;
+    int parts;
+    int next = 0;
+    int done = 0;
+  };
+  // caller holds mu_: the next index of j, dropping j from the queue once taken
+  bool take(Job* j, int* i) {
+    if (j->next >= j->parts) return false;
+    *i = j->next++;
+    if (j->next >= j->parts) {
+      auto it = std::find(jobs_.begin(), jobs_.end(), j);
+      if (it != jobs_.end()) jobs_.erase(it);
+    }
+    return true;
+  }
+  void finish(Job* j) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (++j->done == j->parts) cv_done_.notify_all();
+  }
+  void work() {
+    for (;;) {
+      Job* j;
+      int i;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || !jobs_.empty(); });
+        if (jobs_.empty()) return;  // stopping
+        j = jobs_.front();
+        if (!take(j, &i)) continue;
+      }
+      (*j->fn)(i);
+      finish(j);
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_, cv_done_;
+  std::deque<Job*> jobs_;
+  std::vector<std::thread> th_;
+  bool stop_ = false;
+};
+
+HostPool& host_pool() {
+  static HostPool pool;
+  return pool;
 }
 
-// Linear-time check of a submitted graph: offsets, ids, self-loops, finite
-// weights, and symmetry as equal multisets of (pair, weight) in the two
-// directions (compared through a sum of 64-bit hashes, -0 folded onto +0).
-// Duplicate entries are not detected here; they cannot stall the phase loop.
-static lm_status quick_check(const lm_csr* g) {
-  const int64_t n = g->n;
-  for (int64_t v = 0; v < n; ++v)
-    if (g->row_ptr[v] < 0 || g->row_ptr[v + 1] < g->row_ptr[v] || g->row_ptr[v + 1] > g->nnz) return LM_EINVAL;
+// Copies a submitted graph into its pinned block and checks it in the same
+// pass over the entries: offsets, ids, self-loops, finite weights, and
+// symmetry as equal multisets of (pair, weight) in the two directions
+// (compared through a sum of 64-bit hashes, -0 folded onto +0). Duplicate
+// entries are not detected here; they cannot stall the phase loop. Work is
+// split into row ranges of about equal entry counts.
+static lm_status copy_and_check(const lm_csr* g, int64_t* h_rp, int32_t* h_col, float* h_w) {
+  const int64_t n = g->n, nnz = g->nnz;
+  const int64_t* rp = g->row_ptr;
+  HostPool& pool = host_pool();
+  const int parts = (int)std::max<int64_t>(1, std::min<int64_t>(pool.width() * 2, (nnz + n) / (1 << 18)));
   struct Acc {
     uint64_t up = 0, down = 0;
     lm_status st = LM_OK;
   };
-  std::vector<Acc> acc(16);
-  parallel_ranges(n, (int64_t)1 << 16, [&](int64_t v0, int64_t v1, int part) {
+  std::vector<Acc> acc((size_t)parts);
+  // part p takes rows [bnd[p], bnd[p+1]): the rows whose first entry lies in
+  // [nnz p / parts, nnz (p+1) / parts) when the offsets are valid (they are
+  // checked below; the bounds stay ordered and in range either way)
+  std::vector<int64_t> bnd((size_t)parts + 1);
+  bnd[0] = 0;
+  for (int q = 1; q < parts; ++q)
+    bnd[(size_t)q] = std::max(bnd[(size_t)q - 1], (int64_t)(std::lower_bound(rp, rp + n, nnz * q / parts) - rp));
+  bnd[(size_t)parts] = n;
+  h_rp[n] = rp[n];
+  auto body = [&](int p) {
+    const int64_t v0 = bnd[(size_t)p], v1 = bnd[(size_t)p + 1];
     Acc a;
+    for (int64_t v = v0; v < v1; ++v) {
+      h_rp[v] = rp[v];
+      if (rp[v] < 0 || rp[v + 1] < rp[v] || rp[v + 1] > nnz) {
+        a.st = LM_EINVAL;
+        break;
+      }
+    }
     for (int64_t v = v0; v < v1 && a.st == LM_OK; ++v) {
-      for (int64_t k = g->row_ptr[v]; k < g->row_ptr[v + 1]; ++k) {
+      for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
         const int32_t u = g->col[k];
+        const float x = g->w ? g->w[k] : 1.0f;  // no weight array: unweighted, served with unit weights
+        h_col[k] = u;
+        h_w[k] = x;
         if (u < 0 || u >= n || u == v) {
           a.st = LM_EGRAPH;
           break;
         }
-        const float x = g->w ? g->w[k] : 1.0f;  // no weight array: unweighted
         if (!(x == x) || x == 1.0f / 0.0f || x == -1.0f / 0.0f) {
           a.st = LM_EWEIGHT;
           break;
@@ -175,8 +273,12 @@ static lm_status quick_check(const lm_csr* g) {
           a.down += h;
       }
     }
-    acc[(size_t)part] = a;
-  });
+    acc[(size_t)p] = a;
+  };
+  if (parts == 1)
+    body(0);
+  else
+    pool.run(parts, body);
   uint64_t up = 0, down = 0;
   for (const Acc& a : acc) {
     if (a.st != LM_OK) return a.st;
@@ -184,12 +286,6 @@ static lm_status quick_check(const lm_csr* g) {
     down += a.down;
   }
   return up == down ? LM_OK : LM_EGRAPH;
-}
-
-static void parallel_copy(void* dst, const void* src, size_t bytes) {
-  parallel_ranges((int64_t)bytes, (int64_t)16 << 20, [&](int64_t a, int64_t b, int) {
-    std::memcpy((char*)dst + a, (const char*)src + a, (size_t)(b - a));
-  });
 }
 
 }  // namespace lm
@@ -248,8 +344,6 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
                            2 * (int64_t)(((size_t)std::max<int64_t>(g->nnz, 1) * 4 + 255) & ~(size_t)255);
     if (g->n > ncap || g->nnz > ecap || staged > scap) return LM_ETOOBIG;
   }
-  const lm_status qc = quick_check(g);
-  if (qc != LM_OK) return qc;
   auto r = std::make_shared<Request>();
   r->n = g->n;
   r->nnz = g->nnz;
@@ -267,14 +361,8 @@ lm_status lm_server_submit(lm_server* s, const lm_csr* g, uint64_t seed, uint64_
   r->off_col = b_rp;
   r->off_w = b_rp + b_e;
   r->block_used = b_rp + 2 * b_e;
-  parallel_copy(r->h_rp, g->row_ptr, (size_t)(g->n + 1) * 8);
-  if (g->nnz > 0) {
-    parallel_copy(r->h_col, g->col, (size_t)g->nnz * 4);
-    if (g->w)
-      parallel_copy(r->h_w, g->w, (size_t)g->nnz * 4);
-    else
-      std::fill(r->h_w, r->h_w + g->nnz, 1.0f);  // an unweighted request is served with unit weights
-  }
+  const lm_status qc = copy_and_check(g, r->h_rp, r->h_col, r->h_w);
+  if (qc != LM_OK) return qc;  // (r returns its block to the pool)
   std::lock_guard<std::mutex> lk(S.mu);
   if (S.stopping) return LM_EINVAL;
   if ((int)S.queue.size() >= S.opts.queue_cap) return LM_EAGAIN;
