@@ -82,7 +82,7 @@ def main():
                     help="enqueue set-up and first phases as one captured HIP graph (LM_GRAPH)")
     ap.add_argument("--serve", action="store_true",
                     help="also run the serving trace: continuous-batching server vs FIFO (extra minutes)")
-    ap.add_argument("--serve-rates", type=str, default="50,150",
+    ap.add_argument("--serve-rates", type=str, default="50,150,300",
                     help="Poisson arrival rates (requests/s) for --serve")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--weight-array", action="store_true",
