@@ -1,12 +1,13 @@
-"""Full-size parity in the launch configuration the benchmark times.
+"""Full-size parity in the launch configurations the benchmark times.
 
 RGG 2^24 (average degree 10, w = 1 - distance): mate[] and the phase log
 against the oracle, element by element. R-MAT scale 24 (edge factor 16,
-unit weights, so the order is the tie-break hash alone): the oracle takes
-about a minute there, so the check is the greedy certificate, which decides
-equality with the greedy matching under the key -- the oracle's result by
-the theorem that local max with a strict key reaches greedy -- in one pass,
-plus the phase-log invariants (Lemma 1: live entries shrink every phase).
+unit weights, so the order is the tie-break hash alone), solved as the bench
+solves it (no weight array: the unweighted kernels): mate[] and the phase log
+against the oracle on the unit-weight graph, element by element; the same
+graph with its all-ones weight array (the weighted kernels) must give the
+same mate[], and passes the greedy certificate (every matched edge is the
+largest-key edge among those not blocked by a larger matched edge).
 """
 import numpy as np
 import pytest
@@ -28,12 +29,12 @@ def ctx():
     c.close()
 
 
-def _solve_device(ctx, g, seed):
+def _solve_device(ctx, g, seed, weights=True):
     import torch
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
-    w = torch.from_numpy(g.w).to(dev)
+    w = torch.from_numpy(g.w).to(dev) if weights else None
     mate, st = ctx.match(rp, col, w, seed=seed)
     out = mate.cpu().numpy()
     del rp, col, w, mate
@@ -63,10 +64,33 @@ def test_rgg_2p24_equals_oracle(ctx):
     _log_invariants(st, mate)
 
 
-def test_rmat_scale24_unit_weights_certificate(ctx):
-    print("case: rmat scale=24 edge_factor=16 unit weights seed=1", flush=True)
-    g = lmgen.rmat(24, 16, seed=1)
+@pytest.fixture(scope="module")
+def rmat24():
+    print("case: generating rmat scale=24 edge_factor=16 unit weights seed=1", flush=True)
+    return lmgen.rmat(24, 16, seed=1)
+
+
+def test_rmat_scale24_unweighted_equals_oracle(ctx, rmat24):
+    g = rmat24
+    print("case: rmat scale=24 unweighted (bench launch configuration) vs oracle", flush=True)
+    mate, st = _solve_device(ctx, g, 1, weights=False)
+    ref_mate, ref_log = oracle.local_max_graph(g, 1)
+    if not np.array_equal(mate, ref_mate):
+        bad = np.flatnonzero(mate != ref_mate)
+        raise AssertionError(f"{len(bad)} vertices differ, first {bad[:5]}")
+    assert st.phases == len(ref_log)
+    assert np.array_equal(st.log[:, 0], 2 * ref_log[:, 0])
+    assert np.array_equal(st.log[:, 1], ref_log[:, 1])
+    assert np.array_equal(st.log[:, 2], ref_log[:, 2])
+    _log_invariants(st, mate)
+
+
+def test_rmat_scale24_weight_array_certificate(ctx, rmat24):
+    g = rmat24
+    print("case: rmat scale=24 with the all-ones weight array", flush=True)
     mate, st = _solve_device(ctx, g, 1)
     viol = oracle.greedy_certificate(g.n, g.row_ptr, g.col, g.w, 1, mate)
     assert viol == 0, f"{viol} certificate violations"
     _log_invariants(st, mate)
+    unw, _ = _solve_device(ctx, g, 1, weights=False)
+    assert np.array_equal(mate, unw), "weighted and unweighted kernels differ on unit weights"
