@@ -154,7 +154,7 @@ lm_status lm_match_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, in
  * of at least this size). */
 typedef struct {
   int32_t block_entries;   /* 2048..4194304 */
-  int32_t grid_per_cu;     /* persistent workgroups per compute unit, 1..16 */
+  int32_t grid_per_cu;     /* workgroups per compute unit at most, 1..16 (default 16: each kernel's resident count) */
   int32_t phases_per_sync; /* phases kept queued past the live set the host checks for emptiness, 1..64 (32 used at most) */
 } lm_tuning;
 

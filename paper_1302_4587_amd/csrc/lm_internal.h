@@ -235,7 +235,7 @@ hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool lat
                           hipEvent_t* ev = nullptr);
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 enum class StreamKind { kFirst, kCompact, kLateCompact };
-int max_blocks_per_cu_stream(StreamKind kind);
+int max_blocks_per_cu_stream(StreamKind kind, bool unweighted = false);
 
 uint64_t premix_seed(uint64_t seed);
 

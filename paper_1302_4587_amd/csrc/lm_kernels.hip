@@ -507,7 +507,12 @@ constexpr int kLong = 32;                        // longer pieces are reduced by
 constexpr int kTieLanes = 4;                     // more tied pieces per batch: striped tie-break
 constexpr int kLongMax = kCap / (kLong + 1) + 1;  // long pieces per batch at most
 
-template <int W>  // pieces in a batch window
+// Entries per lane in a batch: 8 for weighted graphs; 4 for unweighted ones,
+// whose kernels hash every entry and run best with more resident waves.
+template <bool UNW>
+constexpr int stream_items() { return UNW ? 4 : 8; }
+
+template <int W, int IT>  // pieces in a batch window, entries per lane
 struct StreamSmem {
   int p_v[W];
   int p_delta[W];            // entry-buffer offset minus batch position of the piece's first entry
@@ -518,12 +523,12 @@ struct StreamSmem {
   unsigned p_w[W];           // best ordered weight of the piece (0 = none)
   int p_u[W];                // best neighbour of the piece (local id) or -1
   unsigned char p_cont[W];   // the piece continues the previous piece's vertex
-  unsigned short rowof[kCap];   // piece of every loaded position
-  unsigned short kpre[kCap + 2];  // survivors before every loaded position; [NLD] = total
-  uint2 e_cw[kCap];             // {ordered weight or 0 when dropped, local neighbour id}
+  unsigned short rowof[kBlock * IT];     // piece of every loaded position
+  unsigned short kpre[kBlock * IT + 2];  // survivors before every loaded position; [NLD] = total
+  uint2 e_cw[kBlock * IT];               // {ordered weight or 0 when dropped, local neighbour id}
   unsigned long long s_scan[kWaves];
   unsigned s_max[kWaves];
-  unsigned s_cnt[kItems * kWaves];
+  unsigned s_cnt[IT * kWaves];
   unsigned s_emit[kWaves];
   unsigned long long p_hash[W];  // largest tie-break hash per tied piece
   unsigned char p_tie[W];        // the piece's largest weight repeats
@@ -631,9 +636,11 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // neither loaded nor stored, every loaded piece is tied, the weight scans are
 // skipped and the hash pass decides every piece.
 template <bool FIRST, int PPL, bool UNW>
-__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL>& sm,
+__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<UNW>()>& sm,
                              unsigned long long seed0) {
   constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f (0x3f800000 | sign bit)
+  constexpr int kItems = stream_items<UNW>();  // (shadows the defaults of the other kernels)
+  constexpr int kCap = kBlock * kItems;
   constexpr int kPPL = PPL;
   constexpr int kW = kBlock * kPPL;  // pieces in a batch window
   const int tid = threadIdx.x;
@@ -1321,8 +1328,8 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
 }
 
 template <bool FIRST, int PPL, bool UNW>
-__global__ __launch_bounds__(kBlock, PPL > 1 ? 3 : 4) void k_stream(StreamArgs a) {
-  __shared__ StreamSmem<kBlock * PPL> sm;
+__global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (PPL > 1 ? 3 : 4)) void k_stream(StreamArgs a) {
+  __shared__ StreamSmem<kBlock * PPL, stream_items<UNW>()> sm;
   __shared__ unsigned s_err;
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
@@ -1387,17 +1394,22 @@ hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_
   return launch_timed(k_mutual, dim3(grid), dim3(kBlock), s, ev, a);
 }
 
-int max_blocks_per_cu_stream(StreamKind kind) {
+template <typename K>
+static int blocks_per_cu(K kernel) {
   int nb = 0;
-  hipError_t e;
-  if (kind == StreamKind::kFirst)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<true, 1, false>, kBlock, 0);
-  else if (kind == StreamKind::kCompact)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, 1, false>, kBlock, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stream<false, kLatePPL, false>, kBlock, 0);
-  if (e != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
   return nb;
+}
+
+int max_blocks_per_cu_stream(StreamKind kind, bool unweighted) {
+  if (unweighted) {
+    if (kind == StreamKind::kFirst) return blocks_per_cu(k_stream<true, 1, true>);
+    if (kind == StreamKind::kCompact) return blocks_per_cu(k_stream<false, 1, true>);
+    return blocks_per_cu(k_stream<false, kLatePPL, true>);
+  }
+  if (kind == StreamKind::kFirst) return blocks_per_cu(k_stream<true, 1, false>);
+  if (kind == StreamKind::kCompact) return blocks_per_cu(k_stream<false, 1, false>);
+  return blocks_per_cu(k_stream<false, kLatePPL, false>);
 }
 
 uint64_t premix_seed(uint64_t seed) { return host_mix64(seed + kGoldenGamma); }

@@ -53,6 +53,7 @@ struct Solver {
   int bpc_stream = 1;  // resident compaction workgroups per CU
   int bpc_first = 1;   // resident first-argmax workgroups per CU
   int bpc_late = 1;    // resident late-compaction workgroups per CU
+  int bpc_stream_u = 1, bpc_first_u = 1, bpc_late_u = 1;  // the same for unweighted graphs
   bool busy_server = false;
   int last_phases = 0;
 

@@ -149,8 +149,11 @@ lm_status Solver::init_device(int device, size_t budget) {
   bpc_stream = max_blocks_per_cu_stream(StreamKind::kCompact);
   bpc_first = max_blocks_per_cu_stream(StreamKind::kFirst);
   bpc_late = max_blocks_per_cu_stream(StreamKind::kLateCompact);
+  bpc_stream_u = max_blocks_per_cu_stream(StreamKind::kCompact, true);
+  bpc_first_u = max_blocks_per_cu_stream(StreamKind::kFirst, true);
+  bpc_late_u = max_blocks_per_cu_stream(StreamKind::kLateCompact, true);
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
-  tun.grid_per_cu = bpc_stream;
+  tun.grid_per_cu = 16;  // at most: the resident count of each kernel caps it
   tun.phases_per_sync = 1;  // phases queued past the live set the host checks
   return LM_OK;
 }
@@ -223,11 +226,15 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     }                                      \
   } while (0)
 
-  const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_stream))));
+  // resident workgroups per CU of the kernels this solve uses
+  const int bs = unweighted ? bpc_stream_u : bpc_stream;
+  const int bf = unweighted ? bpc_first_u : bpc_first;
+  const int bl = unweighted ? bpc_late_u : bpc_late;
+  const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bs))));
   // R_1 feeds the first argmax and the first compaction; later live sets feed
   // compactions with the wider piece window, which fit fewer workgroups per CU
-  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(bpc_first, bpc_stream))));
-  const int pcap_late = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bpc_late))));
+  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(bf, bs))));
+  const int pcap_late = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bl))));
   const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
   Ctl* dctl = (Ctl*)ctl.p;
   Totals* dtot = (Totals*)totals.p;
