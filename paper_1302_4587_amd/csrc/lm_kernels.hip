@@ -507,10 +507,12 @@ constexpr int kLong = 32;                        // longer pieces are reduced by
 constexpr int kTieLanes = 4;                     // more tied pieces per batch: striped tie-break
 constexpr int kLongMax = kCap / (kLong + 1) + 1;  // long pieces per batch at most
 
-// Entries per lane in a batch: 8 for weighted graphs; 4 for unweighted ones,
-// whose kernels hash every entry and run best with more resident waves.
-template <bool UNW>
-constexpr int stream_items() { return UNW ? 4 : 8; }
+// Entries per lane in a batch (measured on the shapes of RGG, R-MAT and the
+// batch): weighted kernels 6 (5 workgroups per CU with one piece per lane),
+// unweighted kernels 4 (6 per CU): they hash every entry and gain most from
+// resident waves.
+template <bool FIRST, bool UNW>
+constexpr int stream_items() { return UNW ? 4 : 6; }
 
 template <int W, int IT>  // pieces in a batch window, entries per lane
 struct StreamSmem {
@@ -636,10 +638,10 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // neither loaded nor stored, every loaded piece is tied, the weight scans are
 // skipped and the hash pass decides every piece.
 template <bool FIRST, int PPL, bool UNW>
-__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<UNW>()>& sm,
+__device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()>& sm,
                              unsigned long long seed0) {
   constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f (0x3f800000 | sign bit)
-  constexpr int kItems = stream_items<UNW>();  // (shadows the defaults of the other kernels)
+  constexpr int kItems = stream_items<FIRST, UNW>();  // (shadows the defaults of the other kernels)
   constexpr int kCap = kBlock * kItems;
   constexpr int kPPL = PPL;
   constexpr int kW = kBlock * kPPL;  // pieces in a batch window
@@ -1328,8 +1330,8 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
 }
 
 template <bool FIRST, int PPL, bool UNW>
-__global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (PPL > 1 ? 3 : 4)) void k_stream(StreamArgs a) {
-  __shared__ StreamSmem<kBlock * PPL, stream_items<UNW>()> sm;
+__global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (PPL > 1 ? 3 : 5)) void k_stream(StreamArgs a) {
+  __shared__ StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()> sm;
   __shared__ unsigned s_err;
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
