@@ -53,7 +53,7 @@ struct Ctl {
   int heads;       // live vertices
   int P;           // workgroups for the compaction over this live set
   int Pm;          // workgroups for the mutual check over this live set
-  int pad;
+  int Pf;          // workgroups for the first argmax over this live set (R_1), 0: P
 };
 
 // A row cut by a workgroup boundary: the partial result of one side.
@@ -173,6 +173,7 @@ struct PlanArgs {
   int* rpre_new;
   Ctl* ctl_new;
   int pcap, pmcap;       // workgroup caps for the next phase
+  int pcap_first;        // workgroup cap of the first argmax over the new live set (R_1), 0: none
   int min_per_block;     // virtual entries per compaction workgroup at least
   int pieces_per_block;  // pieces per compaction workgroup at least (0: no bound)
   // log

@@ -207,8 +207,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
   __syncthreads();
   if (s_err) return;
   const Ctl prev = a.ctl_prev ? *a.ctl_prev : Ctl{0, 0, 0, 0, 0, 0, 0};
+  // ranges of the launch being fixed: the first argmax may split R_1 its own way
+  const int Pfix = (a.first && prev.Pf > 0) ? prev.Pf : prev.P;
   if (a.mode & kPlanFix) {
-    for (int b = tid; b < prev.P; b += kPlanThreads) {
+    for (int b = tid; b < Pfix; b += kPlanThreads) {
       const Part pl = a.parts[2 * b + 1];
       if (pl.v < 0) continue;  // block b does not own a cut row
       Key best;
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
       best.u = pl.u;
       int head_row = pl.kept > 0 ? pl.out_row : -1;
       int pieces = pl.out_row >= 0 ? 1 : 0;
-      for (int b2 = b + 1; b2 < prev.P; ++b2) {
+      for (int b2 = b + 1; b2 < Pfix; ++b2) {
         const Part pf = a.parts[2 * b2];
         if (pf.v != pl.v) break;  // defensive: the chain always continues here
         Key k;
@@ -302,9 +304,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
       long long P = (te + a.min_per_block - 1) / a.min_per_block;
       if (a.pieces_per_block > 0) P = std::max<long long>(P, ((long long)tr + a.pieces_per_block - 1) / a.pieces_per_block);
       c.P = (int)std::max<long long>(te > 0 ? 1 : 0, std::min<long long>(P, a.pcap));
+      c.Pf = a.pcap_first > 0 ? (int)std::max<long long>(te > 0 ? 1 : 0, std::min<long long>(P, a.pcap_first)) : 0;
       long long Pm = ((long long)tr + kMutualRound - 1) / kMutualRound;
       c.Pm = (int)std::max<long long>(tr > 0 ? 1 : 0, std::min<long long>(Pm, a.pmcap));
-      c.pad = 0;
       *a.ctl_new = c;
     }
   }
@@ -508,11 +510,11 @@ constexpr int kTieLanes = 4;                     // more tied pieces per batch: 
 constexpr int kLongMax = kCap / (kLong + 1) + 1;  // long pieces per batch at most
 
 // Entries per lane in a batch (measured on the shapes of RGG, R-MAT and the
-// batch): weighted kernels 6 (5 workgroups per CU with one piece per lane),
-// unweighted kernels 4 (6 per CU): they hash every entry and gain most from
-// resident waves.
+// batch): the weighted first argmax 8 (4 workgroups per CU), weighted
+// compactions 6 (5 per CU with one piece per lane), unweighted kernels 4 (6
+// per CU): they hash every entry and gain most from resident waves.
 template <bool FIRST, bool UNW>
-constexpr int stream_items() { return UNW ? 4 : 6; }
+constexpr int stream_items() { return UNW ? 4 : (FIRST ? 8 : 6); }
 
 template <int W, int IT>  // pieces in a batch window, entries per lane
 struct StreamSmem {
@@ -1330,11 +1332,12 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
 }
 
 template <bool FIRST, int PPL, bool UNW>
-__global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (PPL > 1 ? 3 : 5)) void k_stream(StreamArgs a) {
+__global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL > 1 ? 3 : 5))) void k_stream(StreamArgs a) {
   __shared__ StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()> sm;
   __shared__ unsigned s_err;
   if (block_failed(a.c.totals, &s_err)) return;
-  const Ctl ctl = *a.in.ctl;
+  Ctl ctl = *a.in.ctl;
+  if (FIRST && ctl.Pf > 0) ctl.P = ctl.Pf;  // the first argmax's own split of R_1
   const unsigned long long seed0 = a.c.gseed[0];
   for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) {
     stream_range<FIRST, PPL, UNW>(a, ctl, b, sm, seed0);

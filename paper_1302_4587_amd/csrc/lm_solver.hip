@@ -231,9 +231,10 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   const int bf = unweighted ? bpc_first_u : bpc_first;
   const int bl = unweighted ? bpc_late_u : bpc_late;
   const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bs))));
-  // R_1 feeds the first argmax and the first compaction; later live sets feed
-  // compactions with the wider piece window, which fit fewer workgroups per CU
-  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(bf, bs))));
+  // R_1 feeds the first argmax and the first compaction, each split to its
+  // own resident count; later live sets feed compactions with the wider piece
+  // window, which fit fewer workgroups per CU
+  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, bf)));
   const int pcap_late = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bl))));
   const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
   Ctl* dctl = (Ctl*)ctl.p;
@@ -313,9 +314,10 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ia.runs_out = (Run*)runs[0].p;
     ia.rows_out = (int4*)rows[0].p;
     ENQ(launch_init(ia, s, timing(LM_K_INIT)));
-    PlanArgs pa = plan_base();
+    PlanArgs pa = plan_base();  // R_1: split for the first compaction and, apart, the first argmax
     pa.mode = kPlanPrefix;
-    pa.pcap = pcap_first;
+    pa.pcap = pcap;
+    pa.pcap_first = pcap_first;
     pa.pieces_per_block = kBlock;
     pa.ctl_prev = nullptr;
     pa.runs_new = (const Run*)runs[0].p;
@@ -364,7 +366,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     sa.bstat = (BlockStat*)bstat.p;
     const bool late = t > 1;
     const int gx = (int)std::max<int64_t>(
-        1, std::min<int64_t>(late ? pcap_late : pcap_first,
+        1, std::min<int64_t>(late ? pcap_late : pcap,
                              std::max<int64_t>(est_L / std::max(kCap, tun.block_entries),
                                                est_V / (kBlock * (late ? kLatePPL : 1))) + 1));
     ENQ(launch_compact(sa, gx, s, late, unweighted, timing(LM_K_COMPACT)));
