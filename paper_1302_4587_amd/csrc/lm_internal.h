@@ -27,8 +27,8 @@ namespace lm {
 
 constexpr int kBlock = 256;            // lanes per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kItems = 8;              // entries per lane per batch
-constexpr int kCap = kBlock * kItems;  // live entries loaded per batch
+constexpr int kItems = 8;              // entries per lane per round of k_init (the stream kernels pick their own)
+constexpr int kCap = kBlock * kItems;  // vertices per round of k_init; the smallest range a workgroup takes
 constexpr int kLatePPL = 2;                 // pieces per lane in compactions after the first
 constexpr int kMutualRound = kBlock * 4;    // pieces per mutual-check round of a workgroup
 constexpr int kMaxBlocks = 4096;       // run table capacity

@@ -479,7 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
 // ---------------------------------------------------------------- stream
 
 // Compaction (and first argmax) over one virtual range [E0, E1) of the live
-// set, in batches of at most kBlock * PPL pieces and kCap loaded entries:
+// set, in batches of at most kBlock * PPL pieces and kBlock * kItems loaded
+// entries (kItems from stream_items: 4 to 8 by kernel kind):
 //   1. lane j takes piece cur_k + j; a prefix scan decides which pieces fit;
 //   2. continuity flags (a piece continuing the previous piece's vertex) and,
 //      for every loaded position, the piece it belongs to;
