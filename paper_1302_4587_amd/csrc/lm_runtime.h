@@ -70,8 +70,17 @@ struct Solver {
   LogRec* h_log = nullptr;
   LogRec* d_log = nullptr;
   unsigned gen = 0;  // solves so far: tells this solve's mirror records from older ones
+  // per-graph tables as last uploaded (base, premixed seed, vertex offsets),
+  // the device buffers they went to, and their pinned staging area
+  std::vector<int32_t> t_gbase;
+  std::vector<uint64_t> t_gseed;
+  std::vector<int64_t> t_vtxoff;
+  const void* t_dev[3] = {nullptr, nullptr, nullptr};
+  void* t_pinned = nullptr;
+  size_t t_pinned_cap = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipEvent_t e_order = nullptr;  // orders solves after the legacy default stream
+  hipEvent_t e_order = nullptr;   // orders a captured solve after the legacy default stream
+  hipEvent_t e_tables = nullptr;  // after the last per-graph table upload
   std::vector<hipEvent_t> evpool;
 
   lm_status init_device(int device, size_t budget);

@@ -116,7 +116,7 @@ static void fifo_loop(ServerCore* S) {
       std::memset(&stats, 0, sizeof(stats));
       r->mate.assign((size_t)r->n, -1);
       st = solve_locked(S->ctx, r->n, r->nnz, 1, nullptr, r->h_rp, r->h_col, r->h_w, nullptr, r->seed,
-                        r->mate.data(), 0u, nullptr, &stats, nullptr);
+                        r->mate.data(), 0u, (void*)solver_of(S->ctx).own, &stats, nullptr);  // not the default stream
       r->phases = stats.phases;
       r->matched = stats.matched_edges;
     }
@@ -497,7 +497,7 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
           lm_stats st;
           std::memset(&st, 0, sizeof(st));
           rs = solve_locked(c, N, nnz, graphs, vtx_off, row_ptr, col, w, nullptr, 1, mate, fl | LM_OUT_DEVICE,
-                            nullptr, &st, nullptr);
+                            (void*)sv.own, &st, nullptr);
           ms.push_back(st.device_ms);
         }
         if (rs != LM_OK) break;

@@ -114,9 +114,11 @@ lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
   RES(parts, (size_t)kMaxBlocks * 2 * sizeof(Part));
   RES(bstat, (size_t)kMaxBlocks * sizeof(BlockStat));
   RES(mcount, (size_t)kMaxBlocks * 4);
+  const size_t tb0 = gbase.bytes + gseed.bytes + vtxoff.bytes;
   RES(gbase, (size_t)G * 4);
   RES(gseed, (size_t)G * 8);
   RES(vtxoff, (size_t)(G + 1) * 8);
+  if (gbase.bytes + gseed.bytes + vtxoff.bytes != tb0) t_dev[0] = t_dev[1] = t_dev[2] = nullptr;  // reallocated
   if (want_gphase) RES(gphase, (size_t)G * 4);
   RES(totals, sizeof(Totals));
 #undef RES
@@ -140,6 +142,7 @@ lm_status Solver::init_device(int device, size_t budget) {
   if (hipHostMalloc((void**)&h_totals, sizeof(Totals)) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreateWithFlags(&e_order, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
+  if (hipEventCreateWithFlags(&e_tables, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
   const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
   if (hipHostMalloc((void**)&h_mir, sizeof(PhaseMirror) * kMirrorSlots, mapped) != hipSuccess) return LM_EDEVICE;
   if (hipHostMalloc((void**)&h_log, sizeof(LogRec) * (size_t)kLogCap, mapped) != hipSuccess) return LM_EDEVICE;
@@ -172,8 +175,13 @@ void Solver::shutdown() {
   if (e1) (void)hipEventDestroy(e1);
   if (e_order) (void)hipEventDestroy(e_order);
   e_order = nullptr;
+  if (e_tables) (void)hipEventDestroy(e_tables);
+  e_tables = nullptr;
   if (h_totals) (void)hipHostFree(h_totals);
   if (h_mir) (void)hipHostFree(h_mir);
+  if (t_pinned) (void)hipHostFree(t_pinned);
+  t_pinned = nullptr;
+  t_pinned_cap = 0;
   if (h_log) (void)hipHostFree(h_log);
   h_mir = d_mir = nullptr;
   h_log = d_log = nullptr;
@@ -644,12 +652,13 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   if (nnz > 0 && !col) return LM_EINVAL;  // w == nullptr: unweighted graph
   Solver& S = c->s;
   if (hipSetDevice(S.dev) != hipSuccess) return LM_EDEVICE;
-  hipStream_t s = stream ? (hipStream_t)stream : S.own;
-  if (!stream) {
-    // The caller named the legacy default stream (or none): order the solve
-    // after everything already queued there (for example the kernels that
-    // produced device inputs). The context's own stream does not block on
-    // the default stream by itself.
+  // The caller named the legacy default stream (or none): the solve runs on it,
+  // after everything already queued there (for example the kernels that
+  // produced device inputs). A captured graph needs a stream of its own, which
+  // then waits for the default stream.
+  const bool own_stream = !stream && (flags & LM_GRAPH) && !(flags & LM_PROFILE);
+  hipStream_t s = stream ? (hipStream_t)stream : (own_stream ? S.own : nullptr);
+  if (own_stream) {
     if (hipEventRecord(S.e_order, nullptr) != hipSuccess || hipStreamWaitEvent(s, S.e_order, 0) != hipSuccess) {
       (void)hipGetLastError();
       return LM_EDEVICE;
@@ -718,10 +727,40 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
     hv[(size_t)g] = h_vtx_off ? h_vtx_off[g] : 0;
   }
   hv[(size_t)G] = h_vtx_off ? h_vtx_off[G] : N;
-  if (hipMemcpyAsync(S.gbase.p, hb.data(), (size_t)G * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(S.gseed.p, hs.data(), (size_t)G * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(S.vtxoff.p, hv.data(), (size_t)(G + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess)
-    return LM_EDEVICE;
+  // The tables live on the device between solves: upload only what changed
+  // (repeated solves of one shape and seed upload nothing), from pinned memory.
+  if (hb != S.t_gbase || hs != S.t_gseed || hv != S.t_vtxoff || S.t_dev[0] != S.gbase.p ||
+      S.t_dev[1] != S.gseed.p || S.t_dev[2] != S.vtxoff.p) {
+    const size_t bytes = (size_t)G * 4 + (size_t)G * 8 + (size_t)(G + 1) * 8 + 64;
+    if (S.t_pinned_cap < bytes) {
+      if (S.t_pinned) (void)hipHostFree(S.t_pinned);
+      S.t_pinned = nullptr;
+      S.t_pinned_cap = 0;
+      if (hipHostMalloc(&S.t_pinned, bytes) != hipSuccess) return LM_ENOMEM;
+      S.t_pinned_cap = bytes;
+    }
+    // the last copies out of the staging area must have landed before it is rewritten
+    if (hipEventSynchronize(S.e_tables) != hipSuccess) return LM_EDEVICE;
+    char* ph = (char*)S.t_pinned;
+    int64_t* pv = (int64_t*)ph;
+    uint64_t* ps = (uint64_t*)(ph + (size_t)(G + 1) * 8);
+    int32_t* pb = (int32_t*)(ph + (size_t)(G + 1) * 8 + (size_t)G * 8);
+    std::memcpy(pv, hv.data(), (size_t)(G + 1) * 8);
+    std::memcpy(ps, hs.data(), (size_t)G * 8);
+    std::memcpy(pb, hb.data(), (size_t)G * 4);
+    S.t_dev[0] = S.t_dev[1] = S.t_dev[2] = nullptr;  // invalid until the copies are queued
+    if (hipMemcpyAsync(S.gbase.p, pb, (size_t)G * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(S.gseed.p, ps, (size_t)G * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(S.vtxoff.p, pv, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(S.e_tables, s) != hipSuccess)
+      return LM_EDEVICE;
+    S.t_gbase = std::move(hb);
+    S.t_gseed = std::move(hs);
+    S.t_vtxoff = std::move(hv);
+    S.t_dev[0] = S.gbase.p;
+    S.t_dev[1] = S.gseed.p;
+    S.t_dev[2] = S.vtxoff.p;
+  }
   Problem p;
   p.N = N;
   p.nnz = nnz;
