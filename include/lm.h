@@ -79,6 +79,7 @@ typedef int32_t lm_status;
 #define LM_GRAPH 0x10u       /* enqueue the set-up and the first phases as one captured
                                 HIP graph launch (one launch, no host round trip);
                                 ignored together with LM_PROFILE; same results */
+#define LM_WEIGHT_SUM 0x20u  /* after the solve, set stats->matched_weight (needs stats) */
 
 typedef struct lm_ctx lm_ctx;
 typedef struct lm_server lm_server;
@@ -123,6 +124,14 @@ typedef struct {
   int32_t k_launches[LM_K_KINDS]; /* LM_PROFILE: launches per kernel kind */
   double k_ms[LM_K_KINDS];        /* LM_PROFILE: summed event time per kind */
   double k_bytes[LM_K_KINDS];     /* algorithmic bytes per kind */
+  double matched_weight;  /* LM_WEIGHT_SUM: w(M), the sum of w(e) over the matched edges
+                             (|M| for an unweighted graph; over all graphs of a batch);
+                             0 otherwise. Found by two small kernels after the solve (not
+                             part of device_ms): every matched vertex looks up the weight
+                             of its matched entry in its input row, the sum over both
+                             endpoints is halved. The additions run in double in a fixed
+                             order for a given n, so repeated calls agree exactly; the
+                             value is within 2|M| * 2^-53 * w(M) of the exact sum. */
 } lm_stats;
 
 /* Creates a context on HIP device `device`. hbm_budget_bytes caps the

@@ -18,7 +18,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (KERNEL_KINDS, LM_CHECK_GRAPH, LM_GRAPH, LM_IN_DEVICE, LM_OUT_DEVICE, LM_PROFILE, LM_SERVE_BATCHED,
-                   LM_SERVE_FIFO, LMError, check)
+                   LM_SERVE_FIFO, LM_WEIGHT_SUM, LMError, check)
 
 __all__ = ["Context", "Server", "MatchStats", "LMError", "library_path", "LM_SERVE_BATCHED", "LM_SERVE_FIFO"]
 
@@ -61,16 +61,18 @@ class MatchStats:
     kernel_launches: dict = field(default_factory=dict)
     kernel_ms: dict = field(default_factory=dict)
     kernel_bytes: dict = field(default_factory=dict)
+    matched_weight: float | None = None  # w(M), when asked for (weight_sum=True)
 
 
-def _stats_out(st: _lib.Stats, logbuf) -> MatchStats:
+def _stats_out(st: _lib.Stats, logbuf, weight_sum=False) -> MatchStats:
     n = int(st.log_len)
     log = np.array([[r.live_entries, r.live_rows, r.matched_edges, r.matched_entries] for r in logbuf[:n]],
                    dtype=np.int64).reshape(n, 4)
     return MatchStats(int(st.phases), int(st.matched_edges), float(st.device_ms), float(st.bytes_alg), log,
                       {k: int(st.k_launches[i]) for i, k in enumerate(KERNEL_KINDS)},
                       {k: float(st.k_ms[i]) for i, k in enumerate(KERNEL_KINDS)},
-                      {k: float(st.k_bytes[i]) for i, k in enumerate(KERNEL_KINDS)})
+                      {k: float(st.k_bytes[i]) for i, k in enumerate(KERNEL_KINDS)},
+                      float(st.matched_weight) if weight_sum else None)
 
 
 class Context:
@@ -127,10 +129,10 @@ class Context:
         check(self._lib.lm_set_tuning(self._h, ctypes.byref(t)), "lm_set_tuning")
 
     # -------------------------------------------------------------- solves
-    def _flags_stream(self, dev_in, dev_out, check_graph, profile, stream, hip_graph=False):
+    def _flags_stream(self, dev_in, dev_out, check_graph, profile, stream, hip_graph=False, weight_sum=False):
         flags = (LM_IN_DEVICE if dev_in else 0) | (LM_OUT_DEVICE if dev_out else 0)
         flags |= (LM_CHECK_GRAPH if check_graph else 0) | (LM_PROFILE if profile else 0)
-        flags |= LM_GRAPH if hip_graph else 0
+        flags |= (LM_GRAPH if hip_graph else 0) | (LM_WEIGHT_SUM if weight_sum else 0)
         s = None
         if stream is not None:
             s = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", None)
@@ -140,9 +142,10 @@ class Context:
         return flags, s
 
     def match(self, row_ptr, col, w, seed: int = 1, mate=None, *, check_graph=False, profile=False, stream=None,
-              log_cap: int = 4096, hip_graph=False, profile_kinds=None):
+              log_cap: int = 4096, hip_graph=False, profile_kinds=None, weight_sum=False):
         """Solves one graph. Returns (mate, MatchStats). hip_graph=True enqueues the
-        set-up and first phases as one captured HIP graph (LM_GRAPH)."""
+        set-up and first phases as one captured HIP graph (LM_GRAPH); weight_sum=True
+        also returns w(M) in MatchStats.matched_weight (LM_WEIGHT_SUM)."""
         n = int(row_ptr.shape[0]) - 1
         nnz = int(col.shape[0])
         rp, d0, k0 = _ptr(row_ptr, np.int64)
@@ -157,7 +160,7 @@ class Context:
             else:
                 mate = np.empty(max(n, 0), dtype=np.int32)
         mp, dm, km = _ptr(mate, np.int32)
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum)
         g = _lib.Csr(n, nnz, rp, cp, wp)
         logbuf = self._logbuf(log_cap)
         st = _lib.Stats()
@@ -167,10 +170,11 @@ class Context:
             st.profile_kinds = sum(1 << KERNEL_KINDS.index(k) for k in set(profile_kinds))
         check(self._lib.lm_match(self._h, ctypes.byref(g), seed & (2**64 - 1), mp, flags, s, ctypes.byref(st)),
               "lm_match")
-        return mate, _stats_out(st, logbuf)
+        return mate, _stats_out(st, logbuf, weight_sum)
 
     def match_batch(self, vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1, mate=None, *, check_graph=False,
-                    profile=False, stream=None, log_cap: int = 4096, want_graph_phases=True, hip_graph=True):
+                    profile=False, stream=None, log_cap: int = 4096, want_graph_phases=True, hip_graph=True,
+                    weight_sum=False):
         """Solves a batch (disjoint union, local ids) in one captured HIP graph
         launch unless hip_graph=False or profile=True. Returns (mate, MatchStats,
         graph_phases)."""
@@ -195,7 +199,7 @@ class Context:
         if seeds is not None:
             sk = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
             sp = sk.ctypes.data
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum)
         gph = np.zeros(G, dtype=np.int32) if want_graph_phases else None
         logbuf = self._logbuf(log_cap)
         st = _lib.Stats()
@@ -204,7 +208,7 @@ class Context:
         check(self._lib.lm_match_batch(self._h, G, vo.ctypes.data, nnz, rp, cp, wp, sp, seed0 & (2**64 - 1), mp,
                                        flags, s, ctypes.byref(st),
                                        gph.ctypes.data if gph is not None else None), "lm_match_batch")
-        return mate, _stats_out(st, logbuf), gph
+        return mate, _stats_out(st, logbuf, weight_sum), gph
 
     def autotune_batch(self, vtx_off, row_ptr, col, w, cache_path=None) -> dict:
         vo = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))

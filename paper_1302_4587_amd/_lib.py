@@ -32,6 +32,7 @@ LM_OUT_DEVICE = 0x2
 LM_CHECK_GRAPH = 0x4
 LM_PROFILE = 0x8
 LM_GRAPH = 0x10
+LM_WEIGHT_SUM = 0x20
 
 LM_K_INIT, LM_K_ARGMAX, LM_K_MUTUAL, LM_K_COMPACT, LM_K_PLAN = range(5)
 KERNEL_KINDS = ("init", "argmax", "mutual", "compact", "plan")
@@ -61,7 +62,7 @@ class Stats(ctypes.Structure):
                 ("device_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double),
                 ("log", ctypes.POINTER(PhaseRec)), ("log_cap", ctypes.c_int32),
                 ("profile_kinds", ctypes.c_uint32), ("k_launches", ctypes.c_int32 * 5), ("k_ms", ctypes.c_double * 5),
-                ("k_bytes", ctypes.c_double * 5)]
+                ("k_bytes", ctypes.c_double * 5), ("matched_weight", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):

@@ -18,6 +18,7 @@ namespace lm {
 
 constexpr int kLogCap = 1 << 16;  // device phase records kept per solve
 constexpr int kGraphPhases = 12;  // phases in the captured graph (LM_GRAPH)
+constexpr int kWeightSumMaxGrid = 1024;  // workgroups of the matched-weight sum (LM_WEIGHT_SUM)
 
 struct DevBuf {
   void* p = nullptr;
@@ -61,6 +62,7 @@ struct Solver {
   DevBuf ctl, parts, bstat, mcount;
   DevBuf gbase, gseed, vtxoff, gphase, totals;
   DevBuf in_rp, in_col, in_w, out_mate;
+  DevBuf wsum;  // kWeightSumMaxGrid partial sums, then the total
 
   Totals* h_totals = nullptr;
   // mapped pinned host memory the plan kernel writes: one record per live set
@@ -89,6 +91,12 @@ struct Solver {
   lm_status run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st);
   hipEvent_t event(size_t i);
 };
+
+// Matched weight (LM_WEIGHT_SUM): partial sums go to scratch[0, grid) and the
+// total to scratch[kWeightSumMaxGrid]; scratch holds kWeightSumMaxGrid + 1 doubles.
+int weight_sum_grid(long long N);
+hipError_t launch_weight_sum(const long long* row_ptr, const int* col, const float* w, const int* mate, long long N,
+                             double* scratch, hipStream_t s);
 
 const char* status_text(lm_status st);
 lm_status dev_status(hipError_t e);

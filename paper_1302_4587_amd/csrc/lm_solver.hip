@@ -167,7 +167,7 @@ void Solver::shutdown() {
   DevBuf* all[] = {&C,       &state,   &rows[0], &rows[1], &ecol[0], &ecol[1], &ew[0],   &ew[1],
                    &runs[0], &runs[1], &epre[0], &epre[1], &rpre[0], &rpre[1], &ctl,     &parts,
                    &bstat,   &mcount,  &gbase,   &gseed,   &vtxoff,  &gphase,  &totals,  &in_rp,
-                   &in_col,  &in_w,    &out_mate};
+                   &in_col,  &in_w,    &out_mate, &wsum};
   for (DevBuf* b : all) pool.release(*b);
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   evpool.clear();
@@ -644,7 +644,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
                               const int64_t* row_ptr, const int32_t* col, const float* w, const uint64_t* seeds,
                               uint64_t seed0, int32_t* mate, uint32_t flags, void* stream, lm_stats* st,
                               int32_t* graph_phases) {
-  const uint32_t known = LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE | LM_GRAPH;
+  const uint32_t known = LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE | LM_GRAPH | LM_WEIGHT_SUM;
   if (flags & ~known) return LM_EINVAL;
   if (N < 0 || nnz < 0 || G < 1) return LM_EINVAL;
   if (N >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 31) - 65536) return LM_ETOOBIG;
@@ -686,6 +686,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
     st->device_ms = 0.0;
     st->bytes_alg = 0.0;
     st->log_len = 0;
+    st->matched_weight = 0.0;
   }
   if (graph_phases)
     for (int64_t g = 0; g < G; ++g) graph_phases[g] = 0;
@@ -776,6 +777,17 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   lm_stats* sp = st ? st : &local;
   rs = S.run(p, s, flags, sp);
   if (rs != LM_OK) return rs;
+  double wsum = 0.0;
+  const bool want_w = st && (flags & LM_WEIGHT_SUM);
+  if (want_w) {  // after the solve's timed region
+    if ((rs = S.pool.reserve(S.wsum, sizeof(double) * (kWeightSumMaxGrid + 1))) != LM_OK) return rs;
+    double* ws = (double*)S.wsum.p;
+    if (launch_weight_sum(p.row_ptr, p.col, p.w, p.mate, N, ws, s) != hipSuccess ||
+        hipMemcpyAsync(&wsum, ws + kWeightSumMaxGrid, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) {
+      (void)hipGetLastError();
+      return LM_EDEVICE;
+    }
+  }
   if (!out_dev) {
     if (hipMemcpyAsync(mate, d_mate, (size_t)N * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return LM_EDEVICE;
   }
@@ -784,6 +796,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
       return LM_EDEVICE;
   }
   if (hipStreamSynchronize(s) != hipSuccess) return LM_EDEVICE;
+  if (want_w) st->matched_weight = wsum;
   return LM_OK;
 }
 

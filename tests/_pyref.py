@@ -109,6 +109,15 @@ def matching_weight(g, mate) -> float:
     return float(np.sum(w[sel].astype(np.float64)))
 
 
+def matching_weight_exact(g, mate):
+    """(w(M) correctly rounded, sum of |w| over M, |M|) with math.fsum."""
+    import math
+    lo, hi, w = undirected_edges(g)
+    sel = mate[lo] == hi
+    ws = w[sel].astype(np.float64)
+    return math.fsum(ws.tolist()), math.fsum(np.abs(ws).tolist()), int(sel.sum())
+
+
 def brute_mwm(g) -> float:
     """Maximum weight matching by DP over vertex subsets (n <= 16)."""
     n = g.n

@@ -56,9 +56,9 @@ def test_struct_layouts_match_header():
     """ctypes mirrors agree with the C compiler's layout of lm.h."""
     import paper_1302_4587_amd._lib as L
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "lm.h"\nint main(void){'
-           'printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lm_csr), sizeof(lm_stats), sizeof(lm_phase_rec),'
+           'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lm_csr), sizeof(lm_stats), sizeof(lm_phase_rec),'
            'sizeof(lm_tuning), sizeof(lm_server_opts), sizeof(lm_request_stats), offsetof(lm_stats, k_bytes),'
-           'offsetof(lm_stats, log_cap)); return 0; }\n')
+           'offsetof(lm_stats, log_cap), offsetof(lm_stats, matched_weight)); return 0; }\n')
     exe = os.path.join(ROOT, "_build", "layout_probe")
     os.makedirs(os.path.dirname(exe), exist_ok=True)
     r = subprocess.run(["gcc", "-std=c99", f"-I{ROOT}/include", "-x", "c", "-", "-o", exe], input=src,
@@ -66,7 +66,8 @@ def test_struct_layouts_match_header():
     assert r.returncode == 0, r.stderr
     vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     mine = [ctypes.sizeof(L.Csr), ctypes.sizeof(L.Stats), ctypes.sizeof(L.PhaseRec), ctypes.sizeof(L.Tuning),
-            ctypes.sizeof(L.ServerOpts), ctypes.sizeof(L.RequestStats), L.Stats.k_bytes.offset, L.Stats.log_cap.offset]
+            ctypes.sizeof(L.ServerOpts), ctypes.sizeof(L.RequestStats), L.Stats.k_bytes.offset, L.Stats.log_cap.offset,
+            L.Stats.matched_weight.offset]
     assert vals == mine
 
 

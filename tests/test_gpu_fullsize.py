@@ -7,13 +7,16 @@ solves it (no weight array: the unweighted kernels): mate[] and the phase log
 against the oracle on the unit-weight graph, element by element; the same
 graph with its all-ones weight array (the weighted kernels) must give the
 same mate[], and passes the greedy certificate (every matched edge is the
-largest-key edge among those not blocked by a larger matched edge).
+largest-key edge among those not blocked by a larger matched edge). The
+matched weight w(M) of the RGG solve is checked against an exactly rounded
+sum over the oracle's matching.
 """
 import numpy as np
 import pytest
 
 import lmgen
 import oracle
+from tests import _pyref as ref
 
 pytestmark = pytest.mark.gpu
 
@@ -29,13 +32,13 @@ def ctx():
     c.close()
 
 
-def _solve_device(ctx, g, seed, weights=True):
+def _solve_device(ctx, g, seed, weights=True, **kw):
     import torch
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
     w = torch.from_numpy(g.w).to(dev) if weights else None
-    mate, st = ctx.match(rp, col, w, seed=seed)
+    mate, st = ctx.match(rp, col, w, seed=seed, **kw)
     out = mate.cpu().numpy()
     del rp, col, w, mate
     torch.cuda.empty_cache()
@@ -62,6 +65,13 @@ def test_rgg_2p24_equals_oracle(ctx):
     assert np.array_equal(st.log[:, 1], ref_log[:, 1])
     assert np.array_equal(st.log[:, 2], ref_log[:, 2])
     _log_invariants(st, mate)
+    # w(M) at full size (LM_WEIGHT_SUM), against math.fsum over the oracle's matching
+    print("case: rgg n=2^24 matched weight", flush=True)
+    mate2, st2 = _solve_device(ctx, g, 1, weight_sum=True)
+    assert np.array_equal(mate2, ref_mate)
+    exact, abs_sum, edges = ref.matching_weight_exact(g, ref_mate)
+    tol = 2 * edges * 2.0**-53 * abs_sum + 2.0**-52 * abs(exact)
+    assert abs(st2.matched_weight - exact) <= tol, (st2.matched_weight, exact)
 
 
 @pytest.fixture(scope="module")

@@ -320,6 +320,69 @@ def test_hip_graph_mode_matches_eager(ctx, torch_dev):
             _assert_parity(g, 7, graphed, st_g, f"graph {name}")
 
 
+def _weight_tol(abs_sum, edges, exact):
+    # Any order of 2|M| double additions (each matched edge from both ends,
+    # then halved exactly) is within (2|M| - 1) 2^-53 sum|w| of the exact sum;
+    # the exact sum itself is rounded once (half an ulp).
+    return 2 * edges * 2.0**-53 * abs_sum + 2.0**-52 * abs(exact)
+
+
+def test_matched_weight(ctx, torch_dev):
+    """LM_WEIGHT_SUM: w(M) against math.fsum over the oracle's matching, within
+    the rounding bound of double summation; exact for unit weights; identical
+    on a repeated call."""
+    import torch
+    rng = np.random.default_rng(31)
+    cases = [("er uniform", lmgen.er(20000, 160000, seed=3)),
+             ("rmat 15 uniform", lmgen.rmat(15, 16, seed=4, weights="uniform")),
+             ("star 5000", _star(5000, rng=rng)), ("rgg 30000", lmgen.rgg(30000, 10.0, seed=9))]
+    lo, hi, _ = ref.undirected_edges(cases[0][1])
+    wsg = rng.choice(np.array([-2.5, -0.0, 0.0, 1e-30, 3.0], np.float32), len(lo))
+    cases.append(("er signed", lmgen.from_edges(cases[0][1].n, np.stack([lo, hi], 1), wsg)))
+    for name, g in cases:
+        print(f"case: matched weight {name}", flush=True)
+        ref_mate, _ = oracle.local_max_graph(g, 5)
+        exact, abs_sum, edges = ref.matching_weight_exact(g, ref_mate)
+        mate, st = _solve(ctx, torch_dev, g, 5, weight_sum=True)
+        assert np.array_equal(mate, ref_mate), name
+        assert abs(st.matched_weight - exact) <= _weight_tol(abs_sum, edges, exact), (name, st.matched_weight, exact)
+        _, st2 = _solve(ctx, torch_dev, g, 5, weight_sum=True)
+        assert st2.matched_weight == st.matched_weight, name
+        _, st3 = _solve(ctx, torch_dev, g, 5)
+        assert st3.matched_weight is None
+    # host inputs
+    g = cases[0][1]
+    mate, st = ctx.match(g.row_ptr, g.col, g.w, seed=5, weight_sum=True)
+    exact, abs_sum, edges = ref.matching_weight_exact(g, np.asarray(mate))
+    assert abs(st.matched_weight - exact) <= _weight_tol(abs_sum, edges, exact)
+    # unit weights: w(M) = |M| exactly, with the weight array and without one
+    g = lmgen.rmat(14, 16, seed=3)
+    rp = torch.from_numpy(g.row_ptr).to(torch_dev)
+    col = torch.from_numpy(g.col).to(torch_dev)
+    for w in (torch.from_numpy(g.w).to(torch_dev), None):
+        print(f"case: matched weight rmat 14 unit, weight array {w is not None}", flush=True)
+        mate, st = ctx.match(rp, col, w, seed=1, weight_sum=True)
+        assert st.matched_weight == float(st.matched_edges)
+        assert st.matched_edges == int((mate.cpu().numpy() >= 0).sum()) // 2
+    # a batch: the sum over all graphs (local ids in col and mate)
+    b = lmgen.er_batch(64, seed=5, lg_lo=5.0, lg_hi=11.0)
+    print("case: matched weight batch of 64", flush=True)
+    mate, st, _ = ctx.match_batch(b.vtx_off, b.row_ptr, b.col, b.w, seed0=3, weight_sum=True)
+    mate = np.asarray(mate)
+    ref_mate, _ = oracle.local_max_batch(b.vtx_off, b.row_ptr, b.col, b.w, seed0=3)
+    assert np.array_equal(mate, ref_mate)
+    tot, tabs, tm = [], [], 0
+    for k in range(b.graphs):
+        gk = b.graph(k)
+        e, a_, m_ = ref.matching_weight_exact(gk, mate[b.vtx_off[k]:b.vtx_off[k + 1]])
+        tot.append(e)
+        tabs.append(a_)
+        tm += m_
+    import math
+    exact = math.fsum(tot)
+    assert abs(st.matched_weight - exact) <= _weight_tol(math.fsum(tabs), tm, exact)
+
+
 def test_batch_hip_graph_matches_eager(ctx, torch_dev):
     import torch
     b = lmgen.er_batch(128, seed=4, lg_lo=4.0, lg_hi=12.0)
