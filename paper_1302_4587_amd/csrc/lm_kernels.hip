@@ -640,7 +640,9 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // UNW: an unweighted graph (no weight array; every edge weighs 1). Weights are
 // neither loaded nor stored, every loaded piece is tied, the weight scans are
 // skipped and the hash pass decides every piece.
-template <bool FIRST, int PPL, bool UNW>
+// ONE: the live set holds one graph (vertex base 0, seed seed0), so pieces
+// carry no per-graph base or seed and no table is read.
+template <bool FIRST, int PPL, bool UNW, bool ONE>
 __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()>& sm,
                              unsigned long long seed0) {
   constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f (0x3f800000 | sign bit)
@@ -650,7 +652,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   constexpr int kW = kBlock * kPPL;  // pieces in a batch window
   const int tid = threadIdx.x;
   const int lane = lane_id(), wv = wave_id();
-  const bool single = a.c.graphs == 1;
+  constexpr bool single = ONE;
   const long long E0 = ctl.L * b / ctl.P;
   const long long E1 = ctl.L * (b + 1) / ctl.P;
   if (E0 >= E1) {
@@ -1332,7 +1334,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   }
 }
 
-template <bool FIRST, int PPL, bool UNW>
+template <bool FIRST, int PPL, bool UNW, bool ONE>
 __global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL > 1 ? 3 : 5))) void k_stream(StreamArgs a) {
   __shared__ StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()> sm;
   __shared__ unsigned s_err;
@@ -1341,7 +1343,7 @@ __global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL
   if (FIRST && ctl.Pf > 0) ctl.P = ctl.Pf;  // the first argmax's own split of R_1
   const unsigned long long seed0 = a.c.gseed[0];
   for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) {
-    stream_range<FIRST, PPL, UNW>(a, ctl, b, sm, seed0);
+    stream_range<FIRST, PPL, UNW, ONE>(a, ctl, b, sm, seed0);
     __syncthreads();
   }
 }
@@ -1384,17 +1386,24 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s, hipEvent_t* ev) {
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_timed(k_plan, dim3(1), dim3(kPlanThreads), s, ev, a);
 }
+// A live set of one graph (graphs == 1: vertex base 0) takes the kernels
+// specialised for it; every other live set the ones that read the tables.
+template <bool FIRST, int PPL, bool UNW>
+static hipError_t launch_stream(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
+  if (a.c.graphs == 1) return launch_timed(k_stream<FIRST, PPL, UNW, true>, dim3(grid), dim3(kBlock), s, ev, a);
+  return launch_timed(k_stream<FIRST, PPL, UNW, false>, dim3(grid), dim3(kBlock), s, ev, a);
+}
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev) {
-  if (unweighted) return launch_timed(k_stream<true, 1, true>, dim3(grid), dim3(kBlock), s, ev, a);
-  return launch_timed(k_stream<true, 1, false>, dim3(grid), dim3(kBlock), s, ev, a);
+  if (unweighted) return launch_stream<true, 1, true>(a, grid, s, ev);
+  return launch_stream<true, 1, false>(a, grid, s, ev);
 }
 hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late, bool unweighted, hipEvent_t* ev) {
   if (unweighted) {
-    if (late) return launch_timed(k_stream<false, kLatePPL, true>, dim3(grid), dim3(kBlock), s, ev, a);
-    return launch_timed(k_stream<false, 1, true>, dim3(grid), dim3(kBlock), s, ev, a);
+    if (late) return launch_stream<false, kLatePPL, true>(a, grid, s, ev);
+    return launch_stream<false, 1, true>(a, grid, s, ev);
   }
-  if (late) return launch_timed(k_stream<false, kLatePPL, false>, dim3(grid), dim3(kBlock), s, ev, a);
-  return launch_timed(k_stream<false, 1, false>, dim3(grid), dim3(kBlock), s, ev, a);
+  if (late) return launch_stream<false, kLatePPL, false>(a, grid, s, ev);
+  return launch_stream<false, 1, false>(a, grid, s, ev);
 }
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
   return launch_timed(k_mutual, dim3(grid), dim3(kBlock), s, ev, a);
@@ -1407,15 +1416,21 @@ static int blocks_per_cu(K kernel) {
   return nb;
 }
 
+// Resident workgroups of both specialisations (one graph, tables): the fewer.
+template <bool FIRST, int PPL, bool UNW>
+static int stream_blocks_per_cu() {
+  return std::min(blocks_per_cu(k_stream<FIRST, PPL, UNW, true>), blocks_per_cu(k_stream<FIRST, PPL, UNW, false>));
+}
+
 int max_blocks_per_cu_stream(StreamKind kind, bool unweighted) {
   if (unweighted) {
-    if (kind == StreamKind::kFirst) return blocks_per_cu(k_stream<true, 1, true>);
-    if (kind == StreamKind::kCompact) return blocks_per_cu(k_stream<false, 1, true>);
-    return blocks_per_cu(k_stream<false, kLatePPL, true>);
+    if (kind == StreamKind::kFirst) return stream_blocks_per_cu<true, 1, true>();
+    if (kind == StreamKind::kCompact) return stream_blocks_per_cu<false, 1, true>();
+    return stream_blocks_per_cu<false, kLatePPL, true>();
   }
-  if (kind == StreamKind::kFirst) return blocks_per_cu(k_stream<true, 1, false>);
-  if (kind == StreamKind::kCompact) return blocks_per_cu(k_stream<false, 1, false>);
-  return blocks_per_cu(k_stream<false, kLatePPL, false>);
+  if (kind == StreamKind::kFirst) return stream_blocks_per_cu<true, 1, false>();
+  if (kind == StreamKind::kCompact) return stream_blocks_per_cu<false, 1, false>();
+  return stream_blocks_per_cu<false, kLatePPL, false>();
 }
 
 uint64_t premix_seed(uint64_t seed) { return host_mix64(seed + kGoldenGamma); }
