@@ -29,7 +29,9 @@ constexpr int kBlock = 256;            // lanes per workgroup (4 waves of 64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kItems = 8;              // entries per lane per round of k_init (the stream kernels pick their own)
 constexpr int kCap = kBlock * kItems;  // vertices per round of k_init; the smallest range a workgroup takes
-constexpr int kLatePPL = 2;                 // pieces per lane in compactions after the first
+constexpr int kLatePPL = 3;                 // pieces per lane in compactions after the first
+constexpr int kLatePPLUnw = 2;              // the same for unweighted graphs (every entry hashed: more resident waves pay)
+constexpr int late_ppl(bool unweighted) { return unweighted ? kLatePPLUnw : kLatePPL; }
 constexpr int kMutualRound = kBlock * 4;    // pieces per mutual-check round of a workgroup
 constexpr int kMaxBlocks = 4096;       // run table capacity
 constexpr int kPlanThreads = 1024;

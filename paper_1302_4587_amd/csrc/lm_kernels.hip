@@ -636,7 +636,8 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // A batch looks at PPL pieces per lane. The first argmax and the first
 // compaction take one: rows are long there, so the entry budget fills first.
 // Later compactions see short rows and many pieces of rows matched in the
-// phase (skipped without loading), and take kLatePPL.
+// phase (skipped without loading), and take kLatePPL (kLatePPLUnw when
+// unweighted).
 // UNW: an unweighted graph (no weight array; every edge weighs 1). Weights are
 // neither loaded nor stored, every loaded piece is tied, the weight scans are
 // skipped and the hash pass decides every piece.
@@ -1399,7 +1400,7 @@ hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, boo
 }
 hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late, bool unweighted, hipEvent_t* ev) {
   if (unweighted) {
-    if (late) return launch_stream<false, kLatePPL, true>(a, grid, s, ev);
+    if (late) return launch_stream<false, kLatePPLUnw, true>(a, grid, s, ev);
     return launch_stream<false, 1, true>(a, grid, s, ev);
   }
   if (late) return launch_stream<false, kLatePPL, false>(a, grid, s, ev);
@@ -1426,7 +1427,7 @@ int max_blocks_per_cu_stream(StreamKind kind, bool unweighted) {
   if (unweighted) {
     if (kind == StreamKind::kFirst) return stream_blocks_per_cu<true, 1, true>();
     if (kind == StreamKind::kCompact) return stream_blocks_per_cu<false, 1, true>();
-    return stream_blocks_per_cu<false, kLatePPL, true>();
+    return stream_blocks_per_cu<false, kLatePPLUnw, true>();
   }
   if (kind == StreamKind::kFirst) return stream_blocks_per_cu<true, 1, false>();
   if (kind == StreamKind::kCompact) return stream_blocks_per_cu<false, 1, false>();

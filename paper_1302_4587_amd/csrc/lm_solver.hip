@@ -278,7 +278,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     a.pcap = pcap;
     a.pmcap = pmcap;
     a.min_per_block = std::max(kCap, tun.block_entries);
-    a.pieces_per_block = kBlock * kLatePPL;
+    a.pieces_per_block = kBlock * late_ppl(unweighted);
     a.nruns_new = -1;
     a.log = d_log;
     a.log_cap = kLogCap;
@@ -376,7 +376,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     const int gx = (int)std::max<int64_t>(
         1, std::min<int64_t>(late ? pcap_late : pcap,
                              std::max<int64_t>(est_L / std::max(kCap, tun.block_entries),
-                                               est_V / (kBlock * (late ? kLatePPL : 1))) + 1));
+                                               est_V / (kBlock * (late ? late_ppl(unweighted) : 1))) + 1));
     ENQ(launch_compact(sa, gx, s, late, unweighted, timing(LM_K_COMPACT)));
     PlanArgs pa = plan_base();  // sizes the next compaction, a late one
     pa.pcap = pcap_late;
