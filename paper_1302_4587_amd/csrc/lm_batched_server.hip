@@ -283,6 +283,8 @@ LiveSet BatchedState::live(int tt) const {
   L.rows = (int4*)rows[i].p;
   L.col = (const int*)ecol[tt & 1].p;
   L.w = (const float*)ew[tt & 1].p;
+  L.csr_rp = nullptr;  // every live set has piece records here
+  L.vid = nullptr;
   return L;
 }
 
@@ -362,6 +364,7 @@ lm_status BatchedState::admit(std::vector<std::shared_ptr<Request>>& group, int6
   ia.runs_base = (int)nruns_now;
   ia.runs_out = truns;
   ia.rows_out = (int4*)rows[ti].p;
+  ia.ids = 0;
   if ((e = launch_init(ia, s)) != hipSuccess) return fail(e);
   PlanArgs pa;
   std::memset(&pa, 0, sizeof(pa));

@@ -138,6 +138,8 @@ struct LiveSet {
   int4* rows;
   const int* col;
   const float* w;
+  const long long* csr_rp;  // R_1 as vertex ids into the input CSR: its row_ptr, or nullptr
+  const int* vid;           // ... and the vertex of every piece (with csr_rp)
 };
 
 struct StreamArgs {
@@ -189,6 +191,10 @@ struct PlanArgs {
 // advances totals->t (after the compaction of that phase).
 enum : int { kPlanFix = 1, kPlanPrefix = 2, kPlanLog = 4, kPlanTick = 8 };
 
+// R_1 of a single graph can instead be a list of vertex ids: piece k is the
+// row of vertex vid[k] in the input CSR (offsets from row_ptr), one piece per
+// non-empty row, in the same runs; the matched flag is state[v].
+//
 // Live-set construction for vertices [vfirst, vfirst + vcount) of the
 // vertex space: row_ptr (vcount + 1 offsets into the entry buffer, from ebase
 // to ebase + nnz) and vtx_off (graphs + 1 offsets, relative to vfirst) are
@@ -208,6 +214,7 @@ struct InitArgs {
   int rows_base, runs_base;
   Run* runs_out;
   int4* rows_out;
+  int ids;           // 1: write vertex ids (int) to rows_out instead of piece records
 };
 
 struct CheckArgs {

@@ -98,7 +98,8 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
 // pieces form one run (their rows are back to back in the entry buffer). Also
 // clears mate and state and checks the offsets. Vertices are striped over the
 // lanes (vertex c0 + jj * kBlock + lane) so that every load and store of a
-// round is coalesced; wave ballots rank the non-empty rows.
+// round is coalesced; wave ballots rank the non-empty rows. With a.ids the
+// non-empty rows are listed by vertex id (4 bytes each) instead of records.
 __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
   __shared__ unsigned s_cnt[kItems * kWaves];
   const int tid = threadIdx.x;
@@ -160,7 +161,9 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
         const long long vg = a.vfirst + v;
         a.c.mate[vg] = -1;
         a.c.state[vg] = 0;
-        if ((okm >> jj) & 1u) {
+        if (((okm >> jj) & 1u) && a.ids) {
+          reinterpret_cast<int*>(a.rows_out)[a.rows_base + vb + at] = (int)vg;
+        } else if ((okm >> jj) & 1u) {
           const int slot = a.slot_of ? a.slot_of[g] : g;
           a.rows_out[a.rows_base + vb + at] =
               make_int4((int)vg, (int)r0[jj], (int)(r1[jj] - r0[jj]), (slot & kGraphMask) | kHeadBit);
@@ -399,6 +402,9 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
   const int t = a.c.totals->t;
+  // R_1 as vertex ids: every piece is a whole row (its own head), and the
+  // matched flag lives in state only
+  const bool ids = a.in.csr_rp != nullptr;
   for (int bb = blockIdx.x; bb < ctl.Pm; bb += gridDim.x) {
     const long long V = ctl.pieces;
     const long long p0 = V * bb / ctl.Pm, p1 = V * (bb + 1) / ctl.Pm;
@@ -428,7 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
         }
         int4 rec[kM];
 #pragma unroll
-        for (int i = 0; i < kM; ++i) rec[i] = a.in.rows[row[i] >= 0 ? row[i] : 0];
+        for (int i = 0; i < kM; ++i)
+          rec[i] = ids ? make_int4(a.in.vid[row[i] >= 0 ? row[i] : 0], 0, 0, kHeadBit) : a.in.rows[row[i] >= 0 ? row[i] : 0];
         bool head[kM];
         int cv[kM];
 #pragma unroll
@@ -450,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
             const int g = rec[i].w & kGraphMask;
             a.c.mate[v] = cv[i] - a.c.gbase[g];
             a.c.state[v] = 1;
-            a.in.rows[row[i]].w = rec[i].w | kMatchedBit;
+            if (!ids) a.in.rows[row[i]].w = rec[i].w | kMatchedBit;
             ++cnt;
           }
         }
@@ -554,6 +561,28 @@ struct StreamSmem {
   int open_left;
 };
 
+// How a stream kernel reads its live set: per-graph tables (several graphs),
+// one graph with piece records, or R_1 of one graph as vertex ids.
+enum : int { kViewTables = 0, kViewOne = 1, kViewIds = 2 };
+
+// Piece record of row `row`; for vertex ids made from row_ptr (graph 0, no
+// head or matched bit: the matched flag is state[v]).
+template <bool IDS>
+__device__ __forceinline__ int4 piece_at(const LiveSet& in, int row) {
+  if (IDS) {
+    const int v = in.vid[row];
+    const long long b = in.csr_rp[v], e = in.csr_rp[v + 1];
+    return make_int4(v, (int)b, (int)(e - b), 0);
+  }
+  return in.rows[row];
+}
+
+// First entry of the piece of row `row`.
+template <bool IDS>
+__device__ __forceinline__ long long piece_start(const LiveSet& in, int row) {
+  return IDS ? in.csr_rp[in.vid[row]] : (long long)in.rows[row].y;
+}
+
 // Global row index of piece k, walking forward from run r (updated).
 __device__ __forceinline__ int piece_row(const LiveSet& in, long long k, int& r, int nruns) {
   while (r + 1 < nruns && (long long)in.rpre[r + 1] <= k) ++r;
@@ -641,9 +670,10 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // UNW: an unweighted graph (no weight array; every edge weighs 1). Weights are
 // neither loaded nor stored, every loaded piece is tied, the weight scans are
 // skipped and the hash pass decides every piece.
-// ONE: the live set holds one graph (vertex base 0, seed seed0), so pieces
-// carry no per-graph base or seed and no table is read.
-template <bool FIRST, int PPL, bool UNW, bool ONE>
+// VIEW: kViewOne and kViewIds hold one graph (vertex base 0, seed seed0), so
+// pieces carry no per-graph base or seed and no table is read; kViewIds reads
+// R_1 as vertex ids into the input CSR (one whole row per piece).
+template <bool FIRST, int PPL, bool UNW, int VIEW>
 __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()>& sm,
                              unsigned long long seed0) {
   constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f (0x3f800000 | sign bit)
@@ -653,7 +683,8 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   constexpr int kW = kBlock * kPPL;  // pieces in a batch window
   const int tid = threadIdx.x;
   const int lane = lane_id(), wv = wave_id();
-  constexpr bool single = ONE;
+  constexpr bool single = VIEW != kViewTables;
+  constexpr bool ids = VIEW == kViewIds;
   const long long E0 = ctl.L * b / ctl.P;
   const long long E1 = ctl.L * (b + 1) / ctl.P;
   if (E0 >= E1) {
@@ -686,16 +717,16 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   const long long lo = E0 - a.in.epre[r0];
   const long long ip = block_lower_bound(
       0, run0.row_count,
-      [&](long long i) { return (long long)(a.in.rows[run0.row_begin + i].y - run0.phys_begin) > lo; }, sm.lb);
+      [&](long long i) { return piece_start<ids>(a.in, run0.row_begin + (int)i) - run0.phys_begin > lo; }, sm.lb);
   const int pidx = (int)ip - 1;
   const int k0 = a.in.rpre[r0] + pidx;
   if (tid == 0) {
-    const int4 rec0 = a.in.rows[run0.row_begin + pidx];
+    const int4 rec0 = piece_at<ids>(a.in, run0.row_begin + pidx);
     const int o0 = (int)(lo - (rec0.y - run0.phys_begin));
     // the range starts inside a row when it cuts a piece or when the previous
     // piece (of this run or of the last non-empty run before it) has the same vertex
     int open_left = o0 > 0;
-    if (!open_left && k0 > 0) {
+    if (!ids && !open_left && k0 > 0) {  // (with vertex ids every piece is a whole row)
       if (pidx > 0) {
         open_left = a.in.rows[run0.row_begin + pidx - 1].x == rec0.x;
       } else {
@@ -765,7 +796,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
           rr = max(rr, sm.rc.c0 + kBlock);  // past the cached runs: rpre[c0 + kBlock] <= gk
           row = piece_row(a.in, gk, rr, ctl.nruns);
         }
-        rec[h] = a.in.rows[row];
+        rec[h] = piece_at<ids>(a.in, row);
         if (j == 0) {
           rec[h].y += cur_o;
           rec[h].z -= cur_o;
@@ -783,14 +814,18 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     // last one may be cut. Matched pieces are skipped without loading.
     long long cp = (long long)(ex >> 32);        // virtual entries before the piece
     long long lp = (long long)(ex & 0xffffffffull);  // loadable entries before the piece
+    // A piece is taken when it starts inside the range and the budget (it
+    // then has at least one entry to take).
     long long cpre[kPPL];
     int lpre[kPPL], take[kPPL], ldt[kPPL];
+    bool tkn[kPPL];
 #pragma unroll
     for (int h = 0; h < kPPL; ++h) {
       cpre[h] = cp;
       lpre[h] = (int)(lp < kCap ? lp : kCap);
       take[h] = 0;
-      if (valid[h] && cp < Rrem && lp < kCap) {
+      tkn[h] = valid[h] && cp < Rrem && lp < kCap;
+      if (tkn[h]) {
         long long tk = cov[h] < Rrem - cp ? (long long)cov[h] : Rrem - cp;
         if (!mt[h] && tk > kCap - lp) tk = kCap - lp;
         take[h] = (int)tk;
@@ -802,10 +837,10 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
 #pragma unroll
     for (int h = 0; h < kPPL; ++h) {
       const int j = tid * kPPL + h;
-      if (take[h] > 0) {
+      if (tkn[h]) {
         bool next_taken;
         if (h + 1 < kPPL)
-          next_taken = take[h + 1 < kPPL ? h + 1 : h] > 0;
+          next_taken = tkn[h + 1 < kPPL ? h + 1 : h];
         else
           next_taken = take[h] == cov[h] && j + 1 < kW && (long long)cur_k + j + 1 < ctl.pieces && cp < Rrem &&
                        lp < kCap;
@@ -1288,7 +1323,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         open_right = true;
       } else if (sm.cur_k < ctl.pieces) {
         int rr = sm.cur_r;
-        open_right = a.in.rows[piece_row(a.in, sm.cur_k, rr, ctl.nruns)].x == c.v;
+        open_right = piece_at<ids>(a.in, piece_row(a.in, sm.cur_k, rr, ctl.nruns)).x == c.v;
       }
       const bool cut_left = c.is_first && open_left;
       const int slot = (!FIRST && c.kept > 0) ? sm.row_cursor : -1;
@@ -1335,7 +1370,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   }
 }
 
-template <bool FIRST, int PPL, bool UNW, bool ONE>
+template <bool FIRST, int PPL, bool UNW, int VIEW>
 __global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL > 1 ? 3 : 5))) void k_stream(StreamArgs a) {
   __shared__ StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()> sm;
   __shared__ unsigned s_err;
@@ -1344,7 +1379,7 @@ __global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL
   if (FIRST && ctl.Pf > 0) ctl.P = ctl.Pf;  // the first argmax's own split of R_1
   const unsigned long long seed0 = a.c.gseed[0];
   for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) {
-    stream_range<FIRST, PPL, UNW, ONE>(a, ctl, b, sm, seed0);
+    stream_range<FIRST, PPL, UNW, VIEW>(a, ctl, b, sm, seed0);
     __syncthreads();
   }
 }
@@ -1388,11 +1423,17 @@ hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_timed(k_plan, dim3(1), dim3(kPlanThreads), s, ev, a);
 }
 // A live set of one graph (graphs == 1: vertex base 0) takes the kernels
-// specialised for it; every other live set the ones that read the tables.
+// specialised for it (R_1 as vertex ids when the live set says so); every
+// other live set the ones that read the tables.
 template <bool FIRST, int PPL, bool UNW>
 static hipError_t launch_stream(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
-  if (a.c.graphs == 1) return launch_timed(k_stream<FIRST, PPL, UNW, true>, dim3(grid), dim3(kBlock), s, ev, a);
-  return launch_timed(k_stream<FIRST, PPL, UNW, false>, dim3(grid), dim3(kBlock), s, ev, a);
+  if constexpr (PPL == 1) {
+    if (a.c.graphs == 1 && a.in.csr_rp)
+      return launch_timed(k_stream<FIRST, PPL, UNW, kViewIds>, dim3(grid), dim3(kBlock), s, ev, a);
+  }
+  if (a.in.csr_rp) return hipErrorInvalidValue;  // vertex ids are for R_1 of one graph only
+  if (a.c.graphs == 1) return launch_timed(k_stream<FIRST, PPL, UNW, kViewOne>, dim3(grid), dim3(kBlock), s, ev, a);
+  return launch_timed(k_stream<FIRST, PPL, UNW, kViewTables>, dim3(grid), dim3(kBlock), s, ev, a);
 }
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev) {
   if (unweighted) return launch_stream<true, 1, true>(a, grid, s, ev);
@@ -1417,10 +1458,13 @@ static int blocks_per_cu(K kernel) {
   return nb;
 }
 
-// Resident workgroups of both specialisations (one graph, tables): the fewer.
+// Resident workgroups of every specialisation a launch may take: the fewest.
 template <bool FIRST, int PPL, bool UNW>
 static int stream_blocks_per_cu() {
-  return std::min(blocks_per_cu(k_stream<FIRST, PPL, UNW, true>), blocks_per_cu(k_stream<FIRST, PPL, UNW, false>));
+  int nb = std::min(blocks_per_cu(k_stream<FIRST, PPL, UNW, kViewOne>),
+                    blocks_per_cu(k_stream<FIRST, PPL, UNW, kViewTables>));
+  if constexpr (PPL == 1) nb = std::min(nb, blocks_per_cu(k_stream<FIRST, PPL, UNW, kViewIds>));
+  return nb;
 }
 
 int max_blocks_per_cu_stream(StreamKind kind, bool unweighted) {

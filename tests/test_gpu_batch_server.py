@@ -57,6 +57,25 @@ def test_batch_equals_each_graph_alone(ctx, torch_dev):
     assert st.phases == int(ref_ph.max())
 
 
+def test_batch_of_one_graph(ctx, torch_dev):
+    """A batch of one graph reads its first live set straight from the CSR
+    (empty rows included); its mate[] and its phase count must equal the
+    oracle's, also for a graph with no edge at all (0 phases)."""
+    cases = [("er 5000/3000 (isolated vertices)", lmgen.er(5000, 3000, seed=6)),
+             ("er 100/0 (no edge)", lmgen.er(100, 0, seed=6)),
+             ("rmat 12", lmgen.rmat(12, 16, seed=2))]
+    for name, g in cases:
+        vo = np.array([0, g.n], dtype=np.int64)
+        ref_mate, ref_ph = oracle.local_max_batch(vo, g.row_ptr, g.col, g.w, seed0=4)
+        for hip_graph in (False, True):
+            print(f"case: batch of one, {name}, hip_graph={hip_graph}", flush=True)
+            rp, col, w = _dev(torch_dev, g.row_ptr, g.col, g.w)
+            mate, st, gph = ctx.match_batch(vo, rp, col, w, seed0=4, hip_graph=hip_graph)
+            assert np.array_equal(mate.cpu().numpy(), ref_mate), name
+            assert np.array_equal(gph, ref_ph), (name, gph, ref_ph)
+            assert st.phases == int(ref_ph[0])
+
+
 def test_batch_per_graph_seeds_and_host_inputs(ctx, torch_dev):
     print("case: batch of 64 graphs with per-graph seeds, host inputs", flush=True)
     b = lmgen.er_batch(64, seed=5, lg_lo=5.0, lg_hi=11.0, weights="unit")

@@ -320,6 +320,27 @@ def test_hip_graph_mode_matches_eager(ctx, torch_dev):
             _assert_parity(g, 7, graphed, st_g, f"graph {name}")
 
 
+def test_first_live_set_views_agree(ctx, torch_dev):
+    """A single graph's first live set is a list of vertex ids when its
+    average degree is at most 16, else piece records. Isolated vertices
+    appended to a graph change neither its keys nor its matching, so the same
+    edges solved both ways (average degree 20, then diluted to 10) must give
+    the same mate[] on the original vertices, equal to the oracle, with the
+    same phase log."""
+    for seed, (n, m) in ((1, (6000, 60000)), (2, (20000, 200000)), (3, (1500, 15000))):
+        g = lmgen.er(n, m, seed=seed)
+        lo, hi, w = ref.undirected_edges(g)
+        gd = lmgen.from_edges(2 * n, np.stack([lo, hi], 1), w)  # n isolated vertices appended
+        assert g.nnz > 16 * g.n and gd.nnz <= 16 * gd.n
+        print(f"case: views n={n} m={m} seed={seed}", flush=True)
+        mate, st = _solve(ctx, torch_dev, g, 9)
+        _assert_parity(g, 9, mate, st, "records")
+        mated, std = _solve(ctx, torch_dev, gd, 9)
+        _assert_parity(gd, 9, mated, std, "vertex ids")
+        assert np.array_equal(mated[:n], mate) and np.all(mated[n:] == -1)
+        assert np.array_equal(std.log[:, 0], st.log[:, 0]) and np.array_equal(std.log[:, 2], st.log[:, 2])
+
+
 def _weight_tol(abs_sum, edges, exact):
     # Any order of 2|M| double additions (each matched edge from both ends,
     # then halved exactly) is within (2|M| - 1) 2^-53 sum|w| of the exact sum;
