@@ -284,7 +284,6 @@ LiveSet BatchedState::live(int tt) const {
   L.col = (const int*)ecol[tt & 1].p;
   L.w = (const float*)ew[tt & 1].p;
   L.csr_rp = nullptr;  // every live set has piece records here
-  L.vid = nullptr;
   return L;
 }
 
@@ -364,7 +363,8 @@ lm_status BatchedState::admit(std::vector<std::shared_ptr<Request>>& group, int6
   ia.runs_base = (int)nruns_now;
   ia.runs_out = truns;
   ia.rows_out = (int4*)rows[ti].p;
-  ia.ids = 0;
+  ia.csr = 0;
+  ia.bstat = nullptr;
   if ((e = launch_init(ia, s)) != hipSuccess) return fail(e);
   PlanArgs pa;
   std::memset(&pa, 0, sizeof(pa));

@@ -34,6 +34,7 @@ constexpr int kLatePPLUnw = 2;              // the same for unweighted graphs (e
 constexpr int late_ppl(bool unweighted) { return unweighted ? kLatePPLUnw : kLatePPL; }
 constexpr int kMutualRound = kBlock * 4;    // pieces per mutual-check round of a workgroup
 constexpr int kMaxBlocks = 4096;       // run table capacity
+constexpr int kPieceCost = 8;          // entries one piece weighs when R_1 is split from the CSR
 constexpr int kPlanThreads = 1024;
 constexpr unsigned kDropBit = 0x80000000u;
 constexpr int kHeadBit = (int)0x80000000u;
@@ -138,8 +139,7 @@ struct LiveSet {
   int4* rows;
   const int* col;
   const float* w;
-  const long long* csr_rp;  // R_1 as vertex ids into the input CSR: its row_ptr, or nullptr
-  const int* vid;           // ... and the vertex of every piece (with csr_rp)
+  const long long* csr_rp;  // R_1 read from the input CSR (its row_ptr), or nullptr: piece records
 };
 
 struct StreamArgs {
@@ -178,6 +178,7 @@ struct PlanArgs {
   Ctl* ctl_new;
   int pcap, pmcap;       // workgroup caps for the next phase
   int pcap_first;        // workgroup cap of the first argmax over the new live set (R_1), 0: none
+  const BlockStat* heads_of_runs;  // kPlanPrefix, R_1 read from the CSR: live rows per run (pieces_out)
   int min_per_block;     // virtual entries per compaction workgroup at least
   int pieces_per_block;  // pieces per compaction workgroup at least (0: no bound)
   // log
@@ -191,9 +192,11 @@ struct PlanArgs {
 // advances totals->t (after the compaction of that phase).
 enum : int { kPlanFix = 1, kPlanPrefix = 2, kPlanLog = 4, kPlanTick = 8 };
 
-// R_1 of a single graph can instead be a list of vertex ids: piece k is the
-// row of vertex vid[k] in the input CSR (offsets from row_ptr), one piece per
-// non-empty row, in the same runs; the matched flag is state[v].
+// R_1 of a single graph can instead be read straight from the input CSR: no
+// piece records, piece k is vertex k (its row from row_ptr, empty rows as
+// pieces of length 0), run b covers the vertices of init workgroup b, and the
+// matched flag is state[v]. Workgroup ranges then split entries plus
+// kPieceCost per piece, so no range walks a long stretch of empty rows.
 //
 // Live-set construction for vertices [vfirst, vfirst + vcount) of the
 // vertex space: row_ptr (vcount + 1 offsets into the entry buffer, from ebase
@@ -214,7 +217,9 @@ struct InitArgs {
   int rows_base, runs_base;
   Run* runs_out;
   int4* rows_out;
-  int ids;           // 1: write vertex ids (int) to rows_out instead of piece records
+  int csr;           // 1: no piece records (R_1 read from the CSR): C[v] = -1 for every vertex,
+                     // bstat[b].pieces_out = non-empty rows of workgroup b
+  BlockStat* bstat;
 };
 
 struct CheckArgs {

@@ -98,8 +98,9 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
 // pieces form one run (their rows are back to back in the entry buffer). Also
 // clears mate and state and checks the offsets. Vertices are striped over the
 // lanes (vertex c0 + jj * kBlock + lane) so that every load and store of a
-// round is coalesced; wave ballots rank the non-empty rows. With a.ids the
-// non-empty rows are listed by vertex id (4 bytes each) instead of records.
+// round is coalesced; wave ballots rank the non-empty rows. With a.csr no
+// piece is written: the run covers every vertex of the workgroup, C is
+// cleared, and the count of non-empty rows goes to bstat[b].
 __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
   __shared__ unsigned s_cnt[kItems * kWaves];
   const int tid = threadIdx.x;
@@ -161,8 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
         const long long vg = a.vfirst + v;
         a.c.mate[vg] = -1;
         a.c.state[vg] = 0;
-        if (((okm >> jj) & 1u) && a.ids) {
-          reinterpret_cast<int*>(a.rows_out)[a.rows_base + vb + at] = (int)vg;
+        if (a.csr) {
+          a.c.C[vg] = -1;  // the mutual check reads C of every vertex, empty rows too
         } else if ((okm >> jj) & 1u) {
           const int slot = a.slot_of ? a.slot_of[g] : g;
           a.rows_out[a.rows_base + vb + at] =
@@ -176,7 +177,15 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
   if (tid == 0) {
     Run r;
     r.row_begin = a.rows_base + (int)vb;
-    r.row_count = (int)cursor;
+    r.row_count = a.csr ? (int)(ve - vb) : (int)cursor;  // from the CSR: every vertex is a piece
+    if (a.csr) {
+      BlockStat st;
+      st.loaded = 0;
+      st.matched_len = 0;
+      st.pieces_out = (int)cursor;  // non-empty rows: the live rows of R_1
+      st.pad = 0;
+      a.bstat[b] = st;
+    }
     const long long pb = vb < N ? a.row_ptr[vb] : eend;
     const long long pe = a.row_ptr[ve];
     r.phys_begin = (int)pb;
@@ -200,6 +209,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
   __shared__ int s_extra;
   __shared__ long long s_e[kPlanThreads / 64];
   __shared__ int s_r[kPlanThreads / 64];
+  __shared__ int s_h[kPlanThreads / 64];
   __shared__ long long s_red[4];
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -251,7 +261,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
     long long le[kPer];
     int lr[kPer];
     long long se = 0;
-    int sr = 0;
+    int sr = 0, sh = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int r = tid * kPer + i;
@@ -261,19 +271,22 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
         const Run run = a.runs_new[r];
         le[i] = run.ent_count;
         lr[i] = run.row_count;
+        if (a.heads_of_runs) sh += a.heads_of_runs[r].pieces_out;
       }
       se += le[i];
       sr += lr[i];
     }
     long long ie = wave_incl_sum<long long>(se);
     int ir = wave_incl_sum<int>(sr);
+    const int ih = wave_incl_sum<int>(sh);
     if (lane_id() == 63) {
       s_e[tid >> 6] = ie;
       s_r[tid >> 6] = ir;
+      s_h[tid >> 6] = ih;
     }
     __syncthreads();
     long long pe = 0, te = 0;
-    int pr = 0, tr = 0;
+    int pr = 0, tr = 0, th = 0;
     for (int wv = 0; wv < kPlanThreads / 64; ++wv) {
       if (wv < (tid >> 6)) {
         pe += s_e[wv];
@@ -281,6 +294,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
       }
       te += s_e[wv];
       tr += s_r[wv];
+      th += s_h[wv];
     }
     long long ce = pe + ie - se;
     int cr = pr + ir - sr;
@@ -301,7 +315,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
       c.L = te;
       c.nruns = nr;
       c.pieces = tr;
-      c.heads = tr - s_extra;
+      // live rows: pieces less the extra pieces of cut rows; for R_1 read from
+      // the CSR (empty rows are pieces) the non-empty rows k_init counted
+      c.heads = a.heads_of_runs ? th : tr - s_extra;
       // enough workgroups that each one sees a few full batches at most:
       // short rows fill a batch's piece window before its entry budget
       long long P = (te + a.min_per_block - 1) / a.min_per_block;
@@ -402,18 +418,19 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
   if (block_failed(a.c.totals, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
   const int t = a.c.totals->t;
-  // R_1 as vertex ids: every piece is a whole row (its own head), and the
-  // matched flag lives in state only
-  const bool ids = a.in.csr_rp != nullptr;
+  // R_1 read from the CSR: piece k is vertex k, every vertex is its own head,
+  // and the matched flag lives in state only (C is -1 for empty rows)
+  const bool csr = a.in.csr_rp != nullptr;
   for (int bb = blockIdx.x; bb < ctl.Pm; bb += gridDim.x) {
     const long long V = ctl.pieces;
     const long long p0 = V * bb / ctl.Pm, p1 = V * (bb + 1) / ctl.Pm;
     unsigned cnt = 0;
     if (p0 < p1) {
       // run containing piece p0: first r with rpre[r+1] > p0
-      const int r0 = (int)block_lower_bound(
-          0, ctl.nruns, [&](long long r) { return (long long)a.in.rpre[r + 1] > p0; }, s_lb);
-      run_cache_fill(a.in, ctl.nruns, r0, rc);
+      const int r0 = csr ? 0
+                         : (int)block_lower_bound(
+                               0, ctl.nruns, [&](long long r) { return (long long)a.in.rpre[r + 1] > p0; }, s_lb);
+      if (!csr) run_cache_fill(a.in, ctl.nruns, r0, rc);
       __syncthreads();
       int r = r0;
       // kM pieces per lane per round; every load of a round is issued
@@ -426,7 +443,9 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
         for (int i = 0; i < kM; ++i) {
           const long long pi = base + (long long)i * kBlock + threadIdx.x;
           row[i] = -1;
-          if (pi < p1 && !run_cache_find(rc, pi, r, row[i])) {
+          if (csr) {
+            row[i] = pi < p1 ? (int)pi : -1;
+          } else if (pi < p1 && !run_cache_find(rc, pi, r, row[i])) {
             r = max(r, r0 + kBlock);  // past the cached runs: rpre[r0 + kBlock] <= pi
             while (r + 1 < ctl.nruns && (long long)a.in.rpre[r + 1] <= pi) ++r;
             row[i] = a.in.runs[r].row_begin + (int)(pi - a.in.rpre[r]);
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
         int4 rec[kM];
 #pragma unroll
         for (int i = 0; i < kM; ++i)
-          rec[i] = ids ? make_int4(a.in.vid[row[i] >= 0 ? row[i] : 0], 0, 0, kHeadBit) : a.in.rows[row[i] >= 0 ? row[i] : 0];
+          rec[i] = csr ? make_int4(row[i] >= 0 ? row[i] : 0, 0, 0, kHeadBit) : a.in.rows[row[i] >= 0 ? row[i] : 0];
         bool head[kM];
         int cv[kM];
 #pragma unroll
@@ -457,14 +476,16 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
             const int g = rec[i].w & kGraphMask;
             a.c.mate[v] = cv[i] - a.c.gbase[g];
             a.c.state[v] = 1;
-            if (!ids) a.in.rows[row[i]].w = rec[i].w | kMatchedBit;
+            if (!csr) a.in.rows[row[i]].w = rec[i].w | kMatchedBit;
             ++cnt;
           }
         }
         if (a.c.gphase) {  // one atomic per distinct graph per wave
 #pragma unroll
           for (int i = 0; i < kM; ++i) {
-            const int g = head[i] ? (rec[i].w & kGraphMask) : -1;
+            // a live row: a head piece (read from the CSR: a vertex with a candidate)
+            const bool live_row = head[i] && (!csr || cv[i] >= 0);
+            const int g = live_row ? (rec[i].w & kGraphMask) : -1;
             unsigned long long active = __ballot(g >= 0);
             while (active) {
               const int leader = __ffsll((long long)active) - 1;
@@ -562,25 +583,38 @@ struct StreamSmem {
 };
 
 // How a stream kernel reads its live set: per-graph tables (several graphs),
-// one graph with piece records, or R_1 of one graph as vertex ids.
-enum : int { kViewTables = 0, kViewOne = 1, kViewIds = 2 };
+// one graph with piece records, or R_1 of one graph straight from the CSR.
+enum : int { kViewTables = 0, kViewOne = 1, kViewCsr = 2 };
 
-// Piece record of row `row`; for vertex ids made from row_ptr (graph 0, no
-// head or matched bit: the matched flag is state[v]).
-template <bool IDS>
+// Piece record of row `row`; from the CSR made from row_ptr (vertex = row,
+// graph 0, no head or matched bit: the matched flag is state[v]).
+template <bool CSR>
 __device__ __forceinline__ int4 piece_at(const LiveSet& in, int row) {
-  if (IDS) {
-    const int v = in.vid[row];
-    const long long b = in.csr_rp[v], e = in.csr_rp[v + 1];
-    return make_int4(v, (int)b, (int)(e - b), 0);
+  if (CSR) {
+    const long long b = in.csr_rp[row], e = in.csr_rp[row + 1];
+    return make_int4(row, (int)b, (int)(e - b), 0);
   }
   return in.rows[row];
 }
 
 // First entry of the piece of row `row`.
-template <bool IDS>
+template <bool CSR>
 __device__ __forceinline__ long long piece_start(const LiveSet& in, int row) {
-  return IDS ? in.csr_rp[in.vid[row]] : (long long)in.rows[row].y;
+  return CSR ? in.csr_rp[row] : (long long)in.rows[row].y;
+}
+
+// R_1 read from the CSR: the entry position of cost c, where vertex v's row
+// spans the cost units [row_ptr[v] + K v, row_ptr[v+1] + K (v+1)) (K units
+// for the piece, then one per entry). Monotone in c; c = 0 gives 0 and c =
+// L + K n gives L. Every lane gets the same value.
+__device__ __forceinline__ long long csr_entry_at(const LiveSet& in, long long n, long long c, int* sm) {
+  const long long v1 = block_lower_bound(
+      0, n + 1, [&](long long v) { return in.csr_rp[v] + (long long)kPieceCost * v > c; }, sm);
+  const long long v = v1 - 1;  // cost_start(0) = 0 <= c, so v1 >= 1
+  const long long u = c - (in.csr_rp[v] + (long long)kPieceCost * v);
+  if (u < kPieceCost || v >= n) return in.csr_rp[v];
+  const long long deg = in.csr_rp[v + 1] - in.csr_rp[v];
+  return in.csr_rp[v] + min(u - kPieceCost, deg);
 }
 
 // Global row index of piece k, walking forward from run r (updated).
@@ -670,9 +704,10 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // UNW: an unweighted graph (no weight array; every edge weighs 1). Weights are
 // neither loaded nor stored, every loaded piece is tied, the weight scans are
 // skipped and the hash pass decides every piece.
-// VIEW: kViewOne and kViewIds hold one graph (vertex base 0, seed seed0), so
-// pieces carry no per-graph base or seed and no table is read; kViewIds reads
-// R_1 as vertex ids into the input CSR (one whole row per piece).
+// VIEW: kViewOne and kViewCsr hold one graph (vertex base 0, seed seed0), so
+// pieces carry no per-graph base or seed and no table is read; kViewCsr reads
+// R_1 from the input CSR, empty rows as pieces of length 0, and splits the
+// ranges by entries plus kPieceCost per piece.
 template <bool FIRST, int PPL, bool UNW, int VIEW>
 __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()>& sm,
                              unsigned long long seed0) {
@@ -684,9 +719,16 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   const int tid = threadIdx.x;
   const int lane = lane_id(), wv = wave_id();
   constexpr bool single = VIEW != kViewTables;
-  constexpr bool ids = VIEW == kViewIds;
-  const long long E0 = ctl.L * b / ctl.P;
-  const long long E1 = ctl.L * (b + 1) / ctl.P;
+  constexpr bool csr = VIEW == kViewCsr;
+  long long E0, E1;
+  if (csr) {
+    const long long n = ctl.pieces, cost = ctl.L + (long long)kPieceCost * n;
+    E0 = csr_entry_at(a.in, n, cost * b / ctl.P, sm.lb);
+    E1 = csr_entry_at(a.in, n, cost * (b + 1) / ctl.P, sm.lb);
+  } else {
+    E0 = ctl.L * b / ctl.P;
+    E1 = ctl.L * (b + 1) / ctl.P;
+  }
   if (E0 >= E1) {
     if (tid == 0) {
       if (!FIRST) {
@@ -717,16 +759,16 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   const long long lo = E0 - a.in.epre[r0];
   const long long ip = block_lower_bound(
       0, run0.row_count,
-      [&](long long i) { return piece_start<ids>(a.in, run0.row_begin + (int)i) - run0.phys_begin > lo; }, sm.lb);
+      [&](long long i) { return piece_start<csr>(a.in, run0.row_begin + (int)i) - run0.phys_begin > lo; }, sm.lb);
   const int pidx = (int)ip - 1;
   const int k0 = a.in.rpre[r0] + pidx;
   if (tid == 0) {
-    const int4 rec0 = piece_at<ids>(a.in, run0.row_begin + pidx);
+    const int4 rec0 = piece_at<csr>(a.in, run0.row_begin + pidx);
     const int o0 = (int)(lo - (rec0.y - run0.phys_begin));
     // the range starts inside a row when it cuts a piece or when the previous
     // piece (of this run or of the last non-empty run before it) has the same vertex
     int open_left = o0 > 0;
-    if (!ids && !open_left && k0 > 0) {  // (with vertex ids every piece is a whole row)
+    if (!csr && !open_left && k0 > 0) {  // (from the CSR every piece is a whole row)
       if (pidx > 0) {
         open_left = a.in.rows[run0.row_begin + pidx - 1].x == rec0.x;
       } else {
@@ -796,7 +838,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
           rr = max(rr, sm.rc.c0 + kBlock);  // past the cached runs: rpre[c0 + kBlock] <= gk
           row = piece_row(a.in, gk, rr, ctl.nruns);
         }
-        rec[h] = piece_at<ids>(a.in, row);
+        rec[h] = piece_at<csr>(a.in, row);
         if (j == 0) {
           rec[h].y += cur_o;
           rec[h].z -= cur_o;
@@ -814,8 +856,8 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     // last one may be cut. Matched pieces are skipped without loading.
     long long cp = (long long)(ex >> 32);        // virtual entries before the piece
     long long lp = (long long)(ex & 0xffffffffull);  // loadable entries before the piece
-    // A piece is taken when it starts inside the range and the budget (it
-    // then has at least one entry to take).
+    // A piece is taken when it starts inside the range and the budget; an
+    // empty row (R_1 read from the CSR) is taken with nothing to load.
     long long cpre[kPPL];
     int lpre[kPPL], take[kPPL], ldt[kPPL];
     bool tkn[kPPL];
@@ -1323,7 +1365,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         open_right = true;
       } else if (sm.cur_k < ctl.pieces) {
         int rr = sm.cur_r;
-        open_right = piece_at<ids>(a.in, piece_row(a.in, sm.cur_k, rr, ctl.nruns)).x == c.v;
+        open_right = piece_at<csr>(a.in, piece_row(a.in, sm.cur_k, rr, ctl.nruns)).x == c.v;
       }
       const bool cut_left = c.is_first && open_left;
       const int slot = (!FIRST && c.kept > 0) ? sm.row_cursor : -1;
@@ -1423,15 +1465,15 @@ hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev) {
   return launch_timed(k_plan, dim3(1), dim3(kPlanThreads), s, ev, a);
 }
 // A live set of one graph (graphs == 1: vertex base 0) takes the kernels
-// specialised for it (R_1 as vertex ids when the live set says so); every
+// specialised for it (R_1 read from the CSR when the live set says so); every
 // other live set the ones that read the tables.
 template <bool FIRST, int PPL, bool UNW>
 static hipError_t launch_stream(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
   if constexpr (PPL == 1) {
     if (a.c.graphs == 1 && a.in.csr_rp)
-      return launch_timed(k_stream<FIRST, PPL, UNW, kViewIds>, dim3(grid), dim3(kBlock), s, ev, a);
+      return launch_timed(k_stream<FIRST, PPL, UNW, kViewCsr>, dim3(grid), dim3(kBlock), s, ev, a);
   }
-  if (a.in.csr_rp) return hipErrorInvalidValue;  // vertex ids are for R_1 of one graph only
+  if (a.in.csr_rp) return hipErrorInvalidValue;  // the CSR view is for R_1 of one graph only
   if (a.c.graphs == 1) return launch_timed(k_stream<FIRST, PPL, UNW, kViewOne>, dim3(grid), dim3(kBlock), s, ev, a);
   return launch_timed(k_stream<FIRST, PPL, UNW, kViewTables>, dim3(grid), dim3(kBlock), s, ev, a);
 }
@@ -1463,7 +1505,7 @@ template <bool FIRST, int PPL, bool UNW>
 static int stream_blocks_per_cu() {
   int nb = std::min(blocks_per_cu(k_stream<FIRST, PPL, UNW, kViewOne>),
                     blocks_per_cu(k_stream<FIRST, PPL, UNW, kViewTables>));
-  if constexpr (PPL == 1) nb = std::min(nb, blocks_per_cu(k_stream<FIRST, PPL, UNW, kViewIds>));
+  if constexpr (PPL == 1) nb = std::min(nb, blocks_per_cu(k_stream<FIRST, PPL, UNW, kViewCsr>));
   return nb;
 }
 

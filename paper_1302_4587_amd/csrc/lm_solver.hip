@@ -206,14 +206,11 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   const bool prof = (flags & LM_PROFILE) != 0;
   if (++gen == 0) gen = 1;  // 0 marks a never-written mirror slot
   const bool unweighted = p.w == nullptr;  // no weight array: every edge weighs 1
-  // R_1 of a single graph with short rows (average degree at most 16) is a
-  // list of vertex ids into the input CSR: 4 bytes per non-empty row instead
-  // of a 16-byte piece record, and the mutual check rewrites nothing; the
-  // first argmax and compaction then find each row through row_ptr, one more
-  // dependent load per window, which costs more than it saves on graphs with
-  // long, skewed rows (R-MAT). A batch builds piece records, which carry each
-  // row's graph.
-  const bool ids1 = p.G == 1 && p.nnz <= 16 * p.N;
+  // R_1 of a single graph is read straight from the input CSR: no 16-byte
+  // piece records (k_init writes none, the first argmax, mutual check and
+  // compaction take rows from row_ptr, the mutual check rewrites nothing). A
+  // batch builds piece records, which carry each row's graph.
+  const bool csr1 = p.G == 1;
   std::vector<std::pair<int, size_t>> marks;  // (kind, event index of start)
   size_t evn = 0;
   const uint32_t kmask = (st && st->profile_kinds) ? st->profile_kinds : ((1u << LM_K_KINDS) - 1);
@@ -277,8 +274,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     L.rows = (int4*)rows[i].p;
     L.col = t == 1 ? p.col : (const int*)ecol[t & 1].p;
     L.w = t == 1 ? p.w : (const float*)ew[t & 1].p;
-    L.csr_rp = (t == 1 && ids1) ? p.row_ptr : nullptr;
-    L.vid = (t == 1 && ids1) ? (const int*)rows[0].p : nullptr;  // written by k_init
+    L.csr_rp = (t == 1 && csr1) ? p.row_ptr : nullptr;
     return L;
   };
   auto plan_base = [&]() {
@@ -331,7 +327,8 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ia.runs_base = 0;
     ia.runs_out = (Run*)runs[0].p;
     ia.rows_out = (int4*)rows[0].p;
-    ia.ids = ids1 ? 1 : 0;
+    ia.csr = csr1 ? 1 : 0;
+    ia.bstat = (BlockStat*)bstat.p;
     ENQ(launch_init(ia, s, timing(LM_K_INIT)));
     PlanArgs pa = plan_base();  // R_1: split for the first compaction and, apart, the first argmax
     pa.mode = kPlanPrefix;
@@ -344,6 +341,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     pa.epre_new = (long long*)epre[0].p;
     pa.rpre_new = (int*)rpre[0].p;
     pa.ctl_new = dctl + 0;
+    pa.heads_of_runs = csr1 ? (const BlockStat*)bstat.p : nullptr;
     ENQ(launch_plan(pa, s, timing(LM_K_PLAN)));
     StreamArgs sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -539,22 +537,23 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     }
     // algorithmic bytes per kernel kind (what each must move, from the log).
     // A live row of R_1 costs a 16-byte piece record, written once and read by
-    // the first argmax, mutual check (which rewrites it) and compaction; as a
-    // vertex id it costs 4 bytes written and, in each reader, 4 bytes of id
-    // and 8 of row_ptr (argmax, compaction; the compaction adds state[v]).
+    // the first argmax, mutual check (which rewrites it) and compaction; read
+    // from the CSR it costs 8 bytes of row_ptr per vertex in the argmax and
+    // the compaction (which adds state[v]), C[v] of every vertex in the mutual
+    // check, and k_init clears C instead of writing records.
     const double N = (double)p.N;
     const double V1 = nrec > 0 ? (double)recs[0].live_rows : 0.0;
     const double L1 = nrec > 0 ? (double)recs[0].live_entries : 0.0;
-    st->k_bytes[LM_K_INIT] = 8.0 * (N + 1.0) + 5.0 * N + (ids1 ? 4.0 : 16.0) * V1;
+    st->k_bytes[LM_K_INIT] = 8.0 * (N + 1.0) + (csr1 ? 9.0 * N : 5.0 * N + 16.0 * V1);
     const double eb = unweighted ? 4.0 : 8.0;  // bytes of one entry: col (+ w)
-    st->k_bytes[LM_K_ARGMAX] = (ids1 ? 12.0 : 16.0) * V1 + eb * L1 + 4.0 * V1;
+    st->k_bytes[LM_K_ARGMAX] = (csr1 ? 8.0 * (N + 1.0) : 16.0 * V1) + eb * L1 + 4.0 * V1;
     for (int i = 0; i < nrec; ++i) {
       const double L = (double)recs[i].live_entries, V = (double)recs[i].live_rows;
       const double mv = 2.0 * (double)recs[i].matched_edges, md = (double)recs[i].matched_entries;
       const double L2 = (double)recs[i + 1].live_entries, V2 = (double)recs[i + 1].live_rows;
-      const bool from_ids = ids1 && i == 0;
-      st->k_bytes[LM_K_MUTUAL] += from_ids ? 12.0 * V + 5.0 * mv : 24.0 * V + 9.0 * mv;
-      st->k_bytes[LM_K_COMPACT] += (from_ids ? 13.0 : 16.0) * V + (eb + 1.0) * (L - md) + eb * L2 + 20.0 * V2;
+      const bool from_csr = csr1 && i == 0;
+      st->k_bytes[LM_K_MUTUAL] += from_csr ? 4.0 * N + 4.0 * V + 5.0 * mv : 24.0 * V + 9.0 * mv;
+      st->k_bytes[LM_K_COMPACT] += (from_csr ? 9.0 * N : 16.0 * V) + (eb + 1.0) * (L - md) + eb * L2 + 20.0 * V2;
     }
     st->bytes_alg = 0.0;
     for (int k = 0; k < LM_K_KINDS; ++k) st->bytes_alg += st->k_bytes[k];
