@@ -34,7 +34,8 @@ constexpr int kLatePPLUnw = 2;              // the same for unweighted graphs (e
 constexpr int late_ppl(bool unweighted) { return unweighted ? kLatePPLUnw : kLatePPL; }
 constexpr int kMutualRound = kBlock * 4;    // pieces per mutual-check round of a workgroup
 constexpr int kMaxBlocks = 4096;       // run table capacity
-constexpr int kPieceCost = 8;          // entries one piece weighs when R_1 is split from the CSR
+constexpr int kPieceCost = 8;          // entries one piece weighs when R_1 is split from the CSR (compaction)
+constexpr int kPieceCostFirst = 4;     // the same for the first argmax (measured on R-MAT and RGG)
 constexpr int kPlanThreads = 1024;
 constexpr unsigned kDropBit = 0x80000000u;
 constexpr int kHeadBit = (int)0x80000000u;
@@ -195,8 +196,9 @@ enum : int { kPlanFix = 1, kPlanPrefix = 2, kPlanLog = 4, kPlanTick = 8 };
 // R_1 of a single graph can instead be read straight from the input CSR: no
 // piece records, piece k is vertex k (its row from row_ptr, empty rows as
 // pieces of length 0), run b covers the vertices of init workgroup b, and the
-// matched flag is state[v]. Workgroup ranges then split entries plus
-// kPieceCost per piece, so no range walks a long stretch of empty rows.
+// matched flag is state[v]. Workgroup ranges then split entries plus a fixed
+// cost per piece (kPieceCost, kPieceCostFirst), so no range walks a long
+// stretch of empty rows.
 //
 // Live-set construction for vertices [vfirst, vfirst + vcount) of the
 // vertex space: row_ptr (vcount + 1 offsets into the entry buffer, from ebase

@@ -607,14 +607,15 @@ __device__ __forceinline__ long long piece_start(const LiveSet& in, int row) {
 // spans the cost units [row_ptr[v] + K v, row_ptr[v+1] + K (v+1)) (K units
 // for the piece, then one per entry). Monotone in c; c = 0 gives 0 and c =
 // L + K n gives L. Every lane gets the same value.
+template <int K>
 __device__ __forceinline__ long long csr_entry_at(const LiveSet& in, long long n, long long c, int* sm) {
   const long long v1 = block_lower_bound(
-      0, n + 1, [&](long long v) { return in.csr_rp[v] + (long long)kPieceCost * v > c; }, sm);
+      0, n + 1, [&](long long v) { return in.csr_rp[v] + (long long)K * v > c; }, sm);
   const long long v = v1 - 1;  // cost_start(0) = 0 <= c, so v1 >= 1
-  const long long u = c - (in.csr_rp[v] + (long long)kPieceCost * v);
-  if (u < kPieceCost || v >= n) return in.csr_rp[v];
+  const long long u = c - (in.csr_rp[v] + (long long)K * v);
+  if (u < K || v >= n) return in.csr_rp[v];
   const long long deg = in.csr_rp[v + 1] - in.csr_rp[v];
-  return in.csr_rp[v] + min(u - kPieceCost, deg);
+  return in.csr_rp[v] + min(u - K, deg);
 }
 
 // Global row index of piece k, walking forward from run r (updated).
@@ -707,7 +708,8 @@ __device__ __forceinline__ void close_segment(const StreamArgs& a, Smem& sm, boo
 // VIEW: kViewOne and kViewCsr hold one graph (vertex base 0, seed seed0), so
 // pieces carry no per-graph base or seed and no table is read; kViewCsr reads
 // R_1 from the input CSR, empty rows as pieces of length 0, and splits the
-// ranges by entries plus kPieceCost per piece.
+// ranges by entries plus a fixed cost per piece (kPieceCostFirst for the
+// first argmax, kPieceCost for the compaction).
 template <bool FIRST, int PPL, bool UNW, int VIEW>
 __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()>& sm,
                              unsigned long long seed0) {
@@ -722,9 +724,10 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
   constexpr bool csr = VIEW == kViewCsr;
   long long E0, E1;
   if (csr) {
-    const long long n = ctl.pieces, cost = ctl.L + (long long)kPieceCost * n;
-    E0 = csr_entry_at(a.in, n, cost * b / ctl.P, sm.lb);
-    E1 = csr_entry_at(a.in, n, cost * (b + 1) / ctl.P, sm.lb);
+    constexpr int K = FIRST ? kPieceCostFirst : kPieceCost;
+    const long long n = ctl.pieces, cost = ctl.L + (long long)K * n;
+    E0 = csr_entry_at<K>(a.in, n, cost * b / ctl.P, sm.lb);
+    E1 = csr_entry_at<K>(a.in, n, cost * (b + 1) / ctl.P, sm.lb);
   } else {
     E0 = ctl.L * b / ctl.P;
     E1 = ctl.L * (b + 1) / ctl.P;
