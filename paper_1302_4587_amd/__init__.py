@@ -31,14 +31,23 @@ def _is_torch(x) -> bool:
     return hasattr(x, "data_ptr") and hasattr(x, "is_cuda")
 
 
+_TORCH_DTYPES = {}
+
+
+def _torch_dtype(dtype):
+    if not _TORCH_DTYPES:
+        import torch
+        _TORCH_DTYPES.update({np.int64: torch.int64, np.int32: torch.int32, np.float32: torch.float32})
+    return _TORCH_DTYPES[dtype]
+
+
 def _ptr(x, dtype, on_device=False):
     """(pointer, on_device, keepalive) for a torch tensor or numpy array; None
     (an absent weight array: unweighted graph) takes the residence given."""
     if x is None:
         return None, on_device, None
     if _is_torch(x):
-        import torch
-        want = {np.int64: torch.int64, np.int32: torch.int32, np.float32: torch.float32}[dtype]
+        want = _torch_dtype(dtype)
         if x.dtype != want:
             raise TypeError(f"expected {want}, got {x.dtype}")
         if not x.is_contiguous():
@@ -66,8 +75,8 @@ class MatchStats:
 
 def _stats_out(st: _lib.Stats, logbuf, weight_sum=False) -> MatchStats:
     n = int(st.log_len)
-    log = np.array([[r.live_entries, r.live_rows, r.matched_edges, r.matched_entries] for r in logbuf[:n]],
-                   dtype=np.int64).reshape(n, 4)
+    # lm_phase_rec is four int64: copy the first n records out of the reused buffer
+    log = np.frombuffer(logbuf, dtype=np.int64, count=4 * n).reshape(n, 4).copy()
     return MatchStats(int(st.phases), int(st.matched_edges), float(st.device_ms), float(st.bytes_alg), log,
                       {k: int(st.k_launches[i]) for i, k in enumerate(KERNEL_KINDS)},
                       {k: float(st.k_ms[i]) for i, k in enumerate(KERNEL_KINDS)},
