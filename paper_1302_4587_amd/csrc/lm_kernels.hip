@@ -212,19 +212,51 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
   __shared__ int s_h[kPlanThreads / 64];
   __shared__ long long s_red[4];
   const int tid = threadIdx.x;
+  const Ctl prev = a.ctl_prev ? *a.ctl_prev : Ctl{0, 0, 0, 0, 0, 0, 0};
+  // ranges of the launch being fixed: the first argmax may split R_1 its own way
+  const int Pfix = (a.first && prev.Pf > 0) ? prev.Pf : prev.P;
+  // Everything read from the kernels before is loaded here, before the first
+  // barrier, so that the round trips overlap: the lane's first cut-row part,
+  // the run table, the per-run live rows, the per-workgroup matched counts and
+  // skipped entries, and (lane 0) the running totals. None of it is written
+  // by this kernel before it is used.
+  constexpr int kPer = kMaxBlocks / kPlanThreads;  // runs per lane in the scan
+  const int nr = (a.mode & kPlanPrefix) ? (a.nruns_new >= 0 ? a.nruns_new : prev.P) : 0;
+  long long le[kPer];
+  int lr[kPer];
+  int sh = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int r = tid * kPer + i;
+    le[i] = 0;
+    lr[i] = 0;
+    if (r < nr) {
+      const Run run = a.runs_new[r];
+      le[i] = run.ent_count;
+      lr[i] = run.row_count;
+      if (a.heads_of_runs) sh += a.heads_of_runs[r].pieces_out;
+    }
+  }
+  long long mc = 0, ml = 0;
+  if (a.mode & kPlanLog) {
+    for (int b = tid; b < prev.Pm; b += kPlanThreads) mc += a.mcount[b];
+    for (int b = tid; b < prev.P; b += kPlanThreads) ml += a.bstat[b].matched_len;
+  }
+  Part pl0;
+  pl0.v = -1;
+  if ((a.mode & kPlanFix) && tid < Pfix) pl0 = a.parts[2 * tid + 1];
+  Totals tot;  // lane 0: the totals as the kernels before left them
   if (tid == 0) {
-    s_err = a.c.totals->err;
+    tot = *a.c.totals;
+    s_err = tot.err;
     s_extra = 0;
     s_red[0] = s_red[1] = s_red[2] = 0;
   }
   __syncthreads();
   if (s_err) return;
-  const Ctl prev = a.ctl_prev ? *a.ctl_prev : Ctl{0, 0, 0, 0, 0, 0, 0};
-  // ranges of the launch being fixed: the first argmax may split R_1 its own way
-  const int Pfix = (a.first && prev.Pf > 0) ? prev.Pf : prev.P;
   if (a.mode & kPlanFix) {
     for (int b = tid; b < Pfix; b += kPlanThreads) {
-      const Part pl = a.parts[2 * b + 1];
+      const Part pl = b == tid ? pl0 : a.parts[2 * b + 1];
       if (pl.v < 0) continue;  // block b does not own a cut row
       Key best;
       best.w = pl.w;
@@ -254,25 +286,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
     }
   }
   __syncthreads();
+  Ctl cn{0, 0, 0, 0, 0, 0, 0};  // lane 0: the live set just planned
   if (a.mode & kPlanPrefix) {
-    const int nr = a.nruns_new >= 0 ? a.nruns_new : prev.P;
-    // blocked scan over nr <= kMaxBlocks runs, 4 per lane
-    constexpr int kPer = kMaxBlocks / kPlanThreads;
-    long long le[kPer];
-    int lr[kPer];
+    // blocked scan over nr <= kMaxBlocks runs, kPer per lane
     long long se = 0;
-    int sr = 0, sh = 0;
+    int sr = 0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      const int r = tid * kPer + i;
-      le[i] = 0;
-      lr[i] = 0;
-      if (r < nr) {
-        const Run run = a.runs_new[r];
-        le[i] = run.ent_count;
-        lr[i] = run.row_count;
-        if (a.heads_of_runs) sh += a.heads_of_runs[r].pieces_out;
-      }
       se += le[i];
       sr += lr[i];
     }
@@ -327,12 +347,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
       long long Pm = ((long long)tr + kMutualRound - 1) / kMutualRound;
       c.Pm = (int)std::max<long long>(tr > 0 ? 1 : 0, std::min<long long>(Pm, a.pmcap));
       *a.ctl_new = c;
+      cn = c;
     }
   }
   if (a.mode & kPlanLog) {
-    long long mc = 0, ml = 0;
-    for (int b = tid; b < prev.Pm; b += kPlanThreads) mc += a.mcount[b];
-    for (int b = tid; b < prev.P; b += kPlanThreads) ml += a.bstat[b].matched_len;
     mc = wave_incl_sum<long long>(mc);
     ml = wave_incl_sum<long long>(ml);
     if (lane_id() == 63) {
@@ -341,7 +359,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-      const int t = a.c.totals->t;
+      const int t = tot.t;
       if (t >= 1 && t <= a.log_cap) {
         LogRec r;
         r.live_entries = prev.L;
@@ -350,26 +368,28 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
         r.matched_entries = s_red[1];
         a.log[t - 1] = r;
       }
-      if (prev.heads > 0) a.c.totals->last_nonempty = t;
-      a.c.totals->matched += (unsigned long long)s_red[0];
+      if (prev.heads > 0) tot.last_nonempty = t;
+      tot.matched += (unsigned long long)s_red[0];
+      a.c.totals->last_nonempty = tot.last_nonempty;
+      a.c.totals->matched = tot.matched;
     }
   }
   if (a.mirror && (a.mode & kPlanPrefix) && tid == 0) {
     PhaseMirror m;
-    m.L = a.ctl_new->L;
-    m.matched = a.c.totals->matched;
-    m.pieces = a.ctl_new->pieces;
-    m.t = a.c.totals->t + ((a.mode & kPlanTick) ? 1 : 0);  // the live set for the next phase
+    m.L = cn.L;
+    m.matched = tot.matched;
+    m.pieces = cn.pieces;
+    m.t = tot.t + ((a.mode & kPlanTick) ? 1 : 0);  // the live set for the next phase
     m.gen = a.gen;
-    m.err = a.c.totals->err;
-    m.last_nonempty = a.c.totals->last_nonempty;
+    m.err = tot.err;
+    m.last_nonempty = tot.last_nonempty;
     m.ready = 0u;
     PhaseMirror* slot = &a.mirror[m.t & (kMirrorSlots - 1)];
     *slot = m;
     __threadfence_system();  // the record reaches host memory before it is marked ready
     *(volatile unsigned*)&slot->ready = a.gen;
   }
-  if ((a.mode & kPlanTick) && tid == 0) a.c.totals->t += 1;
+  if ((a.mode & kPlanTick) && tid == 0) a.c.totals->t = tot.t + 1;
 }
 
 // ---------------------------------------------------------------- run lookup
