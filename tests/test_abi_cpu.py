@@ -101,3 +101,27 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         L.load()
+
+
+def test_constants_match_header():
+    """Flags, status codes, kernel kinds and server modes of the binding are
+    the values include/lm.h defines."""
+    import paper_1302_4587_amd._lib as L
+    text = open(HEADER).read()
+    defs = {}
+    for name, val in re.findall(r"#define\s+(LM_[A-Z0-9_]+)\s+\(?(-?(?:0x)?[0-9a-fA-F]+)u?\)?", text):
+        defs[name] = int(val, 0)
+    names = [n for n in dir(L) if n.startswith("LM_") and isinstance(getattr(L, n), int)]
+    assert {"LM_WEIGHT_SUM", "LM_GRAPH", "LM_IN_DEVICE", "LM_EDEVICE", "LM_SERVE_FIFO"} <= set(names)
+    for n in names:
+        assert n in defs, f"{n} is not defined in lm.h"
+        assert getattr(L, n) == defs[n], f"{n}: binding {getattr(L, n)} vs header {defs[n]}"
+    assert len(L.KERNEL_KINDS) == defs["LM_K_KINDS"]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
