@@ -15,7 +15,7 @@
  * library fixes it so that results are reproducible): the key of the edge
  * {lo, hi}, lo < hi in the graph's own (local) vertex ids, is the pair
  *     ( w  compared as a number (-0 equals +0),
- *       H  = mix( ((uint64)lo << 32 | hi) XOR mix(seed + 0x9E3779B97F4A7C15) )
+ *       H  = mix( ((uint64)lo << 32 | hi) XOR mix(seed XOR 0x9E3779B97F4A7C15) )
  *            compared as an unsigned 64-bit integer ),
  * compared lexicographically; mix is the SplitMix64 output function
  * (z ^= z>>30; z *= 0xBF58476D1CE4E5B9; z ^= z>>27; z *= 0x94D049BB133111EB;

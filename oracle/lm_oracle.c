@@ -24,7 +24,7 @@
  * Tie breaking (the paper perturbs equal weights randomly; the reading fixed
  * here): key(e) = (w(e), H(e)) compared lexicographically, w numerically and
  * H as an unsigned 64-bit integer, with H fixed for the whole run:
- *     S       = mix(seed + GAMMA)              (first SplitMix64 output)
+ *     S       = mix(seed XOR GAMMA)
  *     H(e)    = mix(((uint64)lo << 32 | hi) XOR S),   lo < hi the endpoints
  * where mix is the SplitMix64 output function (Steele, Lea & Flood, OOPSLA
  * 2014). mix and XOR with a constant are bijections, so distinct edges get
@@ -49,8 +49,8 @@ uint64_t lmo_mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-/* Per-run seed mix: the first output of a SplitMix64 generator seeded with s. */
-uint64_t lmo_seed_mix(uint64_t seed) { return lmo_mix64(seed + LMO_GAMMA); }
+/* Per-run seed mix: the seed xored with the SplitMix64 increment, then mixed. */
+uint64_t lmo_seed_mix(uint64_t seed) { return lmo_mix64(seed ^ LMO_GAMMA); }
 
 /* Tie-break value of the undirected edge {lo, hi}, lo < hi, local ids. */
 uint64_t lmo_edge_hash(uint64_t seed, int32_t lo, int32_t hi) {

@@ -1543,6 +1543,6 @@ int max_blocks_per_cu_stream(StreamKind kind, bool unweighted) {
   return stream_blocks_per_cu<false, kLatePPL, false>();
 }
 
-uint64_t premix_seed(uint64_t seed) { return host_mix64(seed + kGoldenGamma); }
+uint64_t premix_seed(uint64_t seed) { return host_mix64(seed ^ kGoldenGamma); }
 
 }  // namespace lm

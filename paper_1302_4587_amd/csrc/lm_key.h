@@ -4,7 +4,7 @@
 // library fixes the perturbation as a hash of the edge so that every run and
 // every schedule selects the same matching:
 //   key({lo,hi}) = ( w as a number, H(seed, lo, hi) as uint64 ), lexicographic
-//   H = mix( ((lo << 32) | hi) XOR mix(seed + gamma) )
+//   H = mix( ((lo << 32) | hi) XOR mix(seed XOR gamma) )
 // with mix the SplitMix64 output function. Weights are compared through an
 // order-preserving map of the fp32 bit pattern (after folding -0 onto +0), so
 // the compare is exact and independent of denormal flushing.

@@ -48,6 +48,18 @@ def load_kat():
     return rows
 
 
+def load_edge_hash_kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "edge_hash_kat.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            s, lo, hi, v = line.split()
+            rows.append((int(s, 0), int(lo, 0), int(hi, 0), int(v, 0)))
+    return rows
+
+
 def mix64_np(z: np.ndarray) -> np.ndarray:
     z = z.astype(np.uint64, copy=True)
     with np.errstate(over="ignore"):
@@ -59,8 +71,18 @@ def mix64_np(z: np.ndarray) -> np.ndarray:
     return z
 
 
+def seed_mix(seed: int) -> int:
+    """Per-run seed mix of the tie-break key: mix(seed XOR gamma)."""
+    return mix64((seed & M64) ^ GAMMA)
+
+
+def edge_hash(seed: int, lo: int, hi: int) -> int:
+    """H(seed, lo, hi) in Python big integers."""
+    return mix64((((lo & 0xFFFFFFFF) << 32) | (hi & 0xFFFFFFFF)) ^ seed_mix(seed))
+
+
 def edge_hash_np(seed: int, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
-    S = np.uint64(splitmix_outputs(seed, 1)[0])
+    S = np.uint64(seed_mix(seed))
     pair = (lo.astype(np.uint64) << np.uint64(32)) | hi.astype(np.uint64)
     return mix64_np(pair ^ S)
 
@@ -84,6 +106,46 @@ def greedy(g, seed: int):
             mate[a] = b
             mate[b] = a
     return mate
+
+
+def edge_ranks(lo, hi, w, seed: int, hash_fn=None) -> np.ndarray:
+    """Rank of every undirected edge in the strict key order (w numerically,
+    -0 == +0, then H unsigned); 0 is the smallest key."""
+    wf = (w.astype(np.float32) + np.float32(0.0)).astype(np.float64)
+    H = edge_hash_np(seed, lo, hi) if hash_fn is None else hash_fn(lo, hi)
+    order = np.lexsort((H, wf))
+    r = np.empty(len(lo), dtype=np.int64)
+    r[order] = np.arange(len(lo), dtype=np.int64)
+    return r
+
+
+def local_max_log(g, seed: int, key_of_phase=None):
+    """Local max by its definition (paper, Section 1), edge by edge: in every
+    phase an edge joins M iff its key beats the key of every other live edge
+    sharing an endpoint; then every edge touching a matched vertex dies.
+    Returns (mate, log) with log rows (|E_t|, V_t, matched_t): live edges and
+    vertices with a live edge at the start of phase t, edges matched in it.
+    key_of_phase(t, lo, hi, w) may give per-phase ranks (renewed keys)."""
+    lo, hi, w = undirected_edges(g)
+    live = np.arange(len(lo))
+    fixed = edge_ranks(lo, hi, w, seed) if key_of_phase is None else None
+    mate = np.full(g.n, -1, dtype=np.int32)
+    log = []
+    t = 0
+    while len(live):
+        t += 1
+        a, b = lo[live], hi[live]
+        r = fixed[live] if fixed is not None else key_of_phase(t, a, b, w[live])
+        best = np.full(g.n, -1, dtype=np.int64)
+        np.maximum.at(best, a, r)
+        np.maximum.at(best, b, r)
+        lm = (best[a] == r) & (best[b] == r)
+        vt = len(np.unique(np.concatenate([a, b])))
+        mate[a[lm]] = b[lm]
+        mate[b[lm]] = a[lm]
+        log.append((len(live), vt, int(lm.sum())))
+        live = live[(mate[a] == -1) & (mate[b] == -1)]
+    return mate, np.array(log, dtype=np.int64).reshape(-1, 3)
 
 
 def is_valid_maximal(g, mate) -> bool:

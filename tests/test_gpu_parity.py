@@ -68,9 +68,13 @@ def test_config1_er_4096(ctx, torch_dev):
     assert np.array_equal(mate, ref.greedy(g, 1))
 
 
-@pytest.mark.parametrize("wkind", ["uniform", "tied", "unit", "signed"])
+DENORMALS = np.array([-2.0**-140, -2.0**-149, -0.0, 0.0, 2.0**-149, 2.0**-148, 2.0**-130, 2.0**-127,
+                      2.0**-126, 1e-30], dtype=np.float32)
+
+
+@pytest.mark.parametrize("wkind", ["uniform", "tied", "unit", "signed", "denormal"])
 def test_random_small_graphs(ctx, torch_dev, wkind):
-    rng = np.random.default_rng({"uniform": 11, "tied": 12, "unit": 13, "signed": 14}[wkind])
+    rng = np.random.default_rng({"uniform": 11, "tied": 12, "unit": 13, "signed": 14, "denormal": 15}[wkind])
     for it in range(40):
         n = int(rng.integers(1, 3000))
         m = int(rng.integers(0, min(n * (n - 1) // 2, 12 * n) + 1))
@@ -81,6 +85,8 @@ def test_random_small_graphs(ctx, torch_dev, wkind):
                 w = rng.integers(1, 4, len(lo)).astype(np.float32)
             elif wkind == "unit":
                 w = np.ones(len(lo), np.float32)
+            elif wkind == "denormal":  # subnormal weights: ordered by value, never flushed to zero
+                w = rng.choice(DENORMALS, len(lo))
             else:
                 w = rng.choice(np.array([-2.5, -0.0, 0.0, 1e-30, 3.0], np.float32), len(lo))
             g = lmgen.from_edges(n, np.stack([lo, hi], 1), w)

@@ -34,26 +34,46 @@ def test_oracle_mix_matches_published_vectors():
         assert oracle.mix64(state) == val
 
 
-def test_oracle_seed_mix_is_first_splitmix_output():
+def _seed_for_state(state: int) -> int:
+    """The seed whose mix input (seed XOR gamma) is the given generator state."""
+    return (state ^ ref.GAMMA) & ref.M64
+
+
+def test_oracle_seed_mix_hits_published_vectors():
+    # seed_mix(s) = mix(s XOR gamma): with s = state XOR gamma for the state
+    # behind a published output, seed_mix must return that output.
     for seed, idx, val in ref.load_kat():
-        if idx == 0:
-            assert oracle.seed_mix(seed) == val
+        state = (seed + (idx + 1) * ref.GAMMA) & ref.M64
+        assert oracle.seed_mix(_seed_for_state(state)) == val
+    # seed 0: 0 XOR gamma = 0 + gamma, the generator's own first output
+    assert oracle.seed_mix(0) == [v for s, i, v in ref.load_kat() if s == 0 and i == 0][0]
 
 
 def test_edge_hash_hits_published_vectors():
-    # Choose the pair so that pair XOR S equals the state behind a published
-    # output; then H must be exactly that output.
-    for seed in (0, 1234567):
-        outs = [v for s, i, v in sorted(ref.load_kat()) if s == seed]
+    # Choose the hash seed so that S = seed_mix(seed) is a published output,
+    # and the pair so that pair XOR S equals the state behind another
+    # published output; then H must be exactly that output.
+    for gseed in (0, 1234567):
+        outs = [v for s, i, v in sorted(ref.load_kat()) if s == gseed]
+        seed = _seed_for_state((gseed + ref.GAMMA) & ref.M64)
         S = outs[0]
+        assert oracle.seed_mix(seed) == S
         for k in range(1, len(outs)):
-            state = (seed + (k + 1) * ref.GAMMA) & ref.M64
+            state = (gseed + (k + 1) * ref.GAMMA) & ref.M64
             pair = state ^ S
             lo = pair >> 32
             hi = pair & 0xFFFFFFFF
             lo_s = lo - (1 << 32) if lo >= 1 << 31 else lo
             hi_s = hi - (1 << 32) if hi >= 1 << 31 else hi
             assert oracle.edge_hash(seed, lo_s, hi_s) == outs[k]
+
+
+def test_edge_hash_contract_values():
+    # known answers of the tie-break contract H(seed, lo, hi), stated with the
+    # key definition and derived from it with big-integer arithmetic
+    for seed, lo, hi, val in ref.load_edge_hash_kat():
+        assert ref.edge_hash(seed, lo, hi) == val
+        assert oracle.edge_hash(seed, lo, hi) == val
 
 
 def test_edge_hash_numpy_reference_agrees():
@@ -80,12 +100,21 @@ def _random_graph(rng, n, m, wkind):
         lo, hi, _ = ref.undirected_edges(g)
         w = rng.choice(np.array([-1.5, -0.0, 0.0, 0.25, 2.0], dtype=np.float32), len(lo))
         return lmgen.from_edges(n, np.stack([lo, hi], 1), w)
+    if wkind == "denormal":
+        lo, hi, _ = ref.undirected_edges(g)
+        return lmgen.from_edges(n, np.stack([lo, hi], 1), rng.choice(DENORMALS, len(lo)))
     return g
 
 
-@pytest.mark.parametrize("wkind", ["uniform", "tied", "unit", "signed"])
+# subnormal fp32 weights (and their neighbours): a compare that flushed them to
+# zero would tie them with +-0 and hand the decision to the hash
+DENORMALS = np.array([-2.0**-140, -2.0**-149, -0.0, 0.0, 2.0**-149, 2.0**-148, 2.0**-130, 2.0**-127,
+                      2.0**-126, 1e-30], dtype=np.float32)
+
+
+@pytest.mark.parametrize("wkind", ["uniform", "tied", "unit", "signed", "denormal"])
 def test_oracle_equals_greedy(wkind):
-    rng = np.random.default_rng({"uniform": 1, "tied": 2, "unit": 3, "signed": 4}[wkind])
+    rng = np.random.default_rng({"uniform": 1, "tied": 2, "unit": 3, "signed": 4, "denormal": 5}[wkind])
     for _ in range(120):
         n = int(rng.integers(2, 60))
         m = int(rng.integers(0, min(n * (n - 1) // 2, 4 * n) + 1))
@@ -202,6 +231,70 @@ def test_lemma1_removal_fraction_unit_weights():
     mean = float(np.mean(fr))
     assert mean >= 0.5
     assert 0.6 <= mean <= 0.95  # about 3/4 per footnote 4
+
+
+@pytest.mark.parametrize("wkind", ["uniform", "tied", "unit", "signed", "denormal"])
+def test_phase_log_equals_edge_definition(wkind):
+    # every column of the oracle's log, phase by phase, against the
+    # edge-by-edge local-max definition (ranks, not candidates)
+    rng = np.random.default_rng({"uniform": 21, "tied": 22, "unit": 23, "signed": 24, "denormal": 25}[wkind])
+    for _ in range(60):
+        n = int(rng.integers(2, 200))
+        m = int(rng.integers(0, min(n * (n - 1) // 2, 5 * n) + 1))
+        g = _random_graph(rng, n, m, wkind)
+        seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+        mate, log = oracle.local_max_graph(g, seed)
+        rm, rlog = ref.local_max_log(g, seed)
+        assert np.array_equal(mate, rm)
+        assert np.array_equal(log, rlog), (n, m, seed)
+
+
+def test_phase_log_first_row_counts_the_input():
+    # |E_1| = m and V_1 = vertices of positive degree, on every family
+    for g in (lmgen.er(3000, 2000, 4), lmgen.rgg(4000, 10.0, 2), lmgen.rmat(12, 16, seed=3),
+              lmgen.er(500, 0, 1)):
+        _, log = oracle.local_max_graph(g, 1)
+        if g.m == 0:
+            assert len(log) == 0
+            continue
+        assert log[0, 0] == g.m
+        assert log[0, 1] == int((np.diff(g.row_ptr) > 0).sum())
+
+
+def test_phase_log_closed_forms():
+    # star of k leaves: one phase, k edges, k + 1 live vertices
+    k = 23
+    g = lmgen.from_edges(k + 5, [[3, i] for i in range(k + 5) if i != 3][:k], np.arange(1, k + 1))
+    _, log = oracle.local_max_graph(g, 1)
+    assert log.tolist() == [[k, k + 1, 1]]
+    # k disjoint edges: one phase, 2k live vertices, k matched
+    e = [[2 * i, 2 * i + 1] for i in range(k)]
+    _, log = oracle.local_max_graph(lmgen.from_edges(2 * k + 4, e, np.ones(k)), 5)
+    assert log.tolist() == [[k, 2 * k, k]]
+    # increasing path of k edges: |E_t| = k - 2(t-1), V_t = k - 2t + 3, one match per phase
+    for k in (1, 2, 5, 12, 33):
+        g = lmgen.from_edges(k + 1, [[i, i + 1] for i in range(k)], np.arange(1, k + 1))
+        _, log = oracle.local_max_graph(g, 1)
+        want = [[k - 2 * (t - 1), k - 2 * t + 3, 1] for t in range(1, math.ceil(k / 2) + 1)]
+        assert log.tolist() == want, k
+    # triangle with a light pendant edge at vertex 0: phase 1 matches the
+    # heaviest triangle edge {1,2} and kills {0,1} and {0,2}; the pendant
+    # edge {0,3} is alone in phase 2
+    g = lmgen.from_edges(4, [[0, 1], [1, 2], [0, 2], [0, 3]], [0.5, 0.9, 0.7, 0.1])
+    mate, log = oracle.local_max_graph(g, 1)
+    assert log.tolist() == [[4, 4, 1], [1, 2, 1]]
+    assert mate.tolist() == [3, 2, 1, 0]
+
+
+def test_denormal_weights_order_by_value():
+    # a star whose leaves carry distinct subnormal weights: the centre takes the
+    # largest by value, never a tie broken by the hash
+    w = np.array([2.0**-149, 2.0**-140, 2.0**-135, 2.0**-133, 2.0**-128], dtype=np.float32)
+    for perm in ([0, 1, 2, 3, 4], [4, 3, 2, 1, 0], [2, 4, 0, 3, 1]):
+        g = lmgen.from_edges(6, [[0, i + 1] for i in range(5)], w[perm])
+        for seed in (1, 2, 3):
+            mate, _ = oracle.local_max_graph(g, seed)
+            assert mate[0] == 1 + perm.index(4)
 
 
 def test_log_consistency():
