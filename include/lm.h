@@ -157,6 +157,28 @@ lm_status lm_match_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, in
                          const int32_t* col, const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate,
                          uint32_t flags, void* stream, lm_stats* stats, int32_t* graph_phases);
 
+/* Allocation-free variant of lm_match, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation). Same result, statistics and
+ * errors as lm_match with the same flags, with these limits:
+ *  - flags must include LM_IN_DEVICE | LM_OUT_DEVICE (host buffers would need
+ *    staging) and may add LM_CHECK_GRAPH; any other flag gives LM_EINVAL;
+ *  - the working buffers come from one device array of
+ *    LM_NOALLOC_SCRATCH_BYTES per GPU (held from the first lm_create on that
+ *    GPU until the process ends), not from the context's pool; a graph needs
+ *    37 n + 16 nnz bytes plus about 0.85 MiB of tables (each piece rounded up
+ *    to 256 bytes), and a larger one gives LM_ETOOBIG before any device work
+ *    (for example n = 2^19 with nnz up to 2.9 M entries fits);
+ *  - the call makes no hipMalloc, hipFree, pinned or other device allocation.
+ * Every call on one GPU shares that GPU's array, whose contents persist from
+ * the last call (the solve clears what it needs): calls that overlap in time
+ * on one GPU, from any contexts or streams, race and must be serialised by
+ * the caller. stream as in lm_match (NULL = the legacy default stream); the
+ * call returns once mate holds the result. */
+#define LM_NOALLOC_SCRATCH_BYTES 0x4000000u /* 64 MiB */
+lm_status lm_match_noalloc(lm_ctx* ctx, const lm_csr* g, uint64_t seed, int32_t* mate, uint32_t flags, void* stream,
+                           lm_stats* stats);
+
 /* Tuning knobs of the phase kernels. Results never depend on them.
  * block_entries: the least number of live entries a compaction workgroup
  * streams (the live entries are cut into at most grid_per_cu * CUs ranges

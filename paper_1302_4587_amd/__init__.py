@@ -181,6 +181,34 @@ class Context:
               "lm_match")
         return mate, _stats_out(st, logbuf, weight_sum)
 
+    def match_noalloc(self, row_ptr, col, w, seed: int = 1, mate=None, *, check_graph=False, stream=None,
+                      log_cap: int = 4096):
+        """lm_match_noalloc: the allocation-free solve of one graph whose tensors
+        are on the device (working buffers from the library's fixed per-GPU
+        scratch array). Returns (mate, MatchStats)."""
+        n = int(row_ptr.shape[0]) - 1
+        nnz = int(col.shape[0])
+        rp, d0, k0 = _ptr(row_ptr, np.int64)
+        cp, d1, k1 = _ptr(col, np.int32)
+        wp, d2, k2 = _ptr(w, np.float32, d0)
+        if not (d0 and d1 and d2):
+            raise ValueError("match_noalloc takes device tensors only")
+        if mate is None:
+            import torch
+            mate = torch.empty(max(n, 0), dtype=torch.int32, device=row_ptr.device)
+        mp, dm, km = _ptr(mate, np.int32)
+        if not dm:
+            raise ValueError("match_noalloc writes a device tensor")
+        flags, s = self._flags_stream(True, True, check_graph, False, stream)
+        g = _lib.Csr(n, nnz, rp, cp, wp)
+        logbuf = self._logbuf(log_cap)
+        st = _lib.Stats()
+        st.log = logbuf
+        st.log_cap = log_cap
+        check(self._lib.lm_match_noalloc(self._h, ctypes.byref(g), seed & (2**64 - 1), mp, flags, s,
+                                         ctypes.byref(st)), "lm_match_noalloc")
+        return mate, _stats_out(st, logbuf)
+
     def match_batch(self, vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1, mate=None, *, check_graph=False,
                     profile=False, stream=None, log_cap: int = 4096, want_graph_phases=True, hip_graph=True,
                     weight_sum=False):

@@ -34,6 +34,9 @@ LM_PROFILE = 0x8
 LM_GRAPH = 0x10
 LM_WEIGHT_SUM = 0x20
 
+# bytes of the per-GPU scratch array of lm_match_noalloc
+LM_NOALLOC_SCRATCH_BYTES = 0x4000000
+
 LM_K_INIT, LM_K_ARGMAX, LM_K_MUTUAL, LM_K_COMPACT, LM_K_PLAN = range(5)
 KERNEL_KINDS = ("init", "argmax", "mutual", "compact", "plan")
 
@@ -41,7 +44,7 @@ LM_SERVE_BATCHED = 0
 LM_SERVE_FIFO = 1
 
 EXPORTED = (
-    "lm_create", "lm_destroy", "lm_match", "lm_match_batch", "lm_get_tuning", "lm_set_tuning",
+    "lm_create", "lm_destroy", "lm_match", "lm_match_noalloc", "lm_match_batch", "lm_get_tuning", "lm_set_tuning",
     "lm_autotune_batch", "lm_server_create", "lm_server_submit", "lm_server_poll", "lm_server_wait",
     "lm_server_destroy", "lm_strerror",
 )
@@ -97,6 +100,7 @@ def load():
     lib.lm_destroy.argtypes = [vp]
     lib.lm_destroy.restype = None
     lib.lm_match.argtypes = [vp, ctypes.POINTER(Csr), u64, vp, u32, vp, ctypes.POINTER(Stats)]
+    lib.lm_match_noalloc.argtypes = [vp, ctypes.POINTER(Csr), u64, vp, u32, vp, ctypes.POINTER(Stats)]
     lib.lm_match_batch.argtypes = [vp, i32, vp, i64, vp, vp, vp, vp, u64, vp, u32, vp, ctypes.POINTER(Stats), vp]
     lib.lm_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.lm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -108,7 +112,7 @@ def load():
     lib.lm_server_destroy.argtypes = [vp]
     lib.lm_strerror.argtypes = [i32]
     lib.lm_strerror.restype = ctypes.c_char_p
-    for f in ("lm_create", "lm_match", "lm_match_batch", "lm_get_tuning", "lm_set_tuning", "lm_autotune_batch",
+    for f in ("lm_create", "lm_match", "lm_match_noalloc", "lm_match_batch", "lm_get_tuning", "lm_set_tuning", "lm_autotune_batch",
               "lm_server_create", "lm_server_submit", "lm_server_poll", "lm_server_wait", "lm_server_destroy"):
         getattr(lib, f).restype = i32
     _lib = lib

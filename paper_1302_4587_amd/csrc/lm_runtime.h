@@ -33,6 +33,33 @@ struct Pool {
   void release(DevBuf& b);
 };
 
+// Device working buffers of one solve (beyond inputs and outputs): from the
+// context's pool (Solver::pool_work) or carved from one caller-independent
+// region (carve_work).
+struct Work {
+  int* C = nullptr;
+  unsigned char* state = nullptr;
+  int4* rows[2] = {nullptr, nullptr};
+  int* ecol[2] = {nullptr, nullptr};
+  float* ew[2] = {nullptr, nullptr};
+  Run* runs[2] = {nullptr, nullptr};
+  long long* epre[2] = {nullptr, nullptr};
+  int* rpre[2] = {nullptr, nullptr};
+  Ctl* ctl = nullptr;
+  Part* parts = nullptr;
+  BlockStat* bstat = nullptr;
+  int* mcount = nullptr;
+  int* gbase = nullptr;
+  unsigned long long* gseed = nullptr;
+  long long* vtxoff = nullptr;
+  Totals* totals = nullptr;
+};
+
+// Lays the working buffers of a solve of N vertices, nnz entries and G graphs
+// out from base (256-byte aligned pieces) and returns the bytes used; with
+// base == nullptr only the size is computed.
+size_t carve_work(int64_t N, int64_t nnz, int64_t G, void* base, Work* w);
+
 // Device-resident problem: the union of G graphs (G = 1 for lm_match).
 struct Problem {
   int64_t N = 0, nnz = 0, G = 1;
@@ -88,7 +115,8 @@ struct Solver {
   lm_status init_device(int device, size_t budget);
   void shutdown();
   lm_status prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase);
-  lm_status run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st);
+  Work pool_work() const;  // the pool's buffers, after prepare
+  lm_status run(const Problem& p, const Work& wk, hipStream_t s, uint32_t flags, lm_stats* st);
   hipEvent_t event(size_t i);
 };
 
@@ -99,6 +127,9 @@ hipError_t launch_weight_sum(const long long* row_ptr, const int* col, const flo
                              double* scratch, hipStream_t s);
 
 const char* status_text(lm_status st);
+// Looks up this device's copy of the allocation-free solve's scratch array
+// (lm_match_noalloc); called once per device with that device current.
+lm_status noalloc_setup(int dev);
 lm_status dev_status(hipError_t e);
 size_t solve_footprint(int64_t N, int64_t nnz, int64_t G);
 

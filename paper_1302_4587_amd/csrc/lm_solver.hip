@@ -125,6 +125,59 @@ lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
   return LM_OK;
 }
 
+Work Solver::pool_work() const {
+  Work w;
+  w.C = (int*)C.p;
+  w.state = (unsigned char*)state.p;
+  for (int i = 0; i < 2; ++i) {
+    w.rows[i] = (int4*)rows[i].p;
+    w.ecol[i] = (int*)ecol[i].p;
+    w.ew[i] = (float*)ew[i].p;
+    w.runs[i] = (Run*)runs[i].p;
+    w.epre[i] = (long long*)epre[i].p;
+    w.rpre[i] = (int*)rpre[i].p;
+  }
+  w.ctl = (Ctl*)ctl.p;
+  w.parts = (Part*)parts.p;
+  w.bstat = (BlockStat*)bstat.p;
+  w.mcount = (int*)mcount.p;
+  w.gbase = (int*)gbase.p;
+  w.gseed = (unsigned long long*)gseed.p;
+  w.vtxoff = (long long*)vtxoff.p;
+  w.totals = (Totals*)totals.p;
+  return w;
+}
+
+size_t carve_work(int64_t N, int64_t nnz, int64_t G, void* base, Work* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)((char*)base + off) : nullptr;
+    off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return p;
+  };
+  Work x;
+  x.C = (int*)take((size_t)N * 4);
+  x.state = (unsigned char*)take((size_t)N);
+  for (int i = 0; i < 2; ++i) {
+    x.rows[i] = (int4*)take(((size_t)N + 2 * kMaxBlocks + 16) * 16);
+    x.ecol[i] = (int*)take((size_t)nnz * 4);
+    x.ew[i] = (float*)take((size_t)nnz * 4);
+    x.runs[i] = (Run*)take((size_t)kMaxBlocks * sizeof(Run));
+    x.epre[i] = (long long*)take((size_t)(kMaxBlocks + 1) * 8);
+    x.rpre[i] = (int*)take((size_t)(kMaxBlocks + 1) * 4);
+  }
+  x.ctl = (Ctl*)take(2 * sizeof(Ctl));
+  x.parts = (Part*)take((size_t)kMaxBlocks * 2 * sizeof(Part));
+  x.bstat = (BlockStat*)take((size_t)kMaxBlocks * sizeof(BlockStat));
+  x.mcount = (int*)take((size_t)kMaxBlocks * 4);
+  x.gbase = (int*)take((size_t)G * 4);
+  x.gseed = (unsigned long long*)take((size_t)G * 8);
+  x.vtxoff = (long long*)take((size_t)(G + 1) * 8);
+  x.totals = (Totals*)take(sizeof(Totals));
+  if (w) *w = x;
+  return off;
+}
+
 lm_status Solver::init_device(int device, size_t budget) {
   dev = device;
   pool.budget = budget;
@@ -149,6 +202,7 @@ lm_status Solver::init_device(int device, size_t budget) {
   std::memset(h_mir, 0, sizeof(PhaseMirror) * kMirrorSlots);
   if (hipHostGetDevicePointer((void**)&d_mir, h_mir, 0) != hipSuccess) return LM_EDEVICE;
   if (hipHostGetDevicePointer((void**)&d_log, h_log, 0) != hipSuccess) return LM_EDEVICE;
+  if (noalloc_setup(device) != LM_OK) return LM_EDEVICE;
   bpc_stream = max_blocks_per_cu_stream(StreamKind::kCompact);
   bpc_first = max_blocks_per_cu_stream(StreamKind::kFirst);
   bpc_late = max_blocks_per_cu_stream(StreamKind::kLateCompact);
@@ -202,7 +256,7 @@ hipEvent_t Solver::event(size_t i) {
 }
 
 // Runs the phase loop over a problem whose inputs are already on the device.
-lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats* st) {
+lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t flags, lm_stats* st) {
   const bool prof = (flags & LM_PROFILE) != 0;
   if (++gen == 0) gen = 1;  // 0 marks a never-written mirror slot
   const bool unweighted = p.w == nullptr;  // no weight array: every edge weighs 1
@@ -250,17 +304,17 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
   const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, bf)));
   const int pcap_late = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bl))));
   const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
-  Ctl* dctl = (Ctl*)ctl.p;
-  Totals* dtot = (Totals*)totals.p;
+  Ctl* dctl = wk.ctl;
+  Totals* dtot = wk.totals;
 
   Common c;
   c.totals = dtot;
   c.n = (int)p.N;
-  c.C = (int*)C.p;
-  c.state = (unsigned char*)state.p;
+  c.C = wk.C;
+  c.state = wk.state;
   c.mate = p.mate;
-  c.gbase = (const int*)gbase.p;
-  c.gseed = (const unsigned long long*)gseed.p;
+  c.gbase = wk.gbase;
+  c.gseed = wk.gseed;
   c.gphase = p.gphase;
   c.graphs = (int)p.G;
 
@@ -268,12 +322,12 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     const int i = (t - 1) & 1;
     LiveSet L;
     L.ctl = dctl + i;
-    L.runs = (const Run*)runs[i].p;
-    L.epre = (const long long*)epre[i].p;
-    L.rpre = (const int*)rpre[i].p;
-    L.rows = (int4*)rows[i].p;
-    L.col = t == 1 ? p.col : (const int*)ecol[t & 1].p;
-    L.w = t == 1 ? p.w : (const float*)ew[t & 1].p;
+    L.runs = wk.runs[i];
+    L.epre = wk.epre[i];
+    L.rpre = wk.rpre[i];
+    L.rows = wk.rows[i];
+    L.col = t == 1 ? p.col : wk.ecol[t & 1];
+    L.w = t == 1 ? p.w : wk.ew[t & 1];
     L.csr_rp = (t == 1 && csr1) ? p.row_ptr : nullptr;
     return L;
   };
@@ -290,7 +344,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     a.log_cap = kLogCap;
     a.mirror = d_mir;
     a.gen = gen;
-    a.mcount = (const int*)mcount.p;
+    a.mcount = wk.mcount;
     return a;
   };
 
@@ -325,10 +379,10 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     ia.nblocks = pi;
     ia.rows_base = 0;
     ia.runs_base = 0;
-    ia.runs_out = (Run*)runs[0].p;
-    ia.rows_out = (int4*)rows[0].p;
+    ia.runs_out = wk.runs[0];
+    ia.rows_out = wk.rows[0];
     ia.csr = csr1 ? 1 : 0;
-    ia.bstat = (BlockStat*)bstat.p;
+    ia.bstat = wk.bstat;
     ENQ(launch_init(ia, s, timing(LM_K_INIT)));
     PlanArgs pa = plan_base();  // R_1: split for the first compaction and, apart, the first argmax
     pa.mode = kPlanPrefix;
@@ -336,19 +390,19 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     pa.pcap_first = pcap_first;
     pa.pieces_per_block = kBlock;
     pa.ctl_prev = nullptr;
-    pa.runs_new = (const Run*)runs[0].p;
+    pa.runs_new = wk.runs[0];
     pa.nruns_new = pi;
-    pa.epre_new = (long long*)epre[0].p;
-    pa.rpre_new = (int*)rpre[0].p;
+    pa.epre_new = wk.epre[0];
+    pa.rpre_new = wk.rpre[0];
     pa.ctl_new = dctl + 0;
-    pa.heads_of_runs = csr1 ? (const BlockStat*)bstat.p : nullptr;
+    pa.heads_of_runs = csr1 ? wk.bstat : nullptr;
     ENQ(launch_plan(pa, s, timing(LM_K_PLAN)));
     StreamArgs sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.c = c;
     sa.in = live(1);
-    sa.parts = (Part*)parts.p;
-    sa.bstat = (BlockStat*)bstat.p;
+    sa.parts = wk.parts;
+    sa.bstat = wk.bstat;
     const int gx =
         (int)std::max<int64_t>(1, std::min<int64_t>(pcap_first, p.nnz / std::max(kCap, tun.block_entries) + 1));
     ENQ(launch_first_argmax(sa, gx, s, unweighted, timing(LM_K_ARGMAX)));
@@ -356,7 +410,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     pf.mode = kPlanFix;
     pf.first = 1;
     pf.ctl_prev = dctl + 0;
-    pf.parts = (Part*)parts.p;
+    pf.parts = wk.parts;
     ENQ(launch_plan(pf, s, timing(LM_K_PLAN)));
     return hipSuccess;
   };
@@ -367,7 +421,7 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     MutualArgs ma;
     ma.c = c;
     ma.in = in;
-    ma.mcount = (int*)mcount.p;
+    ma.mcount = wk.mcount;
     ma.census = 0;
     const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(pmcap, est_V / kMutualRound + 1));
     ENQ(launch_mutual(ma, gm, s, timing(LM_K_MUTUAL)));
@@ -375,12 +429,12 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     StreamArgs sa;
     sa.c = c;
     sa.in = in;
-    sa.runs_out = (Run*)runs[lo].p;
-    sa.rows_out = (int4*)rows[lo].p;
-    sa.dst_col = (int*)ecol[(t + 1) & 1].p;
-    sa.dst_w = (float*)ew[(t + 1) & 1].p;
-    sa.parts = (Part*)parts.p;
-    sa.bstat = (BlockStat*)bstat.p;
+    sa.runs_out = wk.runs[lo];
+    sa.rows_out = wk.rows[lo];
+    sa.dst_col = wk.ecol[(t + 1) & 1];
+    sa.dst_w = wk.ew[(t + 1) & 1];
+    sa.parts = wk.parts;
+    sa.bstat = wk.bstat;
     const bool late = t > 1;
     const int gx = (int)std::max<int64_t>(
         1, std::min<int64_t>(late ? pcap_late : pcap,
@@ -391,12 +445,12 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     pa.pcap = pcap_late;
     pa.mode = kPlanFix | kPlanPrefix | kPlanLog | kPlanTick;
     pa.ctl_prev = in.ctl;
-    pa.parts = (Part*)parts.p;
-    pa.bstat = (BlockStat*)bstat.p;
-    pa.rows_out = (int4*)rows[lo].p;
-    pa.runs_new = (const Run*)runs[lo].p;
-    pa.epre_new = (long long*)epre[lo].p;
-    pa.rpre_new = (int*)rpre[lo].p;
+    pa.parts = wk.parts;
+    pa.bstat = wk.bstat;
+    pa.rows_out = wk.rows[lo];
+    pa.runs_new = wk.runs[lo];
+    pa.epre_new = wk.epre[lo];
+    pa.rpre_new = wk.rpre[lo];
     pa.ctl_new = dctl + lo;
     ENQ(launch_plan(pa, s, timing(LM_K_PLAN)));
     ++t;
@@ -525,14 +579,14 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
       st->k_launches[m.first] += 1;
       st->k_ms[m.first] += km;
     }
+    // the records are read straight from the mapped log (complete once e1 has
+    // passed); the record after the last one counts as empty
     const int nrec = std::min(phases, kLogCap);
-    std::vector<LogRec> recs((size_t)nrec + 1);
-    if (nrec > 0) std::memcpy(recs.data(), h_log, sizeof(LogRec) * (size_t)nrec);
-    recs[(size_t)nrec] = LogRec{0, 0, 0, 0};
+    auto recs = [&](int i) -> LogRec { return i < nrec ? h_log[i] : LogRec{0, 0, 0, 0}; };
     st->log_len = 0;
     if (st->log && st->log_cap > 0) {
       const int nl = std::min(nrec, st->log_cap);
-      std::memcpy(st->log, recs.data(), sizeof(LogRec) * (size_t)nl);
+      if (nl > 0) std::memcpy(st->log, h_log, sizeof(LogRec) * (size_t)nl);
       st->log_len = nl;
     }
     // algorithmic bytes per kernel kind (what each must move, from the log).
@@ -542,15 +596,15 @@ lm_status Solver::run(const Problem& p, hipStream_t s, uint32_t flags, lm_stats*
     // the compaction (which adds state[v]), C[v] of every vertex in the mutual
     // check, and k_init clears C instead of writing records.
     const double N = (double)p.N;
-    const double V1 = nrec > 0 ? (double)recs[0].live_rows : 0.0;
-    const double L1 = nrec > 0 ? (double)recs[0].live_entries : 0.0;
+    const double V1 = nrec > 0 ? (double)recs(0).live_rows : 0.0;
+    const double L1 = nrec > 0 ? (double)recs(0).live_entries : 0.0;
     st->k_bytes[LM_K_INIT] = 8.0 * (N + 1.0) + (csr1 ? 9.0 * N : 5.0 * N + 16.0 * V1);
     const double eb = unweighted ? 4.0 : 8.0;  // bytes of one entry: col (+ w)
     st->k_bytes[LM_K_ARGMAX] = (csr1 ? 8.0 * (N + 1.0) : 16.0 * V1) + eb * L1 + 4.0 * V1;
     for (int i = 0; i < nrec; ++i) {
-      const double L = (double)recs[i].live_entries, V = (double)recs[i].live_rows;
-      const double mv = 2.0 * (double)recs[i].matched_edges, md = (double)recs[i].matched_entries;
-      const double L2 = (double)recs[i + 1].live_entries, V2 = (double)recs[i + 1].live_rows;
+      const double L = (double)recs(i).live_entries, V = (double)recs(i).live_rows;
+      const double mv = 2.0 * (double)recs(i).matched_edges, md = (double)recs(i).matched_entries;
+      const double L2 = (double)recs(i + 1).live_entries, V2 = (double)recs(i + 1).live_rows;
       const bool from_csr = csr1 && i == 0;
       st->k_bytes[LM_K_MUTUAL] += from_csr ? 4.0 * N + 4.0 * V + 5.0 * mv : 24.0 * V + 9.0 * mv;
       st->k_bytes[LM_K_COMPACT] += (from_csr ? 9.0 * N : 16.0 * V) + (eb + 1.0) * (L - md) + eb * L2 + 20.0 * V2;
@@ -791,7 +845,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   lm_stats local;
   std::memset(&local, 0, sizeof(local));
   lm_stats* sp = st ? st : &local;
-  rs = S.run(p, s, flags, sp);
+  rs = S.run(p, S.pool_work(), s, flags, sp);
   if (rs != LM_OK) return rs;
   double wsum = 0.0;
   const bool want_w = st && (flags & LM_WEIGHT_SUM);
