@@ -76,10 +76,17 @@ typedef int32_t lm_status;
 #define LM_CHECK_GRAPH 0x4u  /* validate ids, self-loops, weights (and, for host
                                 inputs, symmetry and duplicates) before solving */
 #define LM_PROFILE 0x8u      /* time every kernel launch with HIP events */
-#define LM_GRAPH 0x10u       /* enqueue the set-up and the first phases as one captured
-                                HIP graph launch (one launch, no host round trip);
-                                ignored together with LM_PROFILE; same results */
+#define LM_GRAPH 0x10u       /* run the whole solve as one captured HIP graph launch: set-up,
+                                a fixed number of phases that do nothing once the tail kernel
+                                has taken over, and the tail kernel (no host round trip);
+                                ignored together with LM_PROFILE or LM_ASYNC; same results */
 #define LM_WEIGHT_SUM 0x20u  /* after the solve, set stats->matched_weight (needs stats) */
+#define LM_ASYNC 0x40u       /* stream-ordered: enqueue the whole solve on `stream` and return
+                                at once; mate holds the result when the stream reaches that
+                                point. Needs LM_IN_DEVICE | LM_OUT_DEVICE and stats == NULL
+                                (batch: graph_phases == NULL); LM_CHECK_GRAPH, LM_PROFILE and
+                                LM_WEIGHT_SUM are refused (LM_EINVAL). A later call on the same
+                                context first waits for the pending solve to finish. */
 
 typedef struct lm_ctx lm_ctx;
 typedef struct lm_server lm_server;
@@ -109,7 +116,8 @@ typedef struct {
 #define LM_K_MUTUAL 2   /* mutual-candidate check and matched marking */
 #define LM_K_COMPACT 3  /* edge compaction fused with the next argmax */
 #define LM_K_PLAN 4     /* single-workgroup stitching of cut rows and run-table scan */
-#define LM_K_KINDS 5
+#define LM_K_TAIL 5     /* persistent launch running every phase from a small live set on */
+#define LM_K_KINDS 6
 
 typedef struct {
   int32_t phases;         /* phases with at least one live edge */
@@ -141,8 +149,9 @@ lm_status lm_create(int device, size_t hbm_budget_bytes, lm_ctx** out);
 void lm_destroy(lm_ctx* ctx);
 
 /* Solves one graph. seed selects the tie-break hash. stream is a
- * hipStream_t (NULL = the context's own stream); the call returns after the
- * result is in mate. stats may be NULL. */
+ * hipStream_t (NULL = the legacy default stream); the call returns after the
+ * result is in mate (with LM_ASYNC: after enqueueing the solve on stream).
+ * stats may be NULL. */
 lm_status lm_match(lm_ctx* ctx, const lm_csr* g, uint64_t seed, int32_t* mate, uint32_t flags, void* stream,
                    lm_stats* stats);
 
@@ -187,6 +196,12 @@ typedef struct {
   int32_t block_entries;   /* 2048..4194304 */
   int32_t grid_per_cu;     /* workgroups per compute unit at most, 1..16 (default 16: each kernel's resident count) */
   int32_t phases_per_sync; /* phases kept queued past the live set the host checks for emptiness, 1..64 (32 used at most) */
+  int32_t tail_entries;    /* 0..2^30: the phases from the first live set of at most this many
+                              entries on run in one persistent launch (device-controlled
+                              solves: LM_GRAPH, LM_ASYNC); a host-polled solve hands over one
+                              phase after a live set of at most 4x this many (it keeps one phase
+                              queued ahead). 0: host-polled solves never hand over (default
+                              2^20) */
 } lm_tuning;
 
 lm_status lm_get_tuning(lm_ctx* ctx, lm_tuning* out);

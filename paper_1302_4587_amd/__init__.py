@@ -17,8 +17,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _lib
-from ._lib import (KERNEL_KINDS, LM_CHECK_GRAPH, LM_GRAPH, LM_IN_DEVICE, LM_OUT_DEVICE, LM_PROFILE, LM_SERVE_BATCHED,
-                   LM_SERVE_FIFO, LM_WEIGHT_SUM, LMError, check)
+from ._lib import (KERNEL_KINDS, LM_ASYNC, LM_CHECK_GRAPH, LM_GRAPH, LM_IN_DEVICE, LM_OUT_DEVICE, LM_PROFILE,
+                   LM_SERVE_BATCHED, LM_SERVE_FIFO, LM_WEIGHT_SUM, LMError, check)
 
 __all__ = ["Context", "Server", "MatchStats", "LMError", "library_path", "LM_SERVE_BATCHED", "LM_SERVE_FIFO"]
 
@@ -129,19 +129,22 @@ class Context:
         t = _lib.Tuning()
         check(self._lib.lm_get_tuning(self._h, ctypes.byref(t)), "lm_get_tuning")
         return {"block_entries": t.block_entries, "grid_per_cu": t.grid_per_cu,
-                "phases_per_sync": t.phases_per_sync}
+                "phases_per_sync": t.phases_per_sync, "tail_entries": t.tail_entries}
 
-    def set_tuning(self, block_entries=None, grid_per_cu=None, phases_per_sync=None):
+    def set_tuning(self, block_entries=None, grid_per_cu=None, phases_per_sync=None, tail_entries=None):
         cur = self.tuning()
         t = _lib.Tuning(block_entries or cur["block_entries"], grid_per_cu or cur["grid_per_cu"],
-                        phases_per_sync or cur["phases_per_sync"])
+                        phases_per_sync or cur["phases_per_sync"],
+                        cur["tail_entries"] if tail_entries is None else tail_entries)
         check(self._lib.lm_set_tuning(self._h, ctypes.byref(t)), "lm_set_tuning")
 
     # -------------------------------------------------------------- solves
-    def _flags_stream(self, dev_in, dev_out, check_graph, profile, stream, hip_graph=False, weight_sum=False):
+    def _flags_stream(self, dev_in, dev_out, check_graph, profile, stream, hip_graph=False, weight_sum=False,
+                      asynchronous=False):
         flags = (LM_IN_DEVICE if dev_in else 0) | (LM_OUT_DEVICE if dev_out else 0)
         flags |= (LM_CHECK_GRAPH if check_graph else 0) | (LM_PROFILE if profile else 0)
         flags |= (LM_GRAPH if hip_graph else 0) | (LM_WEIGHT_SUM if weight_sum else 0)
+        flags |= LM_ASYNC if asynchronous else 0
         s = None
         if stream is not None:
             s = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", None)
@@ -151,10 +154,12 @@ class Context:
         return flags, s
 
     def match(self, row_ptr, col, w, seed: int = 1, mate=None, *, check_graph=False, profile=False, stream=None,
-              log_cap: int = 4096, hip_graph=False, profile_kinds=None, weight_sum=False):
-        """Solves one graph. Returns (mate, MatchStats). hip_graph=True enqueues the
-        set-up and first phases as one captured HIP graph (LM_GRAPH); weight_sum=True
-        also returns w(M) in MatchStats.matched_weight (LM_WEIGHT_SUM)."""
+              log_cap: int = 4096, hip_graph=False, profile_kinds=None, weight_sum=False, asynchronous=False):
+        """Solves one graph. Returns (mate, MatchStats). hip_graph=True runs the
+        whole solve as one captured HIP graph (LM_GRAPH); weight_sum=True also
+        returns w(M) in MatchStats.matched_weight (LM_WEIGHT_SUM);
+        asynchronous=True (LM_ASYNC, device tensors only) enqueues the solve on
+        the stream and returns (mate, None) at once."""
         n = int(row_ptr.shape[0]) - 1
         nnz = int(col.shape[0])
         rp, d0, k0 = _ptr(row_ptr, np.int64)
@@ -169,8 +174,11 @@ class Context:
             else:
                 mate = np.empty(max(n, 0), dtype=np.int32)
         mp, dm, km = _ptr(mate, np.int32)
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum, asynchronous)
         g = _lib.Csr(n, nnz, rp, cp, wp)
+        if asynchronous:
+            check(self._lib.lm_match(self._h, ctypes.byref(g), seed & (2**64 - 1), mp, flags, s, None), "lm_match")
+            return mate, None
         logbuf = self._logbuf(log_cap)
         st = _lib.Stats()
         st.log = logbuf
@@ -211,10 +219,11 @@ class Context:
 
     def match_batch(self, vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1, mate=None, *, check_graph=False,
                     profile=False, stream=None, log_cap: int = 4096, want_graph_phases=True, hip_graph=True,
-                    weight_sum=False):
+                    weight_sum=False, asynchronous=False):
         """Solves a batch (disjoint union, local ids) in one captured HIP graph
         launch unless hip_graph=False or profile=True. Returns (mate, MatchStats,
-        graph_phases)."""
+        graph_phases); with asynchronous=True (LM_ASYNC) (mate, None, None) at
+        once."""
         vo = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
         G = len(vo) - 1
         N = int(vo[-1])
@@ -236,7 +245,11 @@ class Context:
         if seeds is not None:
             sk = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
             sp = sk.ctypes.data
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum, asynchronous)
+        if asynchronous:
+            check(self._lib.lm_match_batch(self._h, G, vo.ctypes.data, nnz, rp, cp, wp, sp, seed0 & (2**64 - 1), mp,
+                                           flags, s, None, None), "lm_match_batch")
+            return mate, None, None
         gph = np.zeros(G, dtype=np.int32) if want_graph_phases else None
         logbuf = self._logbuf(log_cap)
         st = _lib.Stats()
@@ -258,7 +271,7 @@ class Context:
                                           cache_path.encode() if cache_path else None, ctypes.byref(t)),
               "lm_autotune_batch")
         return {"block_entries": t.block_entries, "grid_per_cu": t.grid_per_cu,
-                "phases_per_sync": t.phases_per_sync}
+                "phases_per_sync": t.phases_per_sync, "tail_entries": t.tail_entries}
 
 
 class Server:

@@ -33,12 +33,13 @@ LM_CHECK_GRAPH = 0x4
 LM_PROFILE = 0x8
 LM_GRAPH = 0x10
 LM_WEIGHT_SUM = 0x20
+LM_ASYNC = 0x40
 
 # bytes of the per-GPU scratch array of lm_match_noalloc
 LM_NOALLOC_SCRATCH_BYTES = 0x4000000
 
-LM_K_INIT, LM_K_ARGMAX, LM_K_MUTUAL, LM_K_COMPACT, LM_K_PLAN = range(5)
-KERNEL_KINDS = ("init", "argmax", "mutual", "compact", "plan")
+LM_K_INIT, LM_K_ARGMAX, LM_K_MUTUAL, LM_K_COMPACT, LM_K_PLAN, LM_K_TAIL = range(6)
+KERNEL_KINDS = ("init", "argmax", "mutual", "compact", "plan", "tail")
 
 LM_SERVE_BATCHED = 0
 LM_SERVE_FIFO = 1
@@ -64,13 +65,13 @@ class Stats(ctypes.Structure):
     _fields_ = [("phases", ctypes.c_int32), ("log_len", ctypes.c_int32), ("matched_edges", ctypes.c_int64),
                 ("device_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double),
                 ("log", ctypes.POINTER(PhaseRec)), ("log_cap", ctypes.c_int32),
-                ("profile_kinds", ctypes.c_uint32), ("k_launches", ctypes.c_int32 * 5), ("k_ms", ctypes.c_double * 5),
-                ("k_bytes", ctypes.c_double * 5), ("matched_weight", ctypes.c_double)]
+                ("profile_kinds", ctypes.c_uint32), ("k_launches", ctypes.c_int32 * 6), ("k_ms", ctypes.c_double * 6),
+                ("k_bytes", ctypes.c_double * 6), ("matched_weight", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block_entries", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
-                ("phases_per_sync", ctypes.c_int32)]
+                ("phases_per_sync", ctypes.c_int32), ("tail_entries", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):

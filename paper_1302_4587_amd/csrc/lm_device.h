@@ -67,6 +67,27 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
   return ((unsigned long long)hi << 32) | lo;
 }
 
+__device__ __forceinline__ Key dpp_key(const Key& x, int c) {
+  Key y;
+  y.w = dpp_u32(x.w, 0u, c);
+  y.hhi = dpp_u32(x.hhi, 0u, c);
+  y.hlo = dpp_u32(x.hlo, 0u, c);
+  y.u = (int)dpp_u32((unsigned)x.u, 0xffffffffu, c);
+  return y;
+}
+
+// Largest key of the wave, returned to every lane.
+__device__ __forceinline__ Key wave_max_key(Key k) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) k = key_max(dpp_key(k, c), k);
+  Key r;
+  r.w = (unsigned)__builtin_amdgcn_readlane((int)k.w, 63);
+  r.hhi = (unsigned)__builtin_amdgcn_readlane((int)k.hhi, 63);
+  r.hlo = (unsigned)__builtin_amdgcn_readlane((int)k.hlo, 63);
+  r.u = __builtin_amdgcn_readlane(k.u, 63);
+  return r;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_sum(T x);
 template <>

@@ -90,13 +90,16 @@ struct Totals {
   int last_nonempty;
   unsigned long long matched;
   int t;    // current phase (1-based): read by the mutual check, advanced by the plan kernel
-  int pad;
+  int tail_from;  // guarded phases: the live set R_t the tail kernel takes over (0 = none yet)
 };
 
 // What the host loop needs after each plan, written by the plan kernel into
 // mapped coherent pinned host memory: the record is stored, made visible to
-// the system, and only then marked ready (ready = gen), so the host polls the
+// the system, and only then tagged (tag = gen << 32 | t), so the host polls the
 // slot of R_t (t & (kMirrorSlots - 1)) with no event or copy on the stream.
+// The tag names both the solve and the live set: a record left in the slot by
+// the same solve kMirrorSlots phases earlier never passes for R_t. The tail
+// kernel leaves the solve's final record in the extra slot kMirrorSlots.
 struct PhaseMirror {
   long long L;                 // live entries of the live set just planned
   unsigned long long matched;  // matched entries so far (both directions)
@@ -105,9 +108,13 @@ struct PhaseMirror {
   unsigned gen;                // solve that wrote the record
   unsigned err;                // error flags so far
   int last_nonempty;           // last phase that had live rows
-  unsigned ready;              // gen once the record is complete
+  int pad;
+  unsigned long long tag;      // (gen << 32) | t once the record is complete
 };
 constexpr int kMirrorSlots = 64;
+__host__ __device__ inline unsigned long long mirror_tag(unsigned gen, int t) {
+  return ((unsigned long long)gen << 32) | (unsigned)t;
+}
 
 enum : unsigned {
   kErrRowPtr = 1u,
@@ -116,6 +123,7 @@ enum : unsigned {
   kErrSelfLoop = 8u,
   kErrWeight = 16u,
   kErrInternal = 32u,
+  kErrStall = 64u,  // a phase removed nothing: the input is not symmetric
 };
 
 // Inputs common to the phase kernels.
@@ -129,6 +137,8 @@ struct Common {
   const unsigned long long* gseed;  // premixed tie-break seed per graph
   int* gphase;                      // optional: last phase with a live row per graph
   int graphs;                       // 1: every piece belongs to graph 0 (no table lookups)
+  int guard;                        // phase kernels of a device-controlled solve: do nothing
+                                    // once the tail kernel has taken the live set over
 };
 
 // A live set as the kernels see it.
@@ -188,6 +198,8 @@ struct PlanArgs {
   int log_cap;
   PhaseMirror* mirror;  // optional (kPlanPrefix): record of the live set just planned
   unsigned gen;
+  long long tail_at;    // device-controlled solve: a planned live set of at most this many
+                        // entries is left to the tail kernel (totals->tail_from); 0: never
 };
 // kPlanLog writes the log record of the phase totals->t; kPlanTick then
 // advances totals->t (after the compaction of that phase).
@@ -224,6 +236,59 @@ struct InitArgs {
   BlockStat* bstat;
 };
 
+// Device-side tail of the phase loop (k_tail): one persistent launch runs
+// every phase from the current live set R_c on, with software grid barriers
+// between the mutual check and the compaction of each phase. Its live rows are
+// records {v, entry offset, live length, graph}. Workgroup b writes the rows it
+// keeps into a segment of its own of the next row list (rows of at most
+// kTailShort live entries from the segment's front, one lane each next phase;
+// longer ones from its back, one wave each), and its counts into a table that
+// every workgroup reads after the barrier: no counter is shared. A row keeps
+// its entry offset for the rest of the solve: phase t reads its entries from
+// one entry buffer and writes the survivors to the same offset of the other.
+constexpr int kTailBlock = 1024;
+constexpr int kTailMaxBlocks = 128;
+constexpr int kTailArrive = 16;  // barrier arrival counters (workgroup b uses b % kTailArrive)
+constexpr int kTailShort = 16;
+
+struct TailSeg {
+  int base, cap;             // the segment: rows [base, base + cap) of the row buffer
+  int ns, nl;                // short rows at [base, base + ns), long rows at [base + cap - nl, base + cap)
+  long long kept;            // live entries of those rows
+  long long md;              // entries of the rows this workgroup dropped as matched
+  unsigned long long mv;     // vertices this workgroup matched
+};
+
+struct TailCtl {
+  unsigned arrive[kTailArrive][32];  // one counter per 128-byte line
+  unsigned top[32];
+  unsigned gen[32];
+  unsigned abort[32];
+  TailSeg seg[2][kTailMaxBlocks];    // segment table of the list phase t writes: seg[t & 1]
+};
+
+struct TailArgs {
+  Common c;
+  TailCtl* tc;
+  // both live-set buffers of the phase kernels: R_c is set (c - 1) & 1
+  const Ctl* ctl[2];
+  const Run* runs[2];
+  const long long* epre[2];
+  const int* rpre[2];
+  int4* rows[2];       // R_c's piece records; afterwards the tail's row lists
+  int row_cap;         // records per row buffer
+  int* ecol[2];
+  float* ew[2];        // nullptr: unweighted
+  const long long* csr_rp;  // R_1 of one graph read from the input CSR, else nullptr
+  const int* in_col;        // the input entries (R_1's)
+  const float* in_w;
+  LogRec* log;
+  int log_cap;
+  PhaseMirror* final_rec;  // the solve's final record
+  unsigned gen;
+  unsigned long long spin_ticks;  // a barrier wait longer than this (device wall clock) aborts the solve
+};
+
 struct CheckArgs {
   Totals* totals;
   long long nnz;
@@ -235,7 +300,7 @@ struct CheckArgs {
   const long long* vtx_off;
 };
 
-hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s);
+hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s, TailCtl* tc = nullptr);
 hipError_t launch_fill_i32(int* p, long long n, int value, hipStream_t s);
 hipError_t launch_add_i64(long long* p, long long n, long long delta, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s);
@@ -251,6 +316,9 @@ hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, boo
 hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false, bool unweighted = false,
                           hipEvent_t* ev = nullptr);
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
+// grid must not exceed tail_blocks_per_cu() * CUs (every workgroup resident)
+hipError_t launch_tail(const TailArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
+int tail_blocks_per_cu();
 enum class StreamKind { kFirst, kCompact, kLateCompact };
 int max_blocks_per_cu_stream(StreamKind kind, bool unweighted = false);
 

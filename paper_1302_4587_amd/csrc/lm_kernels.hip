@@ -23,9 +23,10 @@
 namespace lm {
 
 // Reads the error word once per workgroup so that every lane takes the same
-// branch.
-__device__ __forceinline__ bool block_failed(Totals* t, unsigned* s) {
-  if (threadIdx.x == 0) *s = t->err;
+// branch. A guarded launch (device-controlled solve) also stops once the tail
+// kernel has taken the live set over.
+__device__ __forceinline__ bool block_failed(const Common& c, unsigned* s) {
+  if (threadIdx.x == 0) *s = c.totals->err | ((c.guard && c.totals->tail_from) ? 0x80000000u : 0u);
   __syncthreads();
   const bool f = *s != 0;
   __syncthreads();
@@ -34,16 +35,20 @@ __device__ __forceinline__ bool block_failed(Totals* t, unsigned* s) {
 
 // ---------------------------------------------------------------- small
 
-__global__ void k_zero(Ctl* ctl, int nctl, Totals* totals) {
+__global__ void k_zero(Ctl* ctl, int nctl, Totals* totals, TailCtl* tc) {
   int* p = reinterpret_cast<int*>(ctl);
   const int words = nctl * (int)(sizeof(Ctl) / 4);
   for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
+  if (tc) {
+    int* q = reinterpret_cast<int*>(tc);
+    for (int i = threadIdx.x; i < (int)(sizeof(TailCtl) / 4); i += blockDim.x) q[i] = 0;
+  }
   if (threadIdx.x == 0) {
     totals->err = 0;
     totals->last_nonempty = 0;
     totals->matched = 0;
     totals->t = 1;
-    totals->pad = 0;
+    totals->tail_from = 0;
   }
 }
 
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
   Totals tot;  // lane 0: the totals as the kernels before left them
   if (tid == 0) {
     tot = *a.c.totals;
-    s_err = tot.err;
+    s_err = tot.err | ((a.c.guard && tot.tail_from) ? 0x80000000u : 0u);
     s_extra = 0;
     s_red[0] = s_red[1] = s_red[2] = 0;
   }
@@ -383,13 +388,19 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
     m.gen = a.gen;
     m.err = tot.err;
     m.last_nonempty = tot.last_nonempty;
-    m.ready = 0u;
+    m.pad = 0;
+    m.tag = 0ull;
     PhaseMirror* slot = &a.mirror[m.t & (kMirrorSlots - 1)];
+    *(volatile unsigned long long*)&slot->tag = 0ull;  // the slot is being rewritten
+    __threadfence_system();
     *slot = m;
-    __threadfence_system();  // the record reaches host memory before it is marked ready
-    *(volatile unsigned*)&slot->ready = a.gen;
+    __threadfence_system();  // the record reaches host memory before it is tagged
+    *(volatile unsigned long long*)&slot->tag = mirror_tag(a.gen, m.t);
   }
   if ((a.mode & kPlanTick) && tid == 0) a.c.totals->t = tot.t + 1;
+  // a device-controlled solve leaves a small enough live set to the tail kernel
+  if (a.tail_at > 0 && (a.mode & kPlanPrefix) && tid == 0 && cn.L <= a.tail_at)
+    a.c.totals->tail_from = tot.t + ((a.mode & kPlanTick) ? 1 : 0);
 }
 
 // ---------------------------------------------------------------- run lookup
@@ -435,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
   __shared__ int s_lb[1];
   __shared__ unsigned s32[kWaves];
   __shared__ RunCache rc;
-  if (block_failed(a.c.totals, &s_err)) return;
+  if (block_failed(a.c, &s_err)) return;
   const Ctl ctl = *a.in.ctl;
   const int t = a.c.totals->t;
   // R_1 read from the CSR: piece k is vertex k, every vertex is its own head,
@@ -654,27 +665,6 @@ __device__ __forceinline__ Key full_key(unsigned w, int u, unsigned vloc, unsign
   k.hlo = (unsigned)h;
   k.u = u;
   return k;
-}
-
-__device__ __forceinline__ Key dpp_key(const Key& x, int c) {
-  Key y;
-  y.w = dpp_u32(x.w, 0u, c);
-  y.hhi = dpp_u32(x.hhi, 0u, c);
-  y.hlo = dpp_u32(x.hlo, 0u, c);
-  y.u = (int)dpp_u32((unsigned)x.u, 0xffffffffu, c);
-  return y;
-}
-
-// Largest key of the wave, returned to every lane.
-__device__ __forceinline__ Key wave_max_key(Key k) {
-#pragma unroll
-  for (int c = 0; c < 6; ++c) k = key_max(dpp_key(k, c), k);
-  Key r;
-  r.w = (unsigned)__builtin_amdgcn_readlane((int)k.w, 63);
-  r.hhi = (unsigned)__builtin_amdgcn_readlane((int)k.hhi, 63);
-  r.hlo = (unsigned)__builtin_amdgcn_readlane((int)k.hlo, 63);
-  r.u = __builtin_amdgcn_readlane(k.u, 63);
-  return r;
 }
 
 // Among the entries of one row piece whose ordered weight equals m (at
@@ -1439,7 +1429,7 @@ template <bool FIRST, int PPL, bool UNW, int VIEW>
 __global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL > 1 ? 3 : 5))) void k_stream(StreamArgs a) {
   __shared__ StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()> sm;
   __shared__ unsigned s_err;
-  if (block_failed(a.c.totals, &s_err)) return;
+  if (block_failed(a.c, &s_err)) return;
   Ctl ctl = *a.in.ctl;
   if (FIRST && ctl.Pf > 0) ctl.P = ctl.Pf;  // the first argmax's own split of R_1
   const unsigned long long seed0 = a.c.gseed[0];
@@ -1451,8 +1441,8 @@ __global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, s, ctl, nctl, totals);
+hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s, TailCtl* tc) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, s, ctl, nctl, totals, tc);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(int* p, long long n, int value, hipStream_t s) {

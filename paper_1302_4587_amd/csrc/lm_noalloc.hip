@@ -90,6 +90,10 @@ extern "C" lm_status lm_match_noalloc(lm_ctx* c, const lm_csr* g, uint64_t seed,
   }
   if (N == 0) return LM_OK;
   if (hipSetDevice(S.dev) != hipSuccess) return LM_EDEVICE;
+  if (S.async_pending) {  // a stream-ordered solve may still use the context's mapped records
+    if (hipEventSynchronize(S.e_async) != hipSuccess) return LM_EDEVICE;
+    S.async_pending = false;
+  }
   void* base = scratch_of(S.dev);
   if (!base) return LM_EDEVICE;
   Work wk;

@@ -53,6 +53,7 @@ struct Work {
   unsigned long long* gseed = nullptr;
   long long* vtxoff = nullptr;
   Totals* totals = nullptr;
+  TailCtl* tail = nullptr;
 };
 
 // Lays the working buffers of a solve of N vertices, nnz entries and G graphs
@@ -82,12 +83,16 @@ struct Solver {
   int bpc_first = 1;   // resident first-argmax workgroups per CU
   int bpc_late = 1;    // resident late-compaction workgroups per CU
   int bpc_stream_u = 1, bpc_first_u = 1, bpc_late_u = 1;  // the same for unweighted graphs
+  int bpc_tail = 1;              // resident tail workgroups per CU
+  unsigned long long clock_khz = 100000;  // constant wall clock of the device (barrier time-outs)
+  hipEvent_t e_async = nullptr;  // end of the last LM_ASYNC solve
+  bool async_pending = false;    // an LM_ASYNC solve may still be running on the context's buffers
   bool busy_server = false;
   int last_phases = 0;
 
   DevBuf C, state, rows[2], ecol[2], ew[2], runs[2], epre[2], rpre[2];
   DevBuf ctl, parts, bstat, mcount;
-  DevBuf gbase, gseed, vtxoff, gphase, totals;
+  DevBuf gbase, gseed, vtxoff, gphase, totals, tailc;
   DevBuf in_rp, in_col, in_w, out_mate;
   DevBuf wsum;  // kWeightSumMaxGrid partial sums, then the total
 

@@ -490,7 +490,7 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
   for (int sm : bes) {
     for (int gp = 1; gp <= std::max(1, sv.bpc_stream); ++gp) {
       for (int pp : {1, 2}) {  // phases queued past the checked live set
-        lm_tuning t{sm, gp, pp};
+        lm_tuning t{sm, gp, pp, saved.tail_entries};
         sv.tun = t;
         std::vector<double> ms;
         for (int rep = 0; rep < 3 && rs == LM_OK; ++rep) {

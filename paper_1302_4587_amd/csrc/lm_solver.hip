@@ -121,6 +121,7 @@ lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
   if (gbase.bytes + gseed.bytes + vtxoff.bytes != tb0) t_dev[0] = t_dev[1] = t_dev[2] = nullptr;  // reallocated
   if (want_gphase) RES(gphase, (size_t)G * 4);
   RES(totals, sizeof(Totals));
+  RES(tailc, sizeof(TailCtl));
 #undef RES
   return LM_OK;
 }
@@ -145,6 +146,7 @@ Work Solver::pool_work() const {
   w.gseed = (unsigned long long*)gseed.p;
   w.vtxoff = (long long*)vtxoff.p;
   w.totals = (Totals*)totals.p;
+  w.tail = (TailCtl*)tailc.p;
   return w;
 }
 
@@ -174,6 +176,7 @@ size_t carve_work(int64_t N, int64_t nnz, int64_t G, void* base, Work* w) {
   x.gseed = (unsigned long long*)take((size_t)G * 8);
   x.vtxoff = (long long*)take((size_t)(G + 1) * 8);
   x.totals = (Totals*)take(sizeof(Totals));
+  x.tail = (TailCtl*)take(sizeof(TailCtl));
   if (w) *w = x;
   return off;
 }
@@ -196,10 +199,15 @@ lm_status Solver::init_device(int device, size_t budget) {
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreateWithFlags(&e_order, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
   if (hipEventCreateWithFlags(&e_tables, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
+  if (hipEventCreateWithFlags(&e_async, hipEventDisableTiming) != hipSuccess) return LM_EDEVICE;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    clock_khz = (unsigned long long)khz;
   const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
-  if (hipHostMalloc((void**)&h_mir, sizeof(PhaseMirror) * kMirrorSlots, mapped) != hipSuccess) return LM_EDEVICE;
+  // one slot per live set of the ring, plus the tail kernel's final record
+  if (hipHostMalloc((void**)&h_mir, sizeof(PhaseMirror) * (kMirrorSlots + 1), mapped) != hipSuccess) return LM_EDEVICE;
   if (hipHostMalloc((void**)&h_log, sizeof(LogRec) * (size_t)kLogCap, mapped) != hipSuccess) return LM_EDEVICE;
-  std::memset(h_mir, 0, sizeof(PhaseMirror) * kMirrorSlots);
+  std::memset(h_mir, 0, sizeof(PhaseMirror) * (kMirrorSlots + 1));
   if (hipHostGetDevicePointer((void**)&d_mir, h_mir, 0) != hipSuccess) return LM_EDEVICE;
   if (hipHostGetDevicePointer((void**)&d_log, h_log, 0) != hipSuccess) return LM_EDEVICE;
   if (noalloc_setup(device) != LM_OK) return LM_EDEVICE;
@@ -209,19 +217,23 @@ lm_status Solver::init_device(int device, size_t budget) {
   bpc_stream_u = max_blocks_per_cu_stream(StreamKind::kCompact, true);
   bpc_first_u = max_blocks_per_cu_stream(StreamKind::kFirst, true);
   bpc_late_u = max_blocks_per_cu_stream(StreamKind::kLateCompact, true);
+  bpc_tail = tail_blocks_per_cu();
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = 16;  // at most: the resident count of each kernel caps it
   tun.phases_per_sync = 1;  // phases queued past the live set the host checks
+  tun.tail_entries = 1 << 20;  // live sets handed to the tail kernel (measured on RGG and R-MAT)
   return LM_OK;
 }
 
 void Solver::shutdown() {
   if (dev >= 0) (void)hipSetDevice(dev);
   if (own) (void)hipStreamSynchronize(own);
+  if (e_async && async_pending) (void)hipEventSynchronize(e_async);
+  async_pending = false;
   DevBuf* all[] = {&C,       &state,   &rows[0], &rows[1], &ecol[0], &ecol[1], &ew[0],   &ew[1],
                    &runs[0], &runs[1], &epre[0], &epre[1], &rpre[0], &rpre[1], &ctl,     &parts,
                    &bstat,   &mcount,  &gbase,   &gseed,   &vtxoff,  &gphase,  &totals,  &in_rp,
-                   &in_col,  &in_w,    &out_mate, &wsum};
+                   &in_col,  &in_w,    &out_mate, &wsum,   &tailc};
   for (DevBuf* b : all) pool.release(*b);
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   evpool.clear();
@@ -231,6 +243,8 @@ void Solver::shutdown() {
   e_order = nullptr;
   if (e_tables) (void)hipEventDestroy(e_tables);
   e_tables = nullptr;
+  if (e_async) (void)hipEventDestroy(e_async);
+  e_async = nullptr;
   if (h_totals) (void)hipHostFree(h_totals);
   if (h_mir) (void)hipHostFree(h_mir);
   if (t_pinned) (void)hipHostFree(t_pinned);
@@ -317,6 +331,15 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
   c.gseed = wk.gseed;
   c.gphase = p.gphase;
   c.graphs = (int)p.G;
+  c.guard = 0;
+  // A device-controlled solve (LM_GRAPH, LM_ASYNC) enqueues a fixed number of
+  // guarded phases and then the tail kernel; the plan that produces a live set
+  // of at most tail_at entries hands it to the tail, and the guarded phases
+  // after it do nothing. A host-polled solve hands over from its loop.
+  // (a stream-ordered solve is not captured: its graph would have to outlive the call)
+  const bool use_graph = (flags & LM_GRAPH) != 0 && !prof && !(flags & LM_ASYNC);
+  const bool dev_ctl = use_graph || (flags & LM_ASYNC) != 0;
+  const long long tail_at = tun.tail_entries > 0 ? tun.tail_entries : (1ll << 20);
 
   auto live = [&](int t) {  // live set R_t
     const int i = (t - 1) & 1;
@@ -345,6 +368,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     a.mirror = d_mir;
     a.gen = gen;
     a.mcount = wk.mcount;
+    a.tail_at = dev_ctl ? tail_at : 0;
     return a;
   };
 
@@ -358,7 +382,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
   } while (0)
   // live set R_1 from the input and the first argmax over it
   auto enqueue_prologue = [&]() -> hipError_t {
-    ENQ(launch_zero(dctl, 2, dtot, s));
+    ENQ(launch_zero(dctl, 2, dtot, s, wk.tail));
     if (p.gphase) ENQ(launch_fill_i32(p.gphase, p.G, 0, s));
     if (flags & LM_CHECK_GRAPH) {
       CheckArgs ca{dtot, p.nnz, p.row_ptr, p.col, p.w, (int)p.N, (int)p.G, p.vtx_off};
@@ -456,14 +480,43 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     ++t;
     return hipSuccess;
   };
+  // every remaining phase, from the live set the device phase counter names
+  // at most half the resident capacity, so that two solves' tails on other
+  // streams are resident together
+  const int tail_cap = std::max(1, std::min(kTailMaxBlocks, num_cus * std::max(1, bpc_tail) / 2));
+  auto enqueue_tail = [&](long long L_hint) -> hipError_t {
+    TailArgs ta;
+    std::memset(&ta, 0, sizeof(ta));
+    ta.c = c;
+    ta.c.guard = 0;
+    ta.tc = wk.tail;
+    for (int i = 0; i < 2; ++i) {
+      ta.ctl[i] = dctl + i;
+      ta.runs[i] = wk.runs[i];
+      ta.epre[i] = wk.epre[i];
+      ta.rpre[i] = wk.rpre[i];
+      ta.rows[i] = wk.rows[i];
+      ta.ecol[i] = wk.ecol[i];
+      ta.ew[i] = unweighted ? nullptr : wk.ew[i];
+    }
+    ta.row_cap = (int)(p.N + 2 * kMaxBlocks + 16);
+    ta.csr_rp = csr1 ? p.row_ptr : nullptr;
+    ta.in_col = p.col;
+    ta.in_w = p.w;
+    ta.log = d_log;
+    ta.log_cap = kLogCap;
+    ta.final_rec = d_mir + kMirrorSlots;
+    ta.gen = gen;
+    ta.spin_ticks = clock_khz * 2000ull;  // 2 s
+    // workgroups (1024 lanes each): about one per 16384 live entries
+    const long long want = L_hint < 0 ? tail_cap : (L_hint + 16383) / 16384;
+    const int grid = (int)std::max<long long>(1, std::min<long long>(tail_cap, want));
+    ENQ(launch_tail(ta, grid, s, timing(LM_K_TAIL)));
+    return hipSuccess;
+  };
 #undef ENQ
 
   HIPCHK(hipEventRecord(e0, s));
-  // With LM_GRAPH the prologue and the first kGraphPhases phases are one
-  // captured HIP graph: one launch, no host round trip in between. Phases
-  // after the live set emptied are no-ops (every kernel reads the live-set
-  // size from the device), so overshooting is harmless.
-  const bool use_graph = (flags & LM_GRAPH) != 0 && !prof;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   struct GraphGuard {
@@ -475,42 +528,77 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     }
   } guard{graph, gexec};
   constexpr int kRing = kMirrorSlots - 1;
+  bool tail_queued = false;
+  if (dev_ctl) {
+    // Guarded phases until the live set is expected below tail_at (it shrinks
+    // to about a third or less per phase), then the tail kernel, which runs
+    // whatever is left. With LM_GRAPH the whole solve is one captured graph.
+    int K = 0;
+    for (double x = (double)p.nnz; x > (double)tail_at && K < 24; x /= 3.0) ++K;
+    if (K > 0) ++K;  // one phase of margin: guarded phases after the hand-over do nothing
+    auto enqueue_all = [&]() -> hipError_t {
+      hipError_t e = enqueue_prologue();
+      c.guard = 1;
+      for (int j = 0; j < K && e == hipSuccess; ++j) e = enqueue_phase();
+      c.guard = 0;
+      if (e == hipSuccess) e = enqueue_tail(-1);
+      return e;
+    };
+    if (use_graph) {
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const hipError_t ce = enqueue_all();
+      const hipError_t ee = hipStreamEndCapture(s, &graph);
+      HIPCHK(ce);
+      HIPCHK(ee);
+      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      HIPCHK(hipGraphLaunch(gexec, s));
+    } else {
+      HIPCHK(enqueue_all());
+    }
+    tail_queued = true;
+    if (flags & LM_ASYNC) {
+      HIPCHK(hipEventRecord(e_async, s));
+      async_pending = true;
+      return LM_OK;
+    }
+  } else {
+    HIPCHK(enqueue_prologue());
+    if (tun.tail_entries > 0 && p.nnz <= tun.tail_entries) {  // R_1 is already small
+      HIPCHK(enqueue_tail(p.nnz));
+      tail_queued = true;
+    }
+  }
   // rc: the live set R_rc the host checks next; the plan that produced it
   // leaves its record in h_mir[rc & kRing].
   int rc = 1;
-  if (use_graph) {
-    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = enqueue_prologue();
-    for (int j = 0; j < kGraphPhases && ce == hipSuccess; ++j) ce = enqueue_phase();
-    const hipError_t ee = hipStreamEndCapture(s, &graph);
-    HIPCHK(ce);
-    HIPCHK(ee);
-    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-    HIPCHK(hipGraphLaunch(gexec, s));
-    rc = t;  // the graph's last plan produced R_t
-  } else {
-    HIPCHK(enqueue_prologue());
-  }
   // Phase loop: phases rc .. rc + ahead - 1 stay queued while the host polls
   // the record of R_rc, so the device never idles on the host; the phases
   // queued past the empty live set are no-ops. No event is recorded between
   // phases: each one would put a bubble of a few microseconds on the stream.
+  // Once R_rc is small the phases already queued run and the tail kernel
+  // takes the rest.
   const int ahead = std::max(1, std::min(tun.phases_per_sync, kMirrorSlots / 2));
+  const long long host_tail = tun.tail_entries > 0 ? 4ll * tun.tail_entries : -1;
+  // Reads a record tagged for this solve and live set `idx` (idx < 0: the tail
+  // kernel's final record, any live set). The tag is read before and after the
+  // copy, so a record being rewritten is never taken.
+  auto take_record = [&](const volatile PhaseMirror* slot, int idx, PhaseMirror& m) -> bool {
+    const unsigned long long t0 = slot->tag;
+    if ((unsigned)(t0 >> 32) != gen || (idx >= 0 && t0 != mirror_tag(gen, idx))) return false;
+    std::atomic_thread_fence(std::memory_order_acquire);
+    std::memcpy(&m, (const void*)slot, sizeof(m));
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return slot->tag == t0 && m.tag == t0;
+  };
   // 1: record of R_idx read; 0: the stream drained without it (an error flag
   // stopped the plan); -1: the stream failed
   auto wait_record = [&](int idx, PhaseMirror& m) -> int {
     const volatile PhaseMirror* slot = &h_mir[idx & kRing];
-    auto take = [&]() -> bool {
-      if (slot->ready != gen) return false;
-      std::atomic_thread_fence(std::memory_order_acquire);
-      std::memcpy(&m, (const void*)slot, sizeof(m));
-      return m.t == idx;
-    };
     for (unsigned spin = 1;; ++spin) {
-      if (take()) return 1;
+      if (take_record(slot, idx, m)) return 1;
       if ((spin & 255u) == 0u) {
         const hipError_t q = hipStreamQuery(s);
-        if (q == hipSuccess) return take() ? 1 : 0;
+        if (q == hipSuccess) return take_record(slot, idx, m) ? 1 : 0;
         if (q != hipErrorNotReady) return -1;
       }
     }
@@ -518,7 +606,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
   int64_t last_live = -1;
   bool stalled = false, no_record = false;
   PhaseMirror fin{};
-  for (;;) {
+  while (!tail_queued) {
     while (t < rc + ahead) HIPCHK(enqueue_phase());  // phase t - 1 queued: its plan produces R_t
     PhaseMirror m;
     const int got = wait_record(rc, m);
@@ -538,10 +626,25 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     last_live = m.L;
     est_L = m.L;
     est_V = m.pieces;
+    if (m.L <= host_tail) {
+      HIPCHK(enqueue_tail(m.L));
+      tail_queued = true;
+      break;
+    }
     ++rc;
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
+  int tail_from = 0;  // the live set the tail kernel started from (0: no tail)
+  if (tail_queued && !no_record && !stalled) {
+    PhaseMirror m;
+    if (take_record(&h_mir[kMirrorSlots], -1, m)) {
+      fin = m;
+      tail_from = m.pad;
+    } else {
+      no_record = true;  // the tail stopped on an error flag before its record
+    }
+  }
   Totals tot{};
   if (no_record) {
     HIPCHK(hipMemcpy(h_totals, dtot, sizeof(Totals), hipMemcpyDeviceToHost));
@@ -554,7 +657,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
   const unsigned err = tot.err;
   if (err) {
     if (err & kErrWeight) return LM_EWEIGHT;
-    if (err & (kErrRowPtr | kErrColRange | kErrSelfLoop)) return LM_EGRAPH;
+    if (err & (kErrRowPtr | kErrColRange | kErrSelfLoop | kErrStall)) return LM_EGRAPH;
     if (err & kErrDegree) return LM_ETOOBIG;
     return LM_EDEVICE;
   }
@@ -601,11 +704,24 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     st->k_bytes[LM_K_INIT] = 8.0 * (N + 1.0) + (csr1 ? 9.0 * N : 5.0 * N + 16.0 * V1);
     const double eb = unweighted ? 4.0 : 8.0;  // bytes of one entry: col (+ w)
     st->k_bytes[LM_K_ARGMAX] = (csr1 ? 8.0 * (N + 1.0) : 16.0 * V1) + eb * L1 + 4.0 * V1;
+    // Phases from tail_from on ran in the tail kernel: per phase a 16-byte row
+    // record read twice (mutual check, compaction), C[v] and the C[C[v]]
+    // gather, 5 bytes per matched vertex, the live entries of unmatched rows
+    // with their neighbour's state, the survivors, and a 16-byte record plus
+    // C[v] per next live row; starting from R_c with c >= 2 it first copies
+    // the L_c entries to their virtual positions (a read and a write each) and
+    // reads R_c's piece records.
     for (int i = 0; i < nrec; ++i) {
       const double L = (double)recs(i).live_entries, V = (double)recs(i).live_rows;
       const double mv = 2.0 * (double)recs(i).matched_edges, md = (double)recs(i).matched_entries;
       const double L2 = (double)recs(i + 1).live_entries, V2 = (double)recs(i + 1).live_rows;
       const bool from_csr = csr1 && i == 0;
+      if (tail_from > 0 && i + 1 >= tail_from) {
+        double b = 24.0 * V + 5.0 * mv + 16.0 * V + (eb + 1.0) * (L - md) + eb * L2 + 20.0 * V2;
+        if (i + 1 == tail_from) b += (tail_from >= 2 ? 2.0 * eb * L : 0.0) + (from_csr ? 16.0 * N : 32.0 * V);
+        st->k_bytes[LM_K_TAIL] += b;
+        continue;
+      }
       st->k_bytes[LM_K_MUTUAL] += from_csr ? 4.0 * N + 4.0 * V + 5.0 * mv : 24.0 * V + 9.0 * mv;
       st->k_bytes[LM_K_COMPACT] += (from_csr ? 9.0 * N : 16.0 * V) + (eb + 1.0) * (L - md) + eb * L2 + 20.0 * V2;
     }
@@ -705,6 +821,7 @@ lm_status lm_set_tuning(lm_ctx* c, const lm_tuning* t) {
   if (t->block_entries < 2048 || t->block_entries > (1 << 22)) return LM_EINVAL;
   if (t->grid_per_cu < 1 || t->grid_per_cu > 16) return LM_EINVAL;
   if (t->phases_per_sync < 1 || t->phases_per_sync > 64) return LM_EINVAL;
+  if (t->tail_entries < 0 || t->tail_entries > (1 << 30)) return LM_EINVAL;
   c->s.tun = *t;
   return LM_OK;
 }
@@ -714,14 +831,25 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
                               const int64_t* row_ptr, const int32_t* col, const float* w, const uint64_t* seeds,
                               uint64_t seed0, int32_t* mate, uint32_t flags, void* stream, lm_stats* st,
                               int32_t* graph_phases) {
-  const uint32_t known = LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE | LM_GRAPH | LM_WEIGHT_SUM;
+  const uint32_t known =
+      LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE | LM_GRAPH | LM_WEIGHT_SUM | LM_ASYNC;
   if (flags & ~known) return LM_EINVAL;
+  if (flags & LM_ASYNC) {  // stream-ordered: device buffers only, nothing to report back
+    if ((flags & (LM_IN_DEVICE | LM_OUT_DEVICE)) != (LM_IN_DEVICE | LM_OUT_DEVICE)) return LM_EINVAL;
+    if (flags & (LM_CHECK_GRAPH | LM_PROFILE | LM_WEIGHT_SUM)) return LM_EINVAL;
+    if (st || graph_phases) return LM_EINVAL;
+  }
   if (N < 0 || nnz < 0 || G < 1) return LM_EINVAL;
   if (N >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 31) - 65536) return LM_ETOOBIG;
   if (N > 0 && (!row_ptr || !mate)) return LM_EINVAL;
   if (nnz > 0 && !col) return LM_EINVAL;  // w == nullptr: unweighted graph
   Solver& S = c->s;
   if (hipSetDevice(S.dev) != hipSuccess) return LM_EDEVICE;
+  // the context's buffers belong to a pending stream-ordered solve until it ends
+  if (S.async_pending) {
+    if (hipEventSynchronize(S.e_async) != hipSuccess) return LM_EDEVICE;
+    S.async_pending = false;
+  }
   // The caller named the legacy default stream (or none): the solve runs on it,
   // after everything already queued there (for example the kernels that
   // produced device inputs). A captured graph needs a stream of its own, which
@@ -847,6 +975,7 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   lm_stats* sp = st ? st : &local;
   rs = S.run(p, S.pool_work(), s, flags, sp);
   if (rs != LM_OK) return rs;
+  if (flags & LM_ASYNC) return LM_OK;  // enqueued; the result lands in order on the stream
   double wsum = 0.0;
   const bool want_w = st && (flags & LM_WEIGHT_SUM);
   if (want_w) {  // after the solve's timed region

@@ -295,19 +295,33 @@ def test_budget_too_small(torch_dev):
 
 def test_profile_stats(ctx, torch_dev):
     g = lmgen.rgg(100000, 10.0, seed=3)
-    mate, st = _solve(ctx, torch_dev, g, 1, profile=True)
-    _assert_parity(g, 1, mate, st, "profile")
-    assert st.kernel_launches["init"] == 1 and st.kernel_launches["argmax"] == 1
-    assert st.kernel_launches["mutual"] >= st.phases and st.kernel_launches["compact"] >= st.phases
-    assert all(st.kernel_ms[k] > 0 for k in ("init", "argmax", "mutual", "compact"))
-    assert st.bytes_alg > 8 * g.nnz
+    saved = ctx.tuning()
+    try:
+        # every phase through the phase kernels (no hand-over to the tail kernel)
+        ctx.set_tuning(tail_entries=0)
+        mate, st = _solve(ctx, torch_dev, g, 1, profile=True)
+        _assert_parity(g, 1, mate, st, "profile")
+        assert st.kernel_launches["init"] == 1 and st.kernel_launches["argmax"] == 1
+        assert st.kernel_launches["mutual"] >= st.phases and st.kernel_launches["compact"] >= st.phases
+        assert st.kernel_launches["tail"] == 0
+        assert all(st.kernel_ms[k] > 0 for k in ("init", "argmax", "mutual", "compact"))
+        assert st.bytes_alg > 8 * g.nnz
+        # the graph is below the hand-over size: one tail launch runs every phase
+        ctx.set_tuning(tail_entries=1 << 20)
+        mate, st = _solve(ctx, torch_dev, g, 1, profile=True)
+        _assert_parity(g, 1, mate, st, "profile with tail")
+        assert st.kernel_launches["tail"] == 1 and st.kernel_ms["tail"] > 0
+        assert st.kernel_launches["mutual"] == 0 and st.kernel_launches["compact"] == 0
+        assert st.kernel_bytes["tail"] > 8 * g.nnz
+    finally:
+        ctx.set_tuning(**saved)
 
 
 def test_hip_graph_mode_matches_eager(ctx, torch_dev):
-    """LM_GRAPH captures the set-up and the first phases into one HIP graph per
-    call; the remaining phases (if any) run eagerly. Several graph solves in a
-    row, with eager solves and host syncs in between, must each equal the
-    eager result and the oracle."""
+    """LM_GRAPH captures the whole solve into one HIP graph per call: set-up,
+    guarded phases and the tail kernel, which runs whatever the guarded phases
+    leave. Several graph solves in a row, with eager solves and host syncs in
+    between, must each equal the eager result and the oracle."""
     import torch
     cases = [
         ("er 4096", lmgen.er(4096, 32768, seed=1)),
