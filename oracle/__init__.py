@@ -61,6 +61,14 @@ def _load():
         lib.lmo_local_max_batch.argtypes = [ctypes.c_int64, _P64, _P64, _P32, _PF, _PU64, ctypes.c_uint64,
                                             _P32, _P64]
         lib.lmo_local_max_batch.restype = ctypes.c_int64
+        lib.lmo_local_max_ex.argtypes = [ctypes.c_int64, _P64, _P32, _PF, ctypes.c_uint64, ctypes.c_int, _P32,
+                                         _P64, ctypes.c_int64]
+        lib.lmo_local_max_ex.restype = ctypes.c_int64
+        lib.lmo_local_max_batch_ex.argtypes = [ctypes.c_int64, _P64, _P64, _P32, _PF, _PU64, ctypes.c_uint64,
+                                               ctypes.c_int, _P32, _P64]
+        lib.lmo_local_max_batch_ex.restype = ctypes.c_int64
+        lib.lmo_edge_hash_phase.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+        lib.lmo_edge_hash_phase.restype = ctypes.c_uint64
         lib.lmo_greedy_certificate.argtypes = [ctypes.c_int64, _P64, _P32, _PF, ctypes.c_uint64, _P32]
         lib.lmo_greedy_certificate.restype = ctypes.c_int64
         _lib = lib
@@ -84,26 +92,33 @@ def edge_hash(seed: int, lo: int, hi: int) -> int:
     return int(_load().lmo_edge_hash(seed & (2**64 - 1), lo, hi))
 
 
-def local_max(n, row_ptr, col, w, seed: int = 1, log_cap: int = 1 << 16):
+def edge_hash_phase(seed: int, t: int, lo: int, hi: int) -> int:
+    """Renewed tie-break value of {lo, hi} in iteration t."""
+    return int(_load().lmo_edge_hash_phase(seed & (2**64 - 1), t, lo, hi))
+
+
+def local_max(n, row_ptr, col, w, seed: int = 1, log_cap: int = 1 << 16, renew: bool = False):
     """Returns (mate int32[n], log int64[phases, 3]) where log rows hold
-    (|E_t|, V_t, edges matched in iteration t)."""
+    (|E_t|, V_t, edges matched in iteration t). renew=True draws the
+    tie-break keys anew in every iteration (see lm_oracle.c)."""
     rp = _c(row_ptr, np.int64)
     cc = _c(col, np.int32)
     ww = _c(w, np.float32)
     mate = np.empty(max(n, 1), dtype=np.int32)[:n]
     log = np.zeros((log_cap, 3), dtype=np.int64)
-    t = _load().lmo_local_max(n, rp.ctypes.data_as(_P64), cc.ctypes.data_as(_P32), ww.ctypes.data_as(_PF),
-                              seed & (2**64 - 1), mate.ctypes.data_as(_P32), log.ctypes.data_as(_P64), log_cap)
+    t = _load().lmo_local_max_ex(n, rp.ctypes.data_as(_P64), cc.ctypes.data_as(_P32), ww.ctypes.data_as(_PF),
+                                 seed & (2**64 - 1), 1 if renew else 0, mate.ctypes.data_as(_P32),
+                                 log.ctypes.data_as(_P64), log_cap)
     if t < 0:
         raise ValueError(f"oracle rejected the graph (code {t})")
     return mate, log[: min(int(t), log_cap)].copy()
 
 
-def local_max_graph(g, seed: int = 1):
-    return local_max(g.n, g.row_ptr, g.col, g.w, seed)
+def local_max_graph(g, seed: int = 1, renew: bool = False):
+    return local_max(g.n, g.row_ptr, g.col, g.w, seed, renew=renew)
 
 
-def local_max_batch(vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1):
+def local_max_batch(vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1, renew: bool = False):
     """Solves every graph of a batch alone. Returns (mate local ids, phases[G])."""
     vo = _c(vtx_off, np.int64)
     rp = _c(row_ptr, np.int64)
@@ -117,9 +132,9 @@ def local_max_batch(vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1):
     if seeds is not None:
         sa = _c(np.asarray(seeds, dtype=np.uint64), np.uint64)
         sp = sa.ctypes.data_as(_PU64)
-    t = _load().lmo_local_max_batch(G, vo.ctypes.data_as(_P64), rp.ctypes.data_as(_P64), cc.ctypes.data_as(_P32),
-                                    ww.ctypes.data_as(_PF), sp, seed0 & (2**64 - 1), mate.ctypes.data_as(_P32),
-                                    ph.ctypes.data_as(_P64))
+    t = _load().lmo_local_max_batch_ex(G, vo.ctypes.data_as(_P64), rp.ctypes.data_as(_P64),
+                                       cc.ctypes.data_as(_P32), ww.ctypes.data_as(_PF), sp, seed0 & (2**64 - 1),
+                                       1 if renew else 0, mate.ctypes.data_as(_P32), ph.ctypes.data_as(_P64))
     if t < 0:
         raise ValueError(f"oracle rejected the batch (code {t})")
     return mate, ph

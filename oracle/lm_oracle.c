@@ -30,6 +30,15 @@
  * 2014). mix and XOR with a constant are bijections, so distinct edges get
  * distinct H and the order on edges is strict.
  *
+ * Renewed keys (lmo_local_max_ex with renew = 1; the paper's Lemma 1 draws
+ * fresh random noise in every iteration, its footnote and Section 2.1 step 1):
+ * iteration t compares (w(e), H_t(e)) with
+ *     S_t     = mix(S + t * GAMMA)        (the t-th output of a SplitMix64
+ *                                           stream started at S)
+ *     H_t(e)  = mix(((uint64)lo << 32 | hi) XOR S_t)
+ * so the order of tied edges is drawn anew each iteration. With distinct
+ * weights the hash never decides and both modes give the same matching.
+ *
  * Parity pins (checked by tests, not by this file): SplitMix64 published
  * output vectors pin mix; a sorted greedy scan under the same key, validity,
  * maximality, brute-force maximum weight matching (1/2 bound), closed forms
@@ -109,6 +118,13 @@ static int64_t edges_from_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
   return m;
 }
 
+/* Tie-break value of {lo, hi} in iteration t under renewed keys. */
+uint64_t lmo_edge_hash_phase(uint64_t seed, int64_t t, int32_t lo, int32_t hi) {
+  uint64_t pair = ((uint64_t)(uint32_t)lo << 32) | (uint64_t)(uint32_t)hi;
+  uint64_t st = lmo_mix64(lmo_seed_mix(seed) + (uint64_t)t * LMO_GAMMA);
+  return lmo_mix64(pair ^ st);
+}
+
 /*
  * Local-max matching of one graph given as symmetric CSR.
  *   mate[n]: output, partner id or -1.
@@ -118,8 +134,8 @@ static int64_t edges_from_csr(int64_t n, const int64_t* row_ptr, const int32_t* 
  * Returns the number of iterations (0 for an edgeless graph) or a negative
  * error code. Iterations beyond log_cap are still run, not logged.
  */
-int64_t lmo_local_max(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, uint64_t seed,
-                      int32_t* mate, int64_t* log, int64_t log_cap) {
+int64_t lmo_local_max_ex(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, uint64_t seed,
+                         int renew, int32_t* mate, int64_t* log, int64_t log_cap) {
   lmo_edge* E = NULL;
   int64_t m = edges_from_csr(n, row_ptr, col, w, seed, &E);
   if (m < 0) return m;
@@ -139,6 +155,8 @@ int64_t lmo_local_max(int64_t n, const int64_t* row_ptr, const int32_t* col, con
   int64_t t = 0;
   while (m > 0) {
     ++t;
+    if (renew) /* the keys of this iteration */
+      for (int64_t j = 0; j < m; ++j) E[j].h = lmo_edge_hash_phase(seed, t, E[j].lo, E[j].hi);
     int64_t vt = 0;
     for (int64_t j = 0; j < m; ++j) {
       if (seen[E[j].lo] != t) {
@@ -188,6 +206,12 @@ int64_t lmo_local_max(int64_t n, const int64_t* row_ptr, const int32_t* col, con
   return t;
 }
 
+/* Local max with keys fixed for the whole run. */
+int64_t lmo_local_max(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, uint64_t seed,
+                      int32_t* mate, int64_t* log, int64_t log_cap) {
+  return lmo_local_max_ex(n, row_ptr, col, w, seed, 0, mate, log, log_cap);
+}
+
 /*
  * Batch form: graphs g = 0..G-1 are solved one after another, each alone with
  * its own seed (seeds[g], or seed0 for all when seeds is NULL). Inputs as in
@@ -195,8 +219,9 @@ int64_t lmo_local_max(int64_t n, const int64_t* row_ptr, const int32_t* col, con
  * col holding local ids. mate receives local ids. phases[g] (optional) gets
  * each graph's iteration count. Returns the largest count or an error.
  */
-int64_t lmo_local_max_batch(int64_t G, const int64_t* vtx_off, const int64_t* row_ptr, const int32_t* col,
-                            const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate, int64_t* phases) {
+int64_t lmo_local_max_batch_ex(int64_t G, const int64_t* vtx_off, const int64_t* row_ptr, const int32_t* col,
+                               const float* w, const uint64_t* seeds, uint64_t seed0, int renew, int32_t* mate,
+                               int64_t* phases) {
   int64_t worst = 0;
   for (int64_t g = 0; g < G; ++g) {
     int64_t a = vtx_off[g], b = vtx_off[g + 1];
@@ -205,13 +230,18 @@ int64_t lmo_local_max_batch(int64_t G, const int64_t* vtx_off, const int64_t* ro
     int64_t* rp = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
     if (!rp) return LMO_ENOMEM;
     for (int64_t v = 0; v <= n; ++v) rp[v] = row_ptr[a + v] - e0;
-    int64_t t = lmo_local_max(n, rp, col + e0, w + e0, seeds ? seeds[g] : seed0, mate + a, NULL, 0);
+    int64_t t = lmo_local_max_ex(n, rp, col + e0, w + e0, seeds ? seeds[g] : seed0, renew, mate + a, NULL, 0);
     free(rp);
     if (t < 0) return t;
     if (phases) phases[g] = t;
     if (t > worst) worst = t;
   }
   return worst;
+}
+
+int64_t lmo_local_max_batch(int64_t G, const int64_t* vtx_off, const int64_t* row_ptr, const int32_t* col,
+                            const float* w, const uint64_t* seeds, uint64_t seed0, int32_t* mate, int64_t* phases) {
+  return lmo_local_max_batch_ex(G, vtx_off, row_ptr, col, w, seeds, seed0, 0, mate, phases);
 }
 
 /*
