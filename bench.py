@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 KERNEL_SOURCES = ["paper_1302_4587_amd/csrc/lm_kernels.hip", "paper_1302_4587_amd/csrc/lm_device.h",
                   "paper_1302_4587_amd/csrc/lm_key.h", "paper_1302_4587_amd/csrc/lm_internal.h",
-                  "paper_1302_4587_amd/csrc/lm_tail.hip"]
+                  "paper_1302_4587_amd/csrc/lm_tail.hip", "paper_1302_4587_amd/csrc/lm_first.hip"]
 
 
 def _kernel_sha():
@@ -174,6 +174,27 @@ def run_single(ctx, g, w_t, rp, col, args, name, unweighted):
                 "library_model_bytes_per_launch": round(lib_per_launch, 1),
                 "library_model_frac": round(lib_per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
                 "kernel_ms_untimed_solve": breakdown}
+    renew = None
+    if not args.no_renew:
+        # the same graph with keys renewed every phase (LM_RENEW_KEYS): the
+        # phase count against the fixed keys' (the paper's open question of
+        # its Section 4); a few solves, outside the timed steps
+        rl = []
+        sr = None
+        for _ in range(4):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            _, sr = ctx.match(rp, col, w_t, seed=args.seed, mate=mate, renew_keys=True)
+            rl.append((time.perf_counter() - ts) * 1e3)
+        got_r = mate.cpu().numpy()
+        chk_f = _matching_check(g, got)
+        chk_r = _matching_check(g, got_r)
+        renew = {"phases_fixed": st.phases, "phases_renewed": sr.phases,
+                 "ms_per_solve_renewed": round(float(np.median(rl[1:])), 4),
+                 "live_entries_per_phase_renewed": [int(r[0]) for r in sr.log],
+                 "matched_edges_fixed": chk_f["edges"], "matched_edges_renewed": chk_r["edges"],
+                 "matched_weight_fixed": chk_f["weight"], "matched_weight_renewed": chk_r["weight"],
+                 "renewed_valid_maximal": chk_r["valid_maximal"]}
     import oracle  # test infrastructure: certificate and CPU baseline only
 
     cert = oracle.greedy_certificate(g.n, g.row_ptr, g.col, g.w, args.seed, got)
@@ -185,7 +206,27 @@ def run_single(ctx, g, w_t, rp, col, args, name, unweighted):
            "gbps_alg_whole_solve_library_model": round(st.bytes_alg / (np.median(dev_ms) / 1e3) / 1e9, 1),
            "live_entries_per_phase": [int(r[0]) for r in st.log],
            "certificate_violations": cert, "roofline": roof}
+    if renew is not None:
+        out["renewed_keys"] = renew
     return out, got
+
+
+def _matching_check(g, mate):
+    """Vectorised check that mate is a valid maximal matching of g (mutual, on
+    edges, no edge with both ends free); returns its size and weight."""
+    n = g.n
+    deg = np.diff(g.row_ptr)
+    rows = np.repeat(np.arange(n, dtype=np.int32), deg)
+    m = mate.astype(np.int64)
+    matched = m >= 0
+    mutual = bool(np.all(m[m[matched]] == np.flatnonzero(matched)))
+    on_edge = g.col == mate[rows]
+    hits = np.bincount(rows[on_edge], minlength=n)
+    edges_ok = bool(np.all(hits[matched] == 1))
+    maximal = not bool(np.any((mate[rows] < 0) & (mate[g.col] < 0)))
+    del rows
+    return {"edges": int(matched.sum()) // 2, "weight": round(float(g.w[on_edge].astype(np.float64).sum()) / 2, 3),
+            "valid_maximal": mutual and edges_ok and maximal}
 
 
 def cpu_oracle(g, seed, got, reps):
@@ -221,6 +262,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--no-profile", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-graph batch")
+    ap.add_argument("--no-renew", action="store_true", help="skip the renewed-keys solves")
     ap.add_argument("--batch-replays", type=int, default=50)
     ap.add_argument("--hip-graph", action="store_true",
                     help="run each solve as one captured HIP graph (LM_GRAPH)")

@@ -88,6 +88,16 @@ typedef int32_t lm_status;
                                 LM_WEIGHT_SUM are refused (LM_EINVAL). A later call on the same
                                 context first waits for the pending solve to finish. */
 
+#define LM_RENEW_KEYS 0x80u /* renewed tie-break keys: phase t compares (w, H_t) with
+                                H_t(lo, hi) = mix(((lo << 32) | hi) XOR mix(S + t * gamma)),
+                                S = mix(seed XOR gamma), gamma = 0x9E3779B97F4A7C15, so ties
+                                are ordered anew in every phase (the fresh noise of Lemma 1's
+                                footnote and of step 1 of the CREW algorithm, Section 2.1;
+                                Section 4 asks whether renewing matters). The result is a
+                                maximal local-max matching that no longer equals the fixed-key
+                                greedy matching when weights tie; with distinct weights it is
+                                the same matching. Not with lm_server_*. */
+
 typedef struct lm_ctx lm_ctx;
 typedef struct lm_server lm_server;
 

@@ -18,7 +18,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (KERNEL_KINDS, LM_ASYNC, LM_CHECK_GRAPH, LM_GRAPH, LM_IN_DEVICE, LM_OUT_DEVICE, LM_PROFILE,
-                   LM_SERVE_BATCHED, LM_SERVE_FIFO, LM_WEIGHT_SUM, LMError, check)
+                   LM_RENEW_KEYS, LM_SERVE_BATCHED, LM_SERVE_FIFO, LM_WEIGHT_SUM, LMError, check)
 
 __all__ = ["Context", "Server", "MatchStats", "LMError", "library_path", "LM_SERVE_BATCHED", "LM_SERVE_FIFO"]
 
@@ -140,11 +140,11 @@ class Context:
 
     # -------------------------------------------------------------- solves
     def _flags_stream(self, dev_in, dev_out, check_graph, profile, stream, hip_graph=False, weight_sum=False,
-                      asynchronous=False):
+                      asynchronous=False, renew_keys=False):
         flags = (LM_IN_DEVICE if dev_in else 0) | (LM_OUT_DEVICE if dev_out else 0)
         flags |= (LM_CHECK_GRAPH if check_graph else 0) | (LM_PROFILE if profile else 0)
         flags |= (LM_GRAPH if hip_graph else 0) | (LM_WEIGHT_SUM if weight_sum else 0)
-        flags |= LM_ASYNC if asynchronous else 0
+        flags |= (LM_ASYNC if asynchronous else 0) | (LM_RENEW_KEYS if renew_keys else 0)
         s = None
         if stream is not None:
             s = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", None)
@@ -154,12 +154,14 @@ class Context:
         return flags, s
 
     def match(self, row_ptr, col, w, seed: int = 1, mate=None, *, check_graph=False, profile=False, stream=None,
-              log_cap: int = 4096, hip_graph=False, profile_kinds=None, weight_sum=False, asynchronous=False):
+              log_cap: int = 4096, hip_graph=False, profile_kinds=None, weight_sum=False, asynchronous=False,
+              renew_keys=False):
         """Solves one graph. Returns (mate, MatchStats). hip_graph=True runs the
         whole solve as one captured HIP graph (LM_GRAPH); weight_sum=True also
         returns w(M) in MatchStats.matched_weight (LM_WEIGHT_SUM);
         asynchronous=True (LM_ASYNC, device tensors only) enqueues the solve on
-        the stream and returns (mate, None) at once."""
+        the stream and returns (mate, None) at once; renew_keys=True breaks ties
+        with keys drawn anew in every phase (LM_RENEW_KEYS)."""
         n = int(row_ptr.shape[0]) - 1
         nnz = int(col.shape[0])
         rp, d0, k0 = _ptr(row_ptr, np.int64)
@@ -174,7 +176,8 @@ class Context:
             else:
                 mate = np.empty(max(n, 0), dtype=np.int32)
         mp, dm, km = _ptr(mate, np.int32)
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum, asynchronous)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum, asynchronous,
+                                      renew_keys)
         g = _lib.Csr(n, nnz, rp, cp, wp)
         if asynchronous:
             check(self._lib.lm_match(self._h, ctypes.byref(g), seed & (2**64 - 1), mp, flags, s, None), "lm_match")
@@ -219,7 +222,7 @@ class Context:
 
     def match_batch(self, vtx_off, row_ptr, col, w, seeds=None, seed0: int = 1, mate=None, *, check_graph=False,
                     profile=False, stream=None, log_cap: int = 4096, want_graph_phases=True, hip_graph=True,
-                    weight_sum=False, asynchronous=False):
+                    weight_sum=False, asynchronous=False, renew_keys=False):
         """Solves a batch (disjoint union, local ids) in one captured HIP graph
         launch unless hip_graph=False or profile=True. Returns (mate, MatchStats,
         graph_phases); with asynchronous=True (LM_ASYNC) (mate, None, None) at
@@ -245,7 +248,8 @@ class Context:
         if seeds is not None:
             sk = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
             sp = sk.ctypes.data
-        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum, asynchronous)
+        flags, s = self._flags_stream(d0, dm, check_graph, profile, stream, hip_graph, weight_sum, asynchronous,
+                                      renew_keys)
         if asynchronous:
             check(self._lib.lm_match_batch(self._h, G, vo.ctypes.data, nnz, rp, cp, wp, sp, seed0 & (2**64 - 1), mp,
                                            flags, s, None, None), "lm_match_batch")

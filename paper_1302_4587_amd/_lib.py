@@ -34,6 +34,7 @@ LM_PROFILE = 0x8
 LM_GRAPH = 0x10
 LM_WEIGHT_SUM = 0x20
 LM_ASYNC = 0x40
+LM_RENEW_KEYS = 0x80
 
 # bytes of the per-GPU scratch array of lm_match_noalloc
 LM_NOALLOC_SCRATCH_BYTES = 0x4000000

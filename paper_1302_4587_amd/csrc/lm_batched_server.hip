@@ -436,6 +436,7 @@ lm_status BatchedState::step(int k) {
     StreamArgs sa;
     sa.c = c;
     sa.in = in;
+    sa.cand_phase = t + 1;  // (fixed keys: unused)
     sa.runs_out = (Run*)runs[lo].p;
     sa.rows_out = (int4*)rows[lo].p;
     sa.dst_col = (int*)ecol[(t + 1) & 1].p;

@@ -198,4 +198,19 @@ __device__ __forceinline__ long long block_lower_bound(long long lo, long long h
   return hi;
 }
 
+// R_1 read from the CSR: the entry position of cost c, where vertex v's row
+// spans the cost units [row_ptr[v] + K v, row_ptr[v+1] + K (v+1)) (K units
+// for the piece, then one per entry). Monotone in c; c = 0 gives 0 and c =
+// L + K n gives L. Every lane gets the same value.
+template <int K>
+__device__ __forceinline__ long long csr_entry_at(const LiveSet& in, long long n, long long c, int* sm) {
+  const long long v1 = block_lower_bound(
+      0, n + 1, [&](long long v) { return in.csr_rp[v] + (long long)K * v > c; }, sm);
+  const long long v = v1 - 1;  // cost_start(0) = 0 <= c, so v1 >= 1
+  const long long u = c - (in.csr_rp[v] + (long long)K * v);
+  if (u < K || v >= n) return in.csr_rp[v];
+  const long long deg = in.csr_rp[v + 1] - in.csr_rp[v];
+  return in.csr_rp[v] + min(u - K, deg);
+}
+
 }  // namespace lm

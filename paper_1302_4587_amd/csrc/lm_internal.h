@@ -137,8 +137,10 @@ struct Common {
   const unsigned long long* gseed;  // premixed tie-break seed per graph
   int* gphase;                      // optional: last phase with a live row per graph
   int graphs;                       // 1: every piece belongs to graph 0 (no table lookups)
-  int guard;                        // phase kernels of a device-controlled solve: do nothing
+  int guard = 0;                    // phase kernels of a device-controlled solve: do nothing
                                     // once the tail kernel has taken the live set over
+  int renew = 0;                    // renewed keys: the candidates of phase t break ties with
+                                    // phase_seed(seed, t) instead of the seed
 };
 
 // A live set as the kernels see it.
@@ -156,6 +158,7 @@ struct LiveSet {
 struct StreamArgs {
   Common c;
   LiveSet in;
+  int cand_phase;    // the phase whose candidates this launch computes (renewed keys)
   // outputs (compaction only)
   Run* runs_out;
   int4* rows_out;
@@ -315,6 +318,9 @@ hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, boo
                                hipEvent_t* ev = nullptr);
 hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false, bool unweighted = false,
                           hipEvent_t* ev = nullptr);
+// First argmax of R_1 of one graph read from its CSR (a.in.csr_rp set).
+hipError_t launch_first_csr(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev = nullptr);
+int first_csr_blocks_per_cu(bool unweighted);
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 // grid must not exceed tail_blocks_per_cu() * CUs (every workgroup resident)
 hipError_t launch_tail(const TailArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);

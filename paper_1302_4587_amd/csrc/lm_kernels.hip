@@ -634,21 +634,6 @@ __device__ __forceinline__ long long piece_start(const LiveSet& in, int row) {
   return CSR ? in.csr_rp[row] : (long long)in.rows[row].y;
 }
 
-// R_1 read from the CSR: the entry position of cost c, where vertex v's row
-// spans the cost units [row_ptr[v] + K v, row_ptr[v+1] + K (v+1)) (K units
-// for the piece, then one per entry). Monotone in c; c = 0 gives 0 and c =
-// L + K n gives L. Every lane gets the same value.
-template <int K>
-__device__ __forceinline__ long long csr_entry_at(const LiveSet& in, long long n, long long c, int* sm) {
-  const long long v1 = block_lower_bound(
-      0, n + 1, [&](long long v) { return in.csr_rp[v] + (long long)K * v > c; }, sm);
-  const long long v = v1 - 1;  // cost_start(0) = 0 <= c, so v1 >= 1
-  const long long u = c - (in.csr_rp[v] + (long long)K * v);
-  if (u < K || v >= n) return in.csr_rp[v];
-  const long long deg = in.csr_rp[v + 1] - in.csr_rp[v];
-  return in.csr_rp[v] + min(u - K, deg);
-}
-
 // Global row index of piece k, walking forward from run r (updated).
 __device__ __forceinline__ int piece_row(const LiveSet& in, long long k, int& r, int nruns) {
   while (r + 1 < nruns && (long long)in.rpre[r + 1] <= k) ++r;
@@ -1002,7 +987,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
           const bool hs = ok[jj] && (FIRST || st[jj] == 0);
           unsigned long long hh = 0ull;
           if (hs) {
-            const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+            const unsigned long long S = single ? seed0 : cand_seed(a.c.gseed[sm.p_g[j]], a.c.renew, a.cand_phase);
             hh = edge_hash(S, (unsigned)(sm.p_v[j] - (single ? 0 : sm.p_base[j])), (unsigned)cc[jj]);
           }
           if (j != cur_j) {
@@ -1067,7 +1052,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     }
     // ---- 4. best candidate per piece
     auto seed_of = [&](int h) -> unsigned long long {
-      return single ? seed0 : a.c.gseed[rec[h].w & kGraphMask];
+      return single ? seed0 : cand_seed(a.c.gseed[rec[h].w & kGraphMask], a.c.renew, a.cand_phase);
     };
     auto vloc_of = [&](int h) -> unsigned {
       return (unsigned)(rec[h].x - (single ? 0 : sm.p_base[tid * kPPL + h]));
@@ -1186,7 +1171,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         if (tid + kBlock * jj < NLD && sm.p_tie[j]) {
           const uint2 e = sm.e_cw[q];
           if (e.x == sm.p_w[j]) {
-            const unsigned long long S = single ? seed0 : a.c.gseed[sm.p_g[j]];
+            const unsigned long long S = single ? seed0 : cand_seed(a.c.gseed[sm.p_g[j]], a.c.renew, a.cand_phase);
             hh = edge_hash(S, (unsigned)(sm.p_v[j] - sm.p_base[j]), e.y);
           }
         }
@@ -1283,7 +1268,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
     int slot = row_base + (int)epre;
     if (tid == 0 && old_closes) {
       close_segment<FIRST>(a, sm, carry.is_first && open_left, carry.v, carry.g, carry.base, carry.w, carry.u,
-                           single ? seed0 : a.c.gseed[carry.g], carry.kept, carry.out_start,
+                           single ? seed0 : cand_seed(a.c.gseed[carry.g], a.c.renew, a.cand_phase), carry.kept, carry.out_start,
                            emit_old ? slot++ : -1);
     }
     int sstart[kPPL];
@@ -1388,7 +1373,7 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         sm.row_cursor = slot + 1;
       }
       if (cut_left || open_right) {
-        const Key k = full_key(c.w, c.u, (unsigned)(c.v - c.base), single ? seed0 : a.c.gseed[c.g]);
+        const Key k = full_key(c.w, c.u, (unsigned)(c.v - c.base), single ? seed0 : cand_seed(a.c.gseed[c.g], a.c.renew, a.cand_phase));
         Part p;
         p.v = c.v;
         p.flags = (cut_left && open_right) ? kPartSingle : 0;
@@ -1432,7 +1417,7 @@ __global__ __launch_bounds__(kBlock, UNW ? (PPL > 1 ? 4 : 6) : (FIRST ? 4 : (PPL
   if (block_failed(a.c, &s_err)) return;
   Ctl ctl = *a.in.ctl;
   if (FIRST && ctl.Pf > 0) ctl.P = ctl.Pf;  // the first argmax's own split of R_1
-  const unsigned long long seed0 = a.c.gseed[0];
+  const unsigned long long seed0 = cand_seed(a.c.gseed[0], a.c.renew, a.cand_phase);
   for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) {
     stream_range<FIRST, PPL, UNW, VIEW>(a, ctl, b, sm, seed0);
     __syncthreads();
@@ -1491,6 +1476,7 @@ static hipError_t launch_stream(const StreamArgs& a, int grid, hipStream_t s, hi
   return launch_timed(k_stream<FIRST, PPL, UNW, kViewTables>, dim3(grid), dim3(kBlock), s, ev, a);
 }
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev) {
+  if (a.c.graphs == 1 && a.in.csr_rp && !unweighted) return launch_first_csr(a, grid, s, false, ev);
   if (unweighted) return launch_stream<true, 1, true>(a, grid, s, ev);
   return launch_stream<true, 1, false>(a, grid, s, ev);
 }

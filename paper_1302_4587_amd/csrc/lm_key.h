@@ -48,6 +48,17 @@ __device__ __forceinline__ uint64_t edge_hash(uint64_t S, unsigned a, unsigned b
   return mix64(((uint64_t)lo << 32 | (uint64_t)hi) ^ S);
 }
 
+// Renewed keys: the tie-break seed of phase t is the t-th output of a
+// SplitMix64 stream started at the run's premixed seed S (the paper's Lemma 1
+// draws fresh noise in every iteration), so H_t(lo, hi) = mix(pair XOR
+// mix(S + t gamma)).
+__host__ __device__ __forceinline__ uint64_t phase_seed(uint64_t S, int t) {
+  return mix64(S + (uint64_t)t * kGoldenGamma);
+}
+__host__ __device__ __forceinline__ uint64_t cand_seed(uint64_t S, bool renew, int t) {
+  return renew ? phase_seed(S, t) : S;
+}
+
 // The neighbour u of vertex vloc whose edge hash is h (the hash is a
 // bijection of the pair, so it names the edge).
 __device__ __forceinline__ int hash_neighbour(uint64_t h, uint64_t S, unsigned vloc) {

@@ -218,6 +218,7 @@ lm_status Solver::init_device(int device, size_t budget) {
   bpc_first_u = max_blocks_per_cu_stream(StreamKind::kFirst, true);
   bpc_late_u = max_blocks_per_cu_stream(StreamKind::kLateCompact, true);
   bpc_tail = tail_blocks_per_cu();
+  bpc_first_csr = first_csr_blocks_per_cu(false);
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = 16;  // at most: the resident count of each kernel caps it
   tun.phases_per_sync = 1;  // phases queued past the live set the host checks
@@ -309,7 +310,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
 
   // resident workgroups per CU of the kernels this solve uses
   const int bs = unweighted ? bpc_stream_u : bpc_stream;
-  const int bf = unweighted ? bpc_first_u : bpc_first;
+  const int bf = (csr1 && !unweighted) ? bpc_first_csr : (unweighted ? bpc_first_u : bpc_first);
   const int bl = unweighted ? bpc_late_u : bpc_late;
   const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bs))));
   // R_1 feeds the first argmax and the first compaction, each split to its
@@ -332,6 +333,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
   c.gphase = p.gphase;
   c.graphs = (int)p.G;
   c.guard = 0;
+  c.renew = (flags & LM_RENEW_KEYS) ? 1 : 0;
   // A device-controlled solve (LM_GRAPH, LM_ASYNC) enqueues a fixed number of
   // guarded phases and then the tail kernel; the plan that produces a live set
   // of at most tail_at entries hands it to the tail, and the guarded phases
@@ -427,6 +429,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     sa.in = live(1);
     sa.parts = wk.parts;
     sa.bstat = wk.bstat;
+    sa.cand_phase = 1;
     const int gx =
         (int)std::max<int64_t>(1, std::min<int64_t>(pcap_first, p.nnz / std::max(kCap, tun.block_entries) + 1));
     ENQ(launch_first_argmax(sa, gx, s, unweighted, timing(LM_K_ARGMAX)));
@@ -459,6 +462,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     sa.dst_w = wk.ew[(t + 1) & 1];
     sa.parts = wk.parts;
     sa.bstat = wk.bstat;
+    sa.cand_phase = t + 1;  // the compaction of phase t computes the candidates of phase t + 1
     const bool late = t > 1;
     const int gx = (int)std::max<int64_t>(
         1, std::min<int64_t>(late ? pcap_late : pcap,
@@ -831,8 +835,8 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
                               const int64_t* row_ptr, const int32_t* col, const float* w, const uint64_t* seeds,
                               uint64_t seed0, int32_t* mate, uint32_t flags, void* stream, lm_stats* st,
                               int32_t* graph_phases) {
-  const uint32_t known =
-      LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE | LM_GRAPH | LM_WEIGHT_SUM | LM_ASYNC;
+  const uint32_t known = LM_IN_DEVICE | LM_OUT_DEVICE | LM_CHECK_GRAPH | LM_PROFILE | LM_GRAPH | LM_WEIGHT_SUM |
+                         LM_ASYNC | LM_RENEW_KEYS;
   if (flags & ~known) return LM_EINVAL;
   if (flags & LM_ASYNC) {  // stream-ordered: device buffers only, nothing to report back
     if ((flags & (LM_IN_DEVICE | LM_OUT_DEVICE)) != (LM_IN_DEVICE | LM_OUT_DEVICE)) return LM_EINVAL;

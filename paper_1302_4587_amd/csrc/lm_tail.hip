@@ -483,6 +483,7 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(TailArgs a) {
           int base;
           unsigned long long Sd;
           graph_of(c, r.w, base, Sd);
+          Sd = cand_seed(Sd, c.renew, t + 1);  // the candidates of phase t + 1
           const unsigned vloc = (unsigned)(r.x - base);
           Best best = best_ident();
           const int kept = keep_row_lane(c, r, base, vloc, Sd, cur_col, cur_w, ncol, nw, best);
@@ -507,6 +508,7 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(TailArgs a) {
       int base;
       unsigned long long Sd;
       graph_of(c, r.w, base, Sd);
+      Sd = cand_seed(Sd, c.renew, t + 1);  // the candidates of phase t + 1
       const unsigned vloc = (unsigned)(v - base);
       Best best = best_ident();
       int kept = 0;
