@@ -71,6 +71,8 @@ def _load():
         lib.lmo_edge_hash_phase.restype = ctypes.c_uint64
         lib.lmo_greedy_certificate.argtypes = [ctypes.c_int64, _P64, _P32, _PF, ctypes.c_uint64, _P32]
         lib.lmo_greedy_certificate.restype = ctypes.c_int64
+        lib.lmo_contract.argtypes = [ctypes.c_int64, _P64, _P32, _PF, _P32, _P64, _P32, _P64, _P32, _PF, _P64, _P64]
+        lib.lmo_contract.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -152,3 +154,35 @@ def greedy_certificate(n, row_ptr, col, w, seed, mate) -> int:
     if r < 0:
         raise ValueError(f"certificate check rejected the input (code {r})")
     return int(r)
+
+
+def contract(n, row_ptr, col, w, mate, vw=None):
+    """Contraction by a pairing (see lm_oracle.c). w=None: every fine edge
+    weighs 1; vw=None: every vertex weighs 1. Returns (cmap int32[n],
+    coarse row_ptr int64[nc + 1], col int32[nnz_c], w float32[nnz_c],
+    vertex weights int64[nc])."""
+    rp = _c(row_ptr, np.int64)
+    cc = _c(col, np.int32)
+    nnz = int(rp[-1]) if n > 0 else 0
+    ww = None if w is None else _c(w, np.float32)
+    mm = _c(mate, np.int32)
+    vv = None if vw is None else _c(vw, np.int64)
+    cmap = np.empty(max(n, 1), dtype=np.int32)
+    crp = np.zeros(n + 1, dtype=np.int64)
+    ccol = np.empty(max(nnz, 1), dtype=np.int32)
+    cw = np.empty(max(nnz, 1), dtype=np.float32)
+    cvw = np.empty(max(n, 1), dtype=np.int64)
+    nc = ctypes.c_int64(0)
+    r = _load().lmo_contract(n, rp.ctypes.data_as(_P64), cc.ctypes.data_as(_P32),
+                             ww.ctypes.data_as(_PF) if ww is not None else None, mm.ctypes.data_as(_P32),
+                             vv.ctypes.data_as(_P64) if vv is not None else None, cmap.ctypes.data_as(_P32),
+                             crp.ctypes.data_as(_P64), ccol.ctypes.data_as(_P32), cw.ctypes.data_as(_PF),
+                             cvw.ctypes.data_as(_P64), ctypes.byref(nc))
+    if r < 0:
+        raise ValueError(f"oracle rejected the pairing (code {r})")
+    k = int(nc.value)
+    return cmap[:n].copy(), crp[: k + 1].copy(), ccol[:r].copy(), cw[:r].copy(), cvw[:k].copy()
+
+
+def contract_graph(g, mate, vw=None, unweighted=False):
+    return contract(g.n, g.row_ptr, g.col, None if unweighted else g.w, mate, vw)

@@ -306,3 +306,121 @@ int64_t lmo_greedy_certificate(int64_t n, const int64_t* row_ptr, const int32_t*
   free(has);
   return bad;
 }
+
+/*
+ * Contraction of a graph by a matching -- the coarsening step that multilevel
+ * graph partitioning repeats with maximal matchings (paper, Section 1; its
+ * Section 3.1 reports local max on graph-contraction instances). The paper
+ * gives no layout for the coarse graph; the reading fixed here:
+ *
+ *   rep(v)  = v if v is free (mate[v] = -1) or v < mate[v], else mate[v]
+ *   cmap[v] = the number of representatives r < rep(v): coarse ids follow
+ *             the order of the representatives, a pair shares one id
+ *   coarse vertex c with representative a and partner b = mate[a] (if any):
+ *     cvw[c]  = vw[a] + vw[b]                          (vw NULL: 1 each)
+ *     row c   = every coarse neighbour d != c once, in the order in which a
+ *               fine entry (s, x) with cmap[x] = d first appears when a's
+ *               row and then b's row are read in input order (entries with
+ *               cmap[x] = c, the matched edge itself, are dropped)
+ *     w(c, d) = the fp32 sum of the weights of the fine edges {s, x}, s in
+ *               c's pair and x in d's pair, added in increasing order of
+ *               (min(s, x), max(s, x)): the same order from both sides, so
+ *               the coarse graph is symmetric with equal weights both ways
+ *               (w NULL: every fine edge weighs 1).
+ *
+ * mate must be an involution (mate[mate[v]] = v, mate[v] != v) with -1 for
+ * free vertices; any such pairing is accepted, not only matchings of the
+ * graph. Output capacity: cmap n, crow_ptr n + 1, ccol and cw nnz, cvw n.
+ * Returns the coarse nnz and sets *nc_out; LMO_EINVAL on a bad pairing.
+ * Parity pins live in the tests: the coarse adjacency equals P^T A P with
+ * the diagonal removed (P the fine-to-coarse membership matrix), weight
+ * totals, identity when nothing is matched, closed forms on ladders and
+ * cycles, hand-computed fp32 sums, and planted mistakes.
+ */
+typedef struct {
+  int64_t slot; /* output position of the coarse neighbour */
+  int32_t lo, hi;
+  float w;
+} lmo_contrib;
+
+static int contrib_less(const void* pa, const void* pb) {
+  const lmo_contrib* a = (const lmo_contrib*)pa;
+  const lmo_contrib* b = (const lmo_contrib*)pb;
+  if (a->slot != b->slot) return a->slot < b->slot ? -1 : 1;
+  if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+  if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+  return 0;
+}
+
+int64_t lmo_contract(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, const int32_t* mate,
+                     const int64_t* vw, int32_t* cmap, int64_t* crow_ptr, int32_t* ccol, float* cw, int64_t* cvw,
+                     int64_t* nc_out) {
+  if (n < 0 || !row_ptr || !mate || !cmap || !crow_ptr) return LMO_EINVAL;
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t m = mate[v];
+    if (m == LMO_NONE) continue;
+    if (m < 0 || m >= n || m == v || mate[m] != v) return LMO_EINVAL;
+  }
+  /* coarse ids in the order of the representatives */
+  int64_t nc = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (mate[v] == LMO_NONE || v < mate[v]) cmap[v] = (int32_t)nc++;
+  for (int64_t v = 0; v < n; ++v)
+    if (mate[v] != LMO_NONE && v > mate[v]) cmap[v] = cmap[mate[v]];
+  int64_t maxdeg2 = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t d = row_ptr[v + 1] - row_ptr[v];
+    if (mate[v] != LMO_NONE) d += row_ptr[mate[v] + 1] - row_ptr[mate[v]];
+    if (d > maxdeg2) maxdeg2 = d;
+  }
+  int64_t* pos = (int64_t*)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+  lmo_contrib* cb = (lmo_contrib*)malloc((size_t)(maxdeg2 > 0 ? maxdeg2 : 1) * sizeof(lmo_contrib));
+  if (!pos || !cb) {
+    free(pos);
+    free(cb);
+    return LMO_ENOMEM;
+  }
+  for (int64_t d = 0; d < nc; ++d) pos[d] = -1;
+  int64_t out = 0;
+  for (int64_t a = 0; a < n; ++a) {
+    if (!(mate[a] == LMO_NONE || a < mate[a])) continue;
+    const int64_t c = cmap[a];
+    const int32_t b = mate[a];
+    crow_ptr[c] = out;
+    if (cvw) cvw[c] = (vw ? vw[a] : 1) + (b == LMO_NONE ? 0 : (vw ? vw[b] : 1));
+    int64_t ncb = 0;
+    const int64_t row0 = out;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t s = side == 0 ? a : b;
+      if (s == LMO_NONE) break;
+      for (int64_t k = row_ptr[s]; k < row_ptr[s + 1]; ++k) {
+        const int32_t x = col[k];
+        const int64_t d = cmap[x];
+        if (d == c) continue;
+        if (pos[d] < 0) {
+          pos[d] = out;
+          ccol[out++] = (int32_t)d;
+        }
+        lmo_contrib e;
+        e.slot = pos[d];
+        e.lo = (int32_t)(s < x ? s : x);
+        e.hi = (int32_t)(s < x ? x : s);
+        e.w = w ? w[k] : 1.0f;
+        cb[ncb++] = e;
+      }
+    }
+    qsort(cb, (size_t)ncb, sizeof(lmo_contrib), contrib_less);
+    for (int64_t i = 0; i < ncb; ++i) {
+      if (i == 0 || cb[i].slot != cb[i - 1].slot)
+        cw[cb[i].slot] = cb[i].w;
+      else
+        cw[cb[i].slot] += cb[i].w;
+    }
+    for (int64_t k = row0; k < out; ++k) pos[ccol[k]] = -1;
+  }
+  crow_ptr[nc] = out;
+  free(pos);
+  free(cb);
+  *nc_out = nc;
+  return out;
+}
