@@ -370,6 +370,7 @@ def main():
         "live_entries_per_phase": h["live_entries_per_phase"],
         "certificate_violations": h["certificate_violations"],
         "roofline": h["roofline"],
+        "renewed_keys": h.get("renewed_keys"),
         "cpu_baseline": cpu.get(head),
     }
     for name, res in results.items():
