@@ -225,6 +225,62 @@ lm_status lm_autotune_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off,
                             const int64_t* row_ptr, const int32_t* col, const float* w, uint32_t flags,
                             const char* cache_path, lm_tuning* out);
 
+/* ---------------- contraction by a matching (coarsening) ----------------- */
+
+/* Coarse graph written by lm_contract. The caller allocates every array with
+ * the fine graph's worst-case sizes; n and nnz are set on return. */
+typedef struct {
+  int64_t n;        /* out: coarse vertices (n_fine - matched pairs) */
+  int64_t nnz;      /* out: coarse entries (at most nnz_fine - 2 * matched pairs) */
+  int64_t* row_ptr; /* capacity n_fine + 1; receives n + 1 offsets */
+  int32_t* col;     /* capacity nnz_fine */
+  float* w;         /* capacity nnz_fine; coarse edge weights (also for an unweighted fine graph) */
+  int64_t* vwgt;    /* capacity n_fine; coarse vertex weights, or NULL if not wanted */
+} lm_coarse;
+
+typedef struct {
+  double device_ms;     /* stream time from the first kernel to the last */
+  double bytes_alg;     /* algorithmic HBM bytes: 8(n+1) + 8n + (eb + 4) nnz + 8(nc+1) + 8 nnz_c
+                           (+ 8n in, 8nc out with vertex weights), eb = 8 weighted, 4 unweighted */
+  int64_t long_rows;    /* coarse rows with deg(a) + deg(b) > 512, merged through device-memory
+                           hash tables instead of LDS */
+  int64_t long_entries; /* the fine entries of those rows */
+} lm_contract_stats;
+
+/* Contracts a graph by a matching: the coarsening step of multilevel graph
+ * partitioning, which contracts maximal matchings again and again (paper,
+ * Section 1; Section 3.1 runs local max on graph-contraction instances).
+ *
+ *   rep(v)  = v if v is free (mate[v] = -1) or v < mate[v], else mate[v]
+ *   cmap[v] = the number of representatives below rep(v): coarse ids in the
+ *             order of the pairs' smaller vertex; a pair shares one id
+ *   coarse vertex c with representative a and partner b = mate[a] (if any):
+ *     vwgt[c]  = vwgt_fine[a] + vwgt_fine[b]            (vwgt NULL: 1 each)
+ *     row c    = each coarse neighbour d != c once, in the order in which a
+ *                fine entry (s, x), cmap[x] = d, first appears when a's row
+ *                and then b's row are read in input order; the matched edge
+ *                (and any edge inside the pair) is dropped
+ *     w(c, d)  = the fp32 sum of the weights of the fine edges {s, x} with s
+ *                in c's pair and x in d's pair (at most four), added in
+ *                increasing order of (min(s, x), max(s, x)): the same order
+ *                from both sides, so the coarse graph is again symmetric with
+ *                equal weights both ways (g->w NULL: each fine edge weighs 1)
+ *
+ * g: symmetric CSR as for lm_match (no self-loops, no duplicate entries).
+ * mate: int32[n], an involution with -1 for free vertices (mate[mate[v]] = v,
+ * mate[v] != v); any pairing is accepted, not only matchings of g. vwgt:
+ * int64[n] or NULL. cmap: int32[n] output. Inputs are device pointers with
+ * LM_IN_DEVICE, outputs (cmap and out's arrays) with LM_OUT_DEVICE; no other
+ * flag is accepted. The call returns once out->n and out->nnz are set and the
+ * outputs are written (stream as in lm_match). stats may be NULL.
+ * Errors: LM_EINVAL for null pointers, bad flags or a mate that is not an
+ * involution; LM_EGRAPH for a row_ptr that is not a valid offset array, a
+ * neighbour id outside [0, n) or more than four fine edges between two pairs
+ * (duplicate entries); LM_ETOOBIG beyond the size limits of lm_match or the
+ * HBM budget. After an error the outputs are unspecified. */
+lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const int64_t* vwgt, int32_t* cmap,
+                      lm_coarse* out, uint32_t flags, void* stream, lm_contract_stats* stats);
+
 /* ---------------- serving: continuous batching at phase granularity ----- */
 
 #define LM_SERVE_BATCHED 0  /* continuous batching: resident graphs share every phase launch */

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (KERNEL_KINDS, LM_ASYNC, LM_CHECK_GRAPH, LM_GRAPH, LM_IN_DEVICE, LM_OUT_DEVICE, LM_PROFILE,
                    LM_RENEW_KEYS, LM_SERVE_BATCHED, LM_SERVE_FIFO, LM_WEIGHT_SUM, LMError, check)
 
-__all__ = ["Context", "Server", "MatchStats", "LMError", "library_path", "LM_SERVE_BATCHED", "LM_SERVE_FIFO"]
+__all__ = ["Context", "Server", "MatchStats", "ContractStats", "LMError", "library_path", "LM_SERVE_BATCHED", "LM_SERVE_FIFO"]
 
 
 def library_path() -> str:
@@ -71,6 +71,14 @@ class MatchStats:
     kernel_ms: dict = field(default_factory=dict)
     kernel_bytes: dict = field(default_factory=dict)
     matched_weight: float | None = None  # w(M), when asked for (weight_sum=True)
+
+
+@dataclass
+class ContractStats:
+    device_ms: float
+    bytes_alg: float
+    long_rows: int      # coarse rows merged through device-memory hash tables
+    long_entries: int   # their fine entries
 
 
 def _stats_out(st: _lib.Stats, logbuf, weight_sum=False) -> MatchStats:
@@ -191,6 +199,43 @@ class Context:
         check(self._lib.lm_match(self._h, ctypes.byref(g), seed & (2**64 - 1), mp, flags, s, ctypes.byref(st)),
               "lm_match")
         return mate, _stats_out(st, logbuf, weight_sum)
+
+    def contract(self, row_ptr, col, w, mate, vwgt=None, *, want_vwgt=True, stream=None):
+        """lm_contract: contracts the graph by the pairing mate (coarsening).
+        Device tensors in give device tensors out; numpy arrays in give numpy
+        arrays out. w=None: every fine edge weighs 1; vwgt=None: every vertex
+        weighs 1. Returns (cmap, coarse row_ptr, col, w, vertex weights or
+        None, ContractStats), the coarse arrays trimmed to their sizes."""
+        n = int(row_ptr.shape[0]) - 1
+        nnz = int(col.shape[0])
+        rp, d0, k0 = _ptr(row_ptr, np.int64)
+        cp, d1, k1 = _ptr(col, np.int32)
+        wp, d2, k2 = _ptr(w, np.float32, d0)
+        mp, d3, k3 = _ptr(mate, np.int32)
+        vp_, d4, k4 = _ptr(vwgt, np.int64, d0)
+        if not (d0 == d1 == d2 == d3 == d4):
+            raise ValueError("all inputs must be on the device or all on the host")
+        if d0:
+            import torch
+            dev = row_ptr.device
+            mk = lambda k, dt: torch.empty(max(k, 1), dtype=dt, device=dev)
+            cmap, crp, ccol, cw = (mk(n, torch.int32), mk(n + 1, torch.int64), mk(nnz, torch.int32),
+                                   mk(nnz, torch.float32))
+            cvw = mk(n, torch.int64) if want_vwgt else None
+        else:
+            cmap, crp = np.empty(max(n, 1), np.int32), np.empty(n + 1, np.int64)
+            ccol, cw = np.empty(max(nnz, 1), np.int32), np.empty(max(nnz, 1), np.float32)
+            cvw = np.empty(max(n, 1), np.int64) if want_vwgt else None
+        ptr = (lambda x: x.data_ptr()) if d0 else (lambda x: x.ctypes.data)
+        out = _lib.Coarse(0, 0, ptr(crp), ptr(ccol), ptr(cw), ptr(cvw) if cvw is not None else None)
+        flags, s = self._flags_stream(d0, d0, False, False, stream)
+        g = _lib.Csr(n, nnz, rp, cp, wp)
+        st = _lib.ContractStats()
+        check(self._lib.lm_contract(self._h, ctypes.byref(g), mp, vp_, ptr(cmap), ctypes.byref(out), flags, s,
+                                    ctypes.byref(st)), "lm_contract")
+        nc, mc = int(out.n), int(out.nnz)
+        return (cmap[:n], crp[:nc + 1], ccol[:mc], cw[:mc], cvw[:nc] if cvw is not None else None,
+                ContractStats(float(st.device_ms), float(st.bytes_alg), int(st.long_rows), int(st.long_entries)))
 
     def match_noalloc(self, row_ptr, col, w, seed: int = 1, mate=None, *, check_graph=False, stream=None,
                       log_cap: int = 4096):

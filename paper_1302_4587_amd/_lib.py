@@ -48,7 +48,7 @@ LM_SERVE_FIFO = 1
 EXPORTED = (
     "lm_create", "lm_destroy", "lm_match", "lm_match_noalloc", "lm_match_batch", "lm_get_tuning", "lm_set_tuning",
     "lm_autotune_batch", "lm_server_create", "lm_server_submit", "lm_server_poll", "lm_server_wait",
-    "lm_server_destroy", "lm_strerror",
+    "lm_server_destroy", "lm_strerror", "lm_contract",
 )
 
 
@@ -73,6 +73,16 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block_entries", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
                 ("phases_per_sync", ctypes.c_int32), ("tail_entries", ctypes.c_int32)]
+
+
+class Coarse(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("vwgt", ctypes.c_void_p)]
+
+
+class ContractStats(ctypes.Structure):
+    _fields_ = [("device_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double), ("long_rows", ctypes.c_int64),
+                ("long_entries", ctypes.c_int64)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -112,10 +122,12 @@ def load():
     lib.lm_server_poll.argtypes = [vp, u64, vp, ctypes.POINTER(RequestStats)]
     lib.lm_server_wait.argtypes = [vp, u64, vp, ctypes.POINTER(RequestStats), i64]
     lib.lm_server_destroy.argtypes = [vp]
+    lib.lm_contract.argtypes = [vp, ctypes.POINTER(Csr), vp, vp, vp, ctypes.POINTER(Coarse), u32, vp,
+                                ctypes.POINTER(ContractStats)]
     lib.lm_strerror.argtypes = [i32]
     lib.lm_strerror.restype = ctypes.c_char_p
     for f in ("lm_create", "lm_match", "lm_match_noalloc", "lm_match_batch", "lm_get_tuning", "lm_set_tuning", "lm_autotune_batch",
-              "lm_server_create", "lm_server_submit", "lm_server_poll", "lm_server_wait", "lm_server_destroy"):
+              "lm_server_create", "lm_server_submit", "lm_server_poll", "lm_server_wait", "lm_server_destroy", "lm_contract"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "liblm.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 ARCH = os.environ.get("LM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["lm_kernels.hip", "lm_solver.hip", "lm_server.hip", "lm_batched_server.hip", "lm_weight.hip", "lm_noalloc.hip", "lm_tail.hip", "lm_first.hip"]
+SOURCES = ["lm_kernels.hip", "lm_solver.hip", "lm_server.hip", "lm_batched_server.hip", "lm_weight.hip", "lm_noalloc.hip", "lm_tail.hip", "lm_first.hip", "lm_contract.hip"]
 HEADERS = ["lm_internal.h", "lm_key.h", "lm_runtime.h", "lm_server_impl.h"]
 
 FLAGS = [

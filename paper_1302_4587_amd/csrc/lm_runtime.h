@@ -72,6 +72,8 @@ struct Problem {
   int* gphase = nullptr;  // optional per-graph phase counts
 };
 
+struct ContractState;  // buffers of lm_contract (lm_contract.hip)
+
 struct Solver {
   int dev = -1;
   int num_cus = 0;
@@ -96,6 +98,7 @@ struct Solver {
   DevBuf gbase, gseed, vtxoff, gphase, totals, tailc;
   DevBuf in_rp, in_col, in_w, out_mate;
   DevBuf wsum;  // kWeightSumMaxGrid partial sums, then the total
+  ContractState* contract = nullptr;
 
   Totals* h_totals = nullptr;
   // mapped pinned host memory the plan kernel writes: one record per live set
@@ -133,6 +136,8 @@ hipError_t launch_weight_sum(const long long* row_ptr, const int* col, const flo
                              double* scratch, hipStream_t s);
 
 const char* status_text(lm_status st);
+// Frees the contraction's buffers (at context shutdown).
+void contract_release(Solver& S);
 // Looks up this device's copy of the allocation-free solve's scratch array
 // (lm_match_noalloc); called once per device with that device current.
 lm_status noalloc_setup(int dev);

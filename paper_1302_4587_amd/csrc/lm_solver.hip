@@ -236,6 +236,7 @@ void Solver::shutdown() {
                    &bstat,   &mcount,  &gbase,   &gseed,   &vtxoff,  &gphase,  &totals,  &in_rp,
                    &in_col,  &in_w,    &out_mate, &wsum,   &tailc};
   for (DevBuf* b : all) pool.release(*b);
+  contract_release(*this);
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   evpool.clear();
   if (e0) (void)hipEventDestroy(e0);

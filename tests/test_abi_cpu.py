@@ -58,7 +58,9 @@ def test_struct_layouts_match_header():
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "lm.h"\nint main(void){'
            'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lm_csr), sizeof(lm_stats), sizeof(lm_phase_rec),'
            'sizeof(lm_tuning), sizeof(lm_server_opts), sizeof(lm_request_stats), offsetof(lm_stats, k_bytes),'
-           'offsetof(lm_stats, log_cap), offsetof(lm_stats, matched_weight)); return 0; }\n')
+           'offsetof(lm_stats, log_cap), offsetof(lm_stats, matched_weight));'
+           'printf("%zu %zu %zu\\n", sizeof(lm_coarse), sizeof(lm_contract_stats), offsetof(lm_coarse, vwgt));'
+           'return 0; }\n')
     exe = os.path.join(ROOT, "_build", "layout_probe")
     os.makedirs(os.path.dirname(exe), exist_ok=True)
     r = subprocess.run(["gcc", "-std=c99", f"-I{ROOT}/include", "-x", "c", "-", "-o", exe], input=src,
@@ -67,7 +69,8 @@ def test_struct_layouts_match_header():
     vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     mine = [ctypes.sizeof(L.Csr), ctypes.sizeof(L.Stats), ctypes.sizeof(L.PhaseRec), ctypes.sizeof(L.Tuning),
             ctypes.sizeof(L.ServerOpts), ctypes.sizeof(L.RequestStats), L.Stats.k_bytes.offset, L.Stats.log_cap.offset,
-            L.Stats.matched_weight.offset]
+            L.Stats.matched_weight.offset, ctypes.sizeof(L.Coarse), ctypes.sizeof(L.ContractStats),
+            L.Coarse.vwgt.offset]
     assert vals == mine
 
 
@@ -93,6 +96,7 @@ def test_null_arguments_rejected_without_device():
     assert lib.lm_server_poll(None, 1, None, None) == L.LM_EINVAL
     assert lib.lm_server_destroy(None) == L.LM_EINVAL
     assert lib.lm_set_tuning(None, None) == L.LM_EINVAL
+    assert lib.lm_contract(None, None, None, None, None, None, 0, None, None) == L.LM_EINVAL
 
 
 def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
