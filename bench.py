@@ -41,6 +41,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 KERNEL_SOURCES = ["paper_1302_4587_amd/csrc/lm_kernels.hip", "paper_1302_4587_amd/csrc/lm_device.h",
                   "paper_1302_4587_amd/csrc/lm_key.h", "paper_1302_4587_amd/csrc/lm_internal.h",
                   "paper_1302_4587_amd/csrc/lm_tail.hip", "paper_1302_4587_amd/csrc/lm_first.hip"]
+CONTRACT_SOURCES = ["paper_1302_4587_amd/csrc/lm_contract.hip"]
 
 
 def _kernel_sha():
@@ -195,6 +196,9 @@ def run_single(ctx, g, w_t, rp, col, args, name, unweighted):
                  "matched_edges_fixed": chk_f["edges"], "matched_edges_renewed": chk_r["edges"],
                  "matched_weight_fixed": chk_f["weight"], "matched_weight_renewed": chk_r["weight"],
                  "renewed_valid_maximal": chk_r["valid_maximal"]}
+    contract = None
+    if not args.no_contract:
+        contract = run_contract(ctx, g, w_t, rp, col, got, args, unweighted)
     import oracle  # test infrastructure: certificate and CPU baseline only
 
     cert = oracle.greedy_certificate(g.n, g.row_ptr, g.col, g.w, args.seed, got)
@@ -208,7 +212,54 @@ def run_single(ctx, g, w_t, rp, col, args, name, unweighted):
            "certificate_violations": cert, "roofline": roof}
     if renew is not None:
         out["renewed_keys"] = renew
+    if contract is not None:
+        out["contract"] = contract
     return out, got
+
+
+def run_contract(ctx, g, w_t, rp, col, got, args, unweighted):
+    """Contracts the graph by its matching (lm_contract, the coarsening step):
+    args.steps timed calls after two untimed ones, then the oracle on the
+    same input for equality and the CPU time."""
+    import torch
+
+    dev = rp.device
+    mate_t = torch.from_numpy(got).to(dev)
+    for _ in range(2):
+        ctx.contract(rp, col, w_t, mate_t)
+    torch.cuda.synchronize()
+    lat, dms = [], []
+    out = None
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        out = ctx.contract(rp, col, w_t, mate_t)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        dms.append(out[5].device_ms)
+    torch.cuda.synchronize()
+    st = out[5]
+    dev_ms = float(np.median(dms))
+    achieved = st.bytes_alg / (dev_ms / 1e3) / 1e9
+    res = {"ms_per_call": round(float(np.median(lat)), 4), "device_ms_median": round(dev_ms, 4),
+           "fine_edges_per_s": round(g.m / (dev_ms / 1e3), 1), "coarse_n": int(out[1].shape[0]) - 1,
+           "coarse_nnz": int(out[2].shape[0]), "long_rows": st.long_rows, "long_entries": st.long_entries,
+           "roofline": {"bound": "hbm", "kernel": "whole contraction", "achieved": round(achieved, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "bytes_per_call": st.bytes_alg,
+                        "bytes_model": "8(n+1) + 8n + (eb+4) nnz + 8(nc+1) + 8 nnz_c, eb = 4 unweighted, 8 weighted"}}
+    if not args.no_cpu:
+        import oracle  # test infrastructure: equality check and CPU baseline only
+
+        t1 = time.perf_counter()
+        want = oracle.contract(g.n, g.row_ptr, g.col, None if unweighted else g.w, got)
+        cpu_s = time.perf_counter() - t1
+        gotc = [x.cpu().numpy() for x in out[:4]]
+        same = all(np.array_equal(a.view(np.uint32) if a.dtype == np.float32 else a,
+                                  np.asarray(b).view(np.uint32) if a.dtype == np.float32 else b)
+                   for a, b in zip(gotc, want[:4]))
+        res["matches_oracle"] = bool(same)
+        res["cpu_baseline"] = {"value": round(g.m / cpu_s, 1), "unit": "fine edges/s", "cores": 1, "kind": "oracle",
+                               "sample": f"whole graph, one call, {cpu_s:.2f}s"}
+    return res
 
 
 def _matching_check(g, mate):
@@ -263,6 +314,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-graph batch")
     ap.add_argument("--no-renew", action="store_true", help="skip the renewed-keys solves")
+    ap.add_argument("--no-contract", action="store_true", help="skip the contraction by the matching")
     ap.add_argument("--batch-replays", type=int, default=50)
     ap.add_argument("--hip-graph", action="store_true",
                     help="run each solve as one captured HIP graph (LM_GRAPH)")
@@ -371,6 +423,7 @@ def main():
         "certificate_violations": h["certificate_violations"],
         "roofline": h["roofline"],
         "renewed_keys": h.get("renewed_keys"),
+        "contract": h.get("contract"),
         "cpu_baseline": cpu.get(head),
     }
     for name, res in results.items():

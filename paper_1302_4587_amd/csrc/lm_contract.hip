@@ -14,13 +14,14 @@
 // coarse row whose bound deg(a) + deg(b) is at most kCS is merged in LDS: a
 // workgroup takes the coarse rows of a range of fine vertices in tiles of at
 // most kCT entries, maps each entry's neighbour through cmap, and groups the
-// entries of one (coarse row, coarse neighbour) in an LDS hash table with a
-// list per slot; the first entry of a group (in row order) sums the group
-// and keeps it. (3) Longer rows get a hash table of their own in device
-// memory and the same grouping over all their entries at once. (4) A scan
-// over the coarse rows gives their offsets, and the kept entries of every
-// row part are packed in order to the output. Every entry of the fine graph
-// is read twice (grouping, packing); cmap is gathered once per entry.
+// entries of one coarse neighbour in the row's own slots of an LDS hash
+// table, with a list per slot; the first entry of a group (in row order)
+// keeps it with the group's sum, and the kept entries are written compacted
+// at the start of their fine row part. (3) Longer rows get a hash table of
+// their own in device memory and the same grouping over all their entries at
+// once. (4) A scan over the coarse rows gives their offsets and the kept
+// entries are copied out in order. The fine graph's entries are read once;
+// cmap is gathered once per entry.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,8 +43,6 @@ constexpr int kCT = 1024;               // tile capacity in entries
 constexpr int kCS = 512;                // largest coarse-row bound merged in LDS
 constexpr int kCStep = kCT - kCS;       // tiles take the rows that start in a window of this many entries
 constexpr int kCTI = kCT / kBlock;      // tile entries per lane
-constexpr int kCH = 2048;               // LDS hash slots (load at most 1/2)
-constexpr int kCHBits = 11;
 constexpr int kCMaxDup = 4;             // fine edges one coarse edge merges at most in a simple graph
 constexpr int kCCost = 4;               // cost of a fine vertex when ranges are split (entries cost 1)
 constexpr int kCTopThreads = 1024;
@@ -96,9 +95,6 @@ struct CArgs {
   float* cw;
 };
 
-__device__ __forceinline__ unsigned lds_hash(int r, int d) {
-  return ((unsigned)d * 0x9E3779B1u ^ (unsigned)r * 0x85EBCA77u) >> (32 - kCHBits);
-}
 __device__ __forceinline__ unsigned long long tbl_hash(int d, int bits) {
   return (unsigned long long)(((unsigned)d * 0x9E3779B1u) >> (32 - bits));
 }
@@ -120,14 +116,15 @@ __device__ __forceinline__ long long top_excl_sum(long long x, long long* sm, lo
   return pre + incl - x;
 }
 
-// (1a) Checks mate and row_ptr, counts the pairs' smaller ends per block.
+// (1a) Checks mate and row_ptr and counts the pairs' smaller ends per block
+// (vertex base + i * kBlock + lane: coalesced).
 __global__ __launch_bounds__(kBlock) void k_c_count(CArgs a) {
   __shared__ long long sm[kWaves];
-  const long long v0 = (long long)blockIdx.x * kCBlockV + (long long)threadIdx.x * kCV;
+  const long long base = (long long)blockIdx.x * kCBlockV;
   unsigned err = 0;
   long long reps = 0;
   for (int i = 0; i < kCV; ++i) {
-    const long long v = v0 + i;
+    const long long v = base + (long long)i * kBlock + threadIdx.x;
     if (v >= a.n) break;
     const int m = a.mate[v];
     if (m != -1) {
@@ -162,28 +159,52 @@ __global__ __launch_bounds__(kCTopThreads) void k_c_scan_top(long long* v, long 
   if (threadIdx.x == 0) *total = carry;
 }
 
+// Exclusive prefix, in index order, of the kCBlockV values a block staged in
+// val[] (value of index base + i * kBlock + lane at val[i * kBlock + lane]):
+// every lane sums kCV consecutive values, the lanes are scanned, and val[]
+// receives the prefixes. Returns the block total.
+__device__ __forceinline__ long long block_stage_scan(long long* val, long long start, long long* sm) {
+  long long s = 0;
+  for (int j = 0; j < kCV; ++j) s += val[threadIdx.x * kCV + j];
+  long long total;
+  long long run = start + block_excl_sum<long long>(s, sm, total);  // ends after a barrier
+  for (int j = 0; j < kCV; ++j) {
+    const long long x = val[threadIdx.x * kCV + j];
+    val[threadIdx.x * kCV + j] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
 // (1c) Numbers the coarse vertices, writes cmap, the coarse vertex weights,
 // and clears the per-row-part counts.
 __global__ __launch_bounds__(kBlock) void k_c_map(CArgs a) {
+  __shared__ long long val[kCBlockV];
   __shared__ long long sm[kWaves];
   if (a.tot->err) return;
-  const long long v0 = (long long)blockIdx.x * kCBlockV + (long long)threadIdx.x * kCV;
-  long long reps = 0;
+  const long long base = (long long)blockIdx.x * kCBlockV;
+  int mm[kCV];
+#pragma unroll
   for (int i = 0; i < kCV; ++i) {
-    const long long v = v0 + i;
-    if (v >= a.n) break;
-    const int m = a.mate[v];
-    reps += (m == -1 || v < m) ? 1 : 0;
+    const long long v = base + (long long)i * kBlock + threadIdx.x;
+    int m = -2, f = 0;
+    if (v < a.n) {
+      m = a.mate[v];
+      f = (m == -1 || v < m) ? 1 : 0;
+      a.cnt[v] = 0;
+    }
+    mm[i] = m;
+    val[i * kBlock + threadIdx.x] = f;
   }
-  long long total;
-  long long id = a.bsum[blockIdx.x] + block_excl_sum<long long>(reps, sm, total);
+  __syncthreads();
+  (void)block_stage_scan(val, a.bsum[blockIdx.x], sm);
+#pragma unroll
   for (int i = 0; i < kCV; ++i) {
-    const long long v = v0 + i;
-    if (v >= a.n) break;
-    a.cnt[v] = 0;
-    const int m = a.mate[v];
-    if (!(m == -1 || v < m)) continue;
-    const int c = (int)id++;
+    const long long v = base + (long long)i * kBlock + threadIdx.x;
+    const int m = mm[i];
+    if (v >= a.n || !(m == -1 || v < m)) continue;
+    const int c = (int)val[i * kBlock + threadIdx.x];
     a.cmap[v] = c;
     a.crep[c] = (int)v;
     if (m >= 0) a.cmap[m] = c;
@@ -191,31 +212,70 @@ __global__ __launch_bounds__(kBlock) void k_c_map(CArgs a) {
   }
 }
 
-struct TileSmem {
-  unsigned long long key[kCH];  // (row in chunk << 32 | coarse neighbour), kEmpty if free
-  int head[kCH];                // last entry inserted into the slot's list
-  int eD[kCT];                  // coarse neighbour of the entry, -1 for the matched edge
-  int ex[kCT];                  // fine neighbour
-  float ew[kCT];
-  int ek[kCT];                  // fine entry index (pack: exclusive rank among kept entries)
+// A fine vertex as the head of a coarse row.
+struct RowHead {
+  bool rep, lng;
+  int m, c, dega, ub;
+  long long ka, kb;
+};
+__device__ __forceinline__ RowHead row_head(const CArgs& a, long long v) {
+  RowHead h;
+  h.m = a.mate[v];
+  h.rep = (h.m == -1 || v < h.m);
+  h.c = 0;
+  h.dega = h.ub = 0;
+  h.ka = h.kb = 0;
+  h.lng = false;
+  if (h.rep) {
+    h.c = a.cmap[v];
+    h.ka = a.rp[v];
+    h.dega = (int)(a.rp[v + 1] - h.ka);
+    h.ub = h.dega;
+    if (h.m >= 0) {
+      h.kb = a.rp[h.m];
+      h.ub += (int)(a.rp[h.m + 1] - h.kb);
+    }
+    h.lng = h.ub > kCS;
+  }
+  return h;
+}
+
+// The fine vertices [vb, ve) of workgroup blockIdx.x: ranges split by
+// entries plus kCCost per vertex.
+__device__ __forceinline__ void wg_vertices(const CArgs& a, long long per_wg, long long& vb, long long& ve, int* lb) {
+  const long long C = a.nnz + (long long)kCCost * a.n;
+  const long long c0 = (long long)blockIdx.x * per_wg;
+  const long long c1 = c0 + per_wg;
+  vb = c0 >= C ? a.n
+               : block_lower_bound(0, a.n + 1, [&](long long v) { return a.rp[v] + (long long)kCCost * v >= c0; },
+                                   lb);
+  ve = c1 >= C ? a.n
+               : block_lower_bound(0, a.n + 1, [&](long long v) { return a.rp[v] + (long long)kCCost * v >= c1; },
+                                   lb);
+}
+
+struct GroupSmem {
+  int skey[2 * kCT];      // coarse neighbour of the slot, -1 if free
+  int shead[2 * kCT];     // last tile position inserted into the slot's list
+  int erank[kCT + 1];     // coarse neighbour, then exclusive rank among the kept entries
   short enext[kCT];
   short eslot[kCT];
   unsigned char erow[kCT];
   int st[kBlock + 1];  // chunk-local start of each row's entries; st[kBlock] = chunk total
-  int ra[kBlock], rb[kBlock], rc[kBlock], rdega[kBlock];
-  int rcnt[2][kBlock];
-  long long sm64[kWaves];
+  int ra[kBlock], rb[kBlock], rc[kBlock], rdega[kBlock], rut[kBlock];
+  long long rka[kBlock], rkb[kBlock];
+  int wcnt[kCTI * kWaves];
   int smi[kWaves];
   int lb[1];
 };
 
 // Last row r of the chunk with st[r] <= pos (rows with no tile entries share
 // their start with the next row, so r is the row that holds pos).
-__device__ __forceinline__ int row_of(const TileSmem& sm, int pos) {
+__device__ __forceinline__ int row_of(const int* st, int pos) {
   int lo = 0, hi = kBlock;  // st[lo] <= pos; answer in [lo, hi)
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (sm.st[mid] <= pos)
+    if (st[mid] <= pos)
       lo = mid;
     else
       hi = mid;
@@ -223,141 +283,177 @@ __device__ __forceinline__ int row_of(const TileSmem& sm, int pos) {
   return lo;
 }
 // Start of the first row whose start is at least t (the chunk total if none).
-__device__ __forceinline__ int start_at(const TileSmem& sm, int t) {
-  int lo = 0, hi = kBlock;  // smallest r in [0, kBlock] with st[r] >= t
-  if (sm.st[0] >= t) return sm.st[0];
+__device__ __forceinline__ int start_at(const int* st, int t) {
+  if (st[0] >= t) return st[0];
+  int lo = 0, hi = kBlock;  // st[lo] < t; smallest r in (lo, kBlock] with st[r] >= t
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (sm.st[mid] >= t)
+    if (st[mid] >= t)
       hi = mid;
     else
       lo = mid;
   }
-  return sm.st[hi];
+  return st[hi];
 }
 
-// (2) PASS 0: groups the entries of the short coarse rows and keeps the first
-// of every group with the group's sum; queues the long rows. PASS 1: packs
-// the kept entries of the short rows to the output in order.
-template <int PASS>
-__global__ __launch_bounds__(kBlock) void k_c_tiles(CArgs a, long long per_wg) {
-  __shared__ TileSmem sm;
+// Sums the fine edges of one group in increasing (min end, max end).
+__device__ __forceinline__ float group_sum(const unsigned long long* ord_in, const float* w_in, int n) {
+  unsigned long long ord[kCMaxDup];
+  float wv[kCMaxDup];
+  for (int t = 0; t < n; ++t) {
+    const unsigned long long o = ord_in[t];
+    const float ww = w_in[t];
+    int u = t;
+    while (u > 0 && ord[u - 1] > o) {
+      ord[u] = ord[u - 1];
+      wv[u] = wv[u - 1];
+      --u;
+    }
+    ord[u] = o;
+    wv[u] = ww;
+  }
+  float sum = wv[0];
+  for (int t = 1; t < n; ++t) sum += wv[t];
+  return sum;
+}
+
+__device__ __forceinline__ unsigned long long edge_order(int s, int x) {
+  return ((unsigned long long)(unsigned)min(s, x) << 32) | (unsigned)max(s, x);
+}
+
+// (2) Groups the entries of every short coarse row (bound <= kCS) in LDS and
+// keeps, compacted in place at the start of each row part, the first entry of
+// every group with the group's sum; sets the parts' kept counts. Queues the
+// long rows.
+__global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
+  __shared__ GroupSmem sm;
   if (a.tot->err & (kCErrMate | kCErrRowPtr)) return;
   const int tid = threadIdx.x;
-  const long long C = a.nnz + (long long)kCCost * a.n;
-  const long long c0 = (long long)blockIdx.x * per_wg;
-  if (c0 >= C) return;
-  const long long c1 = c0 + per_wg;
-  const long long vb =
-      block_lower_bound(0, a.n + 1, [&](long long v) { return a.rp[v] + (long long)kCCost * v >= c0; }, sm.lb);
-  const long long ve = c1 >= C ? a.n
-                               : block_lower_bound(0, a.n + 1,
-                                                   [&](long long v) { return a.rp[v] + (long long)kCCost * v >= c1; },
-                                                   sm.lb);
-  if (PASS == 0) {
-    for (int i = tid; i < kCH; i += kBlock) {
-      sm.key[i] = kEmpty;
-      sm.head[i] = -1;
-    }
+  const int wv_id = wave_id();
+  long long vb, ve;
+  wg_vertices(a, per_wg, vb, ve, sm.lb);
+  for (int i = tid; i < 2 * kCT; i += kBlock) {
+    sm.skey[i] = -1;
+    sm.shead[i] = -1;
   }
   unsigned err = 0;
   for (long long cb = vb; cb < ve; cb += kBlock) {
     const long long v = cb + tid;
-    int ut = 0;
-    bool rep = false, lng = false;
-    int m = -1, c = 0, dega = 0, ub = 0;
+    RowHead h;
+    h.rep = false;
+    h.lng = false;
+    h.m = -1;
+    h.c = h.dega = h.ub = 0;
+    h.ka = h.kb = 0;
     if (v < ve) {
-      m = a.mate[v];
-      rep = (m == -1 || v < m);
-      if (rep) {
-        c = a.cmap[v];
-        dega = (int)(a.rp[v + 1] - a.rp[v]);
-        ub = dega + (m >= 0 ? (int)(a.rp[m + 1] - a.rp[m]) : 0);
-        lng = ub > kCS;
-        ut = lng ? 0 : ub;
-        if (PASS == 0 && lng) {
-          const unsigned long long idx = atomicAdd((unsigned long long*)&a.tot->nlong, 1ull);
-          if ((long long)idx < a.lrow_cap) {
-            LongRow L;
-            L.a = (int)v;
-            L.b = m;
-            L.c = c;
-            L.dega = dega;
-            L.ub = ub;
-            L.tbits = 0;
-            L.eoff = 0;
-            L.toff = 0;
-            a.lrows[idx] = L;
-          }
+      h = row_head(a, v);
+      if (h.rep && h.lng) {
+        const unsigned long long idx = atomicAdd((unsigned long long*)&a.tot->nlong, 1ull);
+        if ((long long)idx < a.lrow_cap) {
+          LongRow L;
+          L.a = (int)v;
+          L.b = h.m;
+          L.c = h.c;
+          L.dega = h.dega;
+          L.ub = h.ub;
+          L.tbits = 0;
+          L.eoff = 0;
+          L.toff = 0;
+          a.lrows[idx] = L;
         }
       }
     }
+    const int ut = (h.rep && !h.lng) ? h.ub : 0;
     int U;
     const int st = block_excl_sum<int>(ut, sm.smi, U);
     sm.st[tid] = st;
     if (tid == 0) sm.st[kBlock] = U;
     sm.ra[tid] = (int)v;
-    sm.rb[tid] = m;
-    sm.rc[tid] = c;
-    sm.rdega[tid] = dega;
-    sm.rcnt[0][tid] = 0;
-    sm.rcnt[1][tid] = 0;
+    sm.rb[tid] = h.m;
+    sm.rc[tid] = h.c;
+    sm.rdega[tid] = h.dega;
+    sm.rut[tid] = ut;
+    sm.rka[tid] = h.ka;
+    sm.rkb[tid] = h.kb;
     __syncthreads();
     const int ntile = (U + kCStep - 1) / kCStep;
     for (int j = 0; j < ntile; ++j) {
-      const int lo = start_at(sm, j * kCStep);
-      const int hi = start_at(sm, (j + 1) * kCStep);
+      const int lo = start_at(sm.st, j * kCStep);
+      const int hi = start_at(sm.st, (j + 1) * kCStep);
       const int len = hi - lo;
       if (len <= 0) continue;  // uniform across the workgroup
-      if (PASS == 0) {
+      int Dr[kCTI], xr[kCTI];
+      float wr[kCTI];
+      // 1: load every entry of the lane, then map them all, then insert (the
+      // loads of all rounds are in flight together)
+      int rr[kCTI];
+      long long kr[kCTI];
 #pragma unroll
-        for (int i = 0; i < kCTI; ++i) {
-          const int q = i * kBlock + tid;
-          if (q >= len) break;
+      for (int i = 0; i < kCTI; ++i) {
+        const int q = i * kBlock + tid;
+        rr[i] = 0;
+        kr[i] = -1;
+        Dr[i] = -1;
+        xr[i] = 0;
+        wr[i] = 0.f;
+        if (q < len) {
           const int pos = lo + q;
-          const int r = row_of(sm, pos);
+          const int r = row_of(sm.st, pos);
           const int off = pos - sm.st[r];
           const bool side = off >= sm.rdega[r];
-          const int s = side ? sm.rb[r] : sm.ra[r];
-          const long long k = a.rp[s] + (side ? off - sm.rdega[r] : off);
-          const int x = a.col[k];
-          int D = -1;
-          if ((unsigned)x >= (unsigned)a.n)
-            err |= kCErrCol;
-          else
-            D = a.cmap[x];
-          if (D == sm.rc[r]) D = -1;
-          sm.eD[q] = D;
-          sm.ex[q] = x;
-          sm.ew[q] = a.w ? a.w[k] : 1.0f;
-          sm.ek[q] = (int)k;
+          rr[i] = r;
+          kr[i] = side ? sm.rkb[r] + (off - sm.rdega[r]) : sm.rka[r] + off;
           sm.erow[q] = (unsigned char)r;
-          if (D >= 0) {
-            const unsigned long long kk = ((unsigned long long)(unsigned)r << 32) | (unsigned)D;
-            unsigned h = lds_hash(r, D);
-            for (;;) {
-              const unsigned long long old = atomicCAS(&sm.key[h], kEmpty, kk);
-              if (old == kEmpty || old == kk) break;
-              h = (h + 1) & (kCH - 1);
-            }
-            sm.eslot[q] = (short)h;
-            sm.enext[q] = (short)atomicExch(&sm.head[h], q);
-          }
         }
-        __syncthreads();
+      }
 #pragma unroll
-        for (int i = 0; i < kCTI; ++i) {
-          const int q = i * kBlock + tid;
-          if (q >= len) break;
-          const int D = sm.eD[q];
-          const long long k = sm.ek[q];
-          if (D < 0) {
-            a.scr[k] = make_int2(-1, 0);
-            continue;
+      for (int i = 0; i < kCTI; ++i) {
+        if (kr[i] < 0) continue;
+        xr[i] = a.col[kr[i]];
+        wr[i] = a.w ? a.w[kr[i]] : 1.0f;
+      }
+#pragma unroll
+      for (int i = 0; i < kCTI; ++i) {
+        if (kr[i] < 0) continue;
+        if ((unsigned)xr[i] >= (unsigned)a.n)
+          err |= kCErrCol;
+        else
+          Dr[i] = a.cmap[xr[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < kCTI; ++i) {
+        const int q = i * kBlock + tid;
+        const int r = rr[i];
+        if (kr[i] < 0) continue;
+        if (Dr[i] == sm.rc[r]) Dr[i] = -1;
+        const int D = Dr[i];
+        if (D >= 0) {
+          // the row's own slots: 2 * (its bound) of them from 2 * (its tile start)
+          const unsigned sb = 2u * (unsigned)(sm.st[r] - lo);
+          const unsigned range = 2u * (unsigned)sm.rut[r];
+          unsigned hh = (unsigned)(((unsigned long long)((unsigned)D * 0x9E3779B1u) * range) >> 32);
+          for (;;) {
+            const int old = atomicCAS(&sm.skey[sb + hh], -1, D);
+            if (old == -1 || old == D) break;
+            hh = hh + 1 == range ? 0u : hh + 1;
           }
+          sm.eslot[q] = (short)(sb + hh);
+          sm.enext[q] = (short)atomicExch(&sm.shead[sb + hh], q);
+        }
+      }
+      __syncthreads();
+      // 2: the first entry of every group keeps it, with the group's sum
+      bool keep[kCTI];
+      float sumr[kCTI];
+#pragma unroll
+      for (int i = 0; i < kCTI; ++i) {
+        const int q = i * kBlock + tid;
+        keep[i] = false;
+        sumr[i] = 0.f;
+        if (q < len && Dr[i] >= 0) {
           int lst[kCMaxDup + 1];
           int nl = 0;
-          int p = sm.head[sm.eslot[q]];
+          int p = sm.shead[sm.eslot[q]];
           bool first = true;
           while (p >= 0 && nl <= kCMaxDup) {
             lst[nl++] = p;
@@ -365,104 +461,134 @@ __global__ __launch_bounds__(kBlock) void k_c_tiles(CArgs a, long long per_wg) {
             p = sm.enext[p];
           }
           if (nl > kCMaxDup) err |= kCErrDup;
-          if (!first || nl > kCMaxDup) {
-            a.scr[k] = make_int2(-1, 0);
-            continue;
-          }
-          const int r = sm.erow[q];
-          // the group's fine edges in increasing (min end, max end)
-          unsigned long long ord[kCMaxDup];
-          float wv[kCMaxDup];
-          for (int t = 0; t < nl; ++t) {
-            const int pp = lst[t];
-            const int off = lo + pp - sm.st[r];
-            const int s = off >= sm.rdega[r] ? sm.rb[r] : sm.ra[r];
-            const int x = sm.ex[pp];
-            const unsigned lo_e = (unsigned)min(s, x), hi_e = (unsigned)max(s, x);
-            unsigned long long o = ((unsigned long long)lo_e << 32) | hi_e;
-            float ww = sm.ew[pp];
-            int u = t;
-            while (u > 0 && ord[u - 1] > o) {
-              ord[u] = ord[u - 1];
-              wv[u] = wv[u - 1];
-              --u;
+          if (first && nl <= kCMaxDup) {
+            keep[i] = true;
+            const int r = sm.erow[q];
+            if (nl == 1) {
+              sumr[i] = wr[i];
+            } else {
+              unsigned long long ord[kCMaxDup];
+              float wg[kCMaxDup];
+              for (int t = 0; t < nl; ++t) {
+                const int pp = lst[t];
+                const int off = lo + pp - sm.st[r];
+                const bool side = off >= sm.rdega[r];
+                const int s = side ? sm.rb[r] : sm.ra[r];
+                int xp = xr[i];
+                float wp = wr[i];
+                if (pp != q) {
+                  const long long kp = side ? sm.rkb[r] + (off - sm.rdega[r]) : sm.rka[r] + off;
+                  xp = a.col[kp];
+                  wp = a.w ? a.w[kp] : 1.0f;
+                }
+                ord[t] = edge_order(s, xp);
+                wg[t] = wp;
+              }
+              sumr[i] = group_sum(ord, wg, nl);
             }
-            ord[u] = o;
-            wv[u] = ww;
-          }
-          float sum = wv[0];
-          for (int t = 1; t < nl; ++t) sum += wv[t];
-          a.scr[k] = make_int2(D, __float_as_int(sum));
-          const int off = lo + q - sm.st[r];
-          atomicAdd(&sm.rcnt[off >= sm.rdega[r] ? 1 : 0][r], 1);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < kCTI; ++i) {
-          const int q = i * kBlock + tid;
-          if (q >= len) break;
-          if (sm.eD[q] >= 0) {
-            sm.key[sm.eslot[q]] = kEmpty;
-            sm.head[sm.eslot[q]] = -1;
           }
         }
-        __syncthreads();
-      } else {
-        int flags[kCTI];
-        int carry = 0;
+        const unsigned long long bal = __ballot(keep[i]);
+        if (lane_id() == 0) sm.wcnt[i * kWaves + wv_id] = __popcll(bal);
+        sm.erank[q] = (int)__popcll(bal & lanemask_lt());  // rank inside the wave for now
+      }
+      __syncthreads();
+      // 3: exclusive ranks in tile order: the kept counts of the (round, wave)
+      // groups are scanned across the wave's lanes, each lane takes its groups'
+      {
+        static_assert(kCTI * kWaves <= 64, "one lane per (round, wave) group");
+        const int l = lane_id();
+        const int cg = l < kCTI * kWaves ? sm.wcnt[l] : 0;
+        const int incl = wave_incl_sum<int>(cg);
+        const int excl = incl - cg;
+        const int tot = __shfl(incl, kCTI * kWaves - 1);
 #pragma unroll
         for (int i = 0; i < kCTI; ++i) {
           const int q = i * kBlock + tid;
-          int f = 0;
-          if (q < len) {
-            const int pos = lo + q;
-            const int r = row_of(sm, pos);
-            const int off = pos - sm.st[r];
-            const bool side = off >= sm.rdega[r];
-            const int s = side ? sm.rb[r] : sm.ra[r];
-            const long long k = a.rp[s] + (side ? off - sm.rdega[r] : off);
-            const int2 t = a.scr[k];
-            f = t.x >= 0 ? 1 : 0;
-            sm.eD[q] = t.x;
-            sm.ew[q] = __int_as_float(t.y);
-            sm.erow[q] = (unsigned char)r;
-          }
-          flags[i] = f;
+          sm.erank[q] += __shfl(excl, i * kWaves + wv_id);
         }
+        if (tid == 0) sm.erank[kCT] = tot;
+      }
+      __syncthreads();
+      // 4: write the kept entries at the start of their row part; part counts
 #pragma unroll
-        for (int i = 0; i < kCTI; ++i) {
-          const int q = i * kBlock + tid;
-          int tot;
-          const int e = block_excl_sum<int>(flags[i], sm.smi, tot);
-          if (q < kCT) sm.ek[q] = carry + e;
-          carry += tot;
+      for (int i = 0; i < kCTI; ++i) {
+        const int q = i * kBlock + tid;
+        if (q >= len || !keep[i]) continue;
+        const int r = sm.erow[q];
+        const int off = lo + q - sm.st[r];
+        const bool side = off >= sm.rdega[r];
+        const int ps = sm.st[r] - lo + (side ? sm.rdega[r] : 0);
+        const int prank = sm.erank[q] - sm.erank[ps];
+        a.scr[(side ? sm.rkb[r] : sm.rka[r]) + prank] = make_int2(Dr[i], __float_as_int(sumr[i]));
+      }
+      {
+        const int r = tid;
+        const int s0 = sm.st[r] - lo;
+        if (sm.rut[r] > 0 && sm.st[r] >= lo && sm.st[r] < hi) {
+          const int pb = s0 + sm.rdega[r];
+          const int pe = s0 + sm.rut[r];
+          const int rb_ = pe < len ? sm.erank[pe] : sm.erank[kCT];
+          const int ra_ = pb < len ? sm.erank[pb] : sm.erank[kCT];
+          a.cnt[sm.ra[r]] = ra_ - sm.erank[s0];
+          if (sm.rb[r] >= 0) a.cnt[sm.rb[r]] = rb_ - ra_;
         }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < kCTI; ++i) {
-          const int q = i * kBlock + tid;
-          if (q >= len || !flags[i]) continue;
-          const int r = sm.erow[q];
-          const int off = lo + q - sm.st[r];
-          const bool side = off >= sm.rdega[r];
-          const int ps = sm.st[r] + (side ? sm.rdega[r] : 0) - lo;
-          const int rank = sm.ek[q] - sm.ek[ps];
-          const long long dest = a.crp[sm.rc[r]] + (side ? a.cnt[sm.ra[r]] : 0) + rank;
-          a.ccol[dest] = sm.eD[q];
-          a.cw[dest] = sm.ew[q];
-        }
-        __syncthreads();
+      }
+      for (int i = tid; i < 2 * len; i += kBlock) {
+        sm.skey[i] = -1;
+        sm.shead[i] = -1;
+      }
+      __syncthreads();
+    }
+  }
+  if (err) atomicOr(&a.tot->err, err);
+}
+
+// (4d) Copies the kept entries of every short coarse row from the starts of
+// its two row parts to the output.
+__global__ __launch_bounds__(kBlock) void k_c_copy(CArgs a, long long per_wg) {
+  __shared__ int pre[kBlock + 1];
+  __shared__ int sca[kBlock];
+  __shared__ long long ska[kBlock], skb[kBlock], sd0[kBlock];
+  __shared__ int smi[kWaves];
+  __shared__ int lb[1];
+  if (a.tot->err) return;
+  const int tid = threadIdx.x;
+  long long vb, ve;
+  wg_vertices(a, per_wg, vb, ve, lb);
+  for (long long cb = vb; cb < ve; cb += kBlock) {
+    const long long v = cb + tid;
+    int len = 0, ca = 0;
+    long long ka = 0, kb = 0, d0 = 0;
+    if (v < ve) {
+      const RowHead h = row_head(a, v);
+      if (h.rep && !h.lng) {
+        ca = a.cnt[v];
+        len = ca + (h.m >= 0 ? a.cnt[h.m] : 0);
+        ka = h.ka;
+        kb = h.kb;
+        d0 = a.crp[h.c];
       }
     }
-    if (PASS == 0) {
-      if (v < ve && rep && !lng) {
-        a.cnt[v] = sm.rcnt[0][tid];
-        if (m >= 0) a.cnt[m] = sm.rcnt[1][tid];
-      }
+    int T;
+    const int p = block_excl_sum<int>(len, smi, T);
+    pre[tid] = p;
+    if (tid == 0) pre[kBlock] = T;
+    sca[tid] = ca;
+    ska[tid] = ka;
+    skb[tid] = kb;
+    sd0[tid] = d0;
+    __syncthreads();
+    for (int q = tid; q < T; q += kBlock) {
+      const int r = row_of(pre, q);
+      const int off = q - pre[r];
+      const long long src = off < sca[r] ? ska[r] + off : skb[r] + (off - sca[r]);
+      const int2 t = a.scr[src];
+      a.ccol[sd0[r] + off] = t.x;
+      a.cw[sd0[r] + off] = __int_as_float(t.y);
     }
     __syncthreads();
   }
-  if (err) atomicOr(&a.tot->err, err);
 }
 
 // (3a) Offsets of the long rows' entries and tables, one workgroup.
@@ -515,100 +641,169 @@ __device__ __forceinline__ long long long_row_of(const LongRow* L, long long nl,
   return lo;
 }
 
+// The long row of flat index i, searched forward from r0 (the row of the
+// chunk's first index; rows are longer than a chunk's lane stride).
+__device__ __forceinline__ long long long_row_from(const LongRow* L, long long nl, long long r0, long long i) {
+  long long r = r0;
+  while (r + 1 < nl && L[r + 1].eoff <= i) ++r;
+  return r;
+}
+
+constexpr int kLI = 4;  // long-row entries per lane per round (their loads are in flight together)
+
+// Where flat long-row index i lies: its row, fine entry and side.
+struct LongAt {
+  long long k;
+  int r, off;
+  bool side;
+};
+__device__ __forceinline__ LongAt long_at(const CArgs& a, long long nl, long long r0, long long i) {
+  LongAt t;
+  t.r = (int)long_row_from(a.lrows, nl, r0, i);
+  const LongRow& L = a.lrows[t.r];
+  t.off = (int)(i - L.eoff);
+  t.side = t.off >= L.dega;
+  t.k = t.side ? a.rp[L.b] + (t.off - L.dega) : a.rp[L.a] + t.off;
+  return t;
+}
+
 // (3b) Inserts every entry of the long rows into its row's table.
 __global__ __launch_bounds__(kBlock) void k_c_long_insert(CArgs a, long long nl, long long total) {
   unsigned err = 0;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long long)gridDim.x * kBlock) {
-    const LongRow L = a.lrows[long_row_of(a.lrows, nl, i)];
-    const int off = (int)(i - L.eoff);
-    const bool side = off >= L.dega;
-    const int s = side ? L.b : L.a;
-    const long long k = a.rp[s] + (side ? off - L.dega : off);
-    const int x = a.col[k];
-    if ((unsigned)x >= (unsigned)a.n) {
-      err |= kCErrCol;
-      continue;
+  const long long step = (long long)gridDim.x * kBlock * kLI;
+  for (long long i0 = (long long)blockIdx.x * kBlock * kLI; i0 < total; i0 += step) {
+    const long long r0 = long_row_of(a.lrows, nl, i0);
+    LongAt at[kLI];
+    int x[kLI], D[kLI];
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      const long long i = i0 + (long long)j * kBlock + threadIdx.x;
+      at[j].k = -1;
+      if (i < total) at[j] = long_at(a, nl, r0, i);
     }
-    const int D = a.cmap[x];
-    if (D == L.c) continue;
-    int2* tb = a.table + L.toff;
-    const unsigned long long mask = (1ull << L.tbits) - 1;
-    unsigned long long h = tbl_hash(D, L.tbits);
-    for (;;) {
-      const int old = atomicCAS(&tb[h].x, -1, D);
-      if (old == -1 || old == D) break;
-      h = (h + 1) & mask;
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) x[j] = at[j].k >= 0 ? a.col[at[j].k] : -1;
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      D[j] = -1;
+      if (at[j].k < 0) continue;
+      if ((unsigned)x[j] >= (unsigned)a.n)
+        err |= kCErrCol;
+      else
+        D[j] = a.cmap[x[j]];
     }
-    a.next[k] = atomicExch(&tb[h].y, (int)k);
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      if (D[j] < 0) continue;
+      const LongRow& L = a.lrows[at[j].r];
+      if (D[j] == L.c) continue;
+      int2* tb = a.table + L.toff;
+      const unsigned long long mask = (1ull << L.tbits) - 1;
+      unsigned long long h = tbl_hash(D[j], L.tbits);
+      for (;;) {
+        const int old = atomicCAS(&tb[h].x, -1, D[j]);
+        if (old == -1 || old == D[j]) break;
+        h = (h + 1) & mask;
+      }
+      a.next[at[j].k] = atomicExch(&tb[h].y, (int)at[j].k);
+    }
   }
   if (err) atomicOr(&a.tot->err, err);
 }
 
-// (3c) The first entry of every group of a long row keeps the group's sum.
+// (3c) The first entry of every group of a long row keeps the group's sum
+// (written at its own fine entry; the others write -1).
 __global__ __launch_bounds__(kBlock) void k_c_long_keep(CArgs a, long long nl, long long total) {
   unsigned err = 0;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long long)gridDim.x * kBlock) {
-    const LongRow L = a.lrows[long_row_of(a.lrows, nl, i)];
-    const int off = (int)(i - L.eoff);
-    const bool side = off >= L.dega;
-    const int s = side ? L.b : L.a;
-    const long long ka = a.rp[L.a];
-    const long long kb = L.b >= 0 ? a.rp[L.b] : 0;
-    const long long k = (side ? kb : ka) + (side ? off - L.dega : off);
-    const int x = a.col[k];
-    if ((unsigned)x >= (unsigned)a.n) {
-      a.scr[k] = make_int2(-1, 0);
-      continue;
+  const long long step = (long long)gridDim.x * kBlock * kLI;
+  for (long long i0 = (long long)blockIdx.x * kBlock * kLI; i0 < total; i0 += step) {
+    const long long r0 = long_row_of(a.lrows, nl, i0);
+    LongAt at[kLI];
+    int x[kLI], D[kLI];
+    float wself[kLI];
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      const long long i = i0 + (long long)j * kBlock + threadIdx.x;
+      at[j].k = -1;
+      if (i < total) at[j] = long_at(a, nl, r0, i);
     }
-    const int D = a.cmap[x];
-    if (D == L.c) {
-      a.scr[k] = make_int2(-1, 0);
-      continue;
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      x[j] = at[j].k >= 0 ? a.col[at[j].k] : -1;
+      wself[j] = at[j].k >= 0 && a.w ? a.w[at[j].k] : 1.0f;
     }
-    const int2* tb = a.table + L.toff;
-    const unsigned long long mask = (1ull << L.tbits) - 1;
-    unsigned long long h = tbl_hash(D, L.tbits);
-    while (tb[h].x != D) h = (h + 1) & mask;
-    // the group's entries; row order is a's part, then b's part
-    int lst[kCMaxDup + 1];
-    int nlst = 0;
-    int p = tb[h].y;
-    bool first = true;
-    while (p >= 0 && nlst <= kCMaxDup) {
-      lst[nlst++] = p;
-      const bool pa = (long long)p >= ka && (long long)p < ka + L.dega;
-      const long long pos_p = pa ? p - ka : L.dega + (p - kb);
-      first = first && pos_p >= off;
-      p = a.next[p];
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      D[j] = -1;
+      if (at[j].k >= 0 && (unsigned)x[j] < (unsigned)a.n) D[j] = a.cmap[x[j]];
+      if (D[j] >= 0 && D[j] == a.lrows[at[j].r].c) D[j] = -1;
     }
-    if (nlst > kCMaxDup) err |= kCErrDup;
-    if (!first || nlst > kCMaxDup) {
-      a.scr[k] = make_int2(-1, 0);
-      continue;
-    }
-    unsigned long long ord[kCMaxDup];
-    float wv[kCMaxDup];
-    for (int t = 0; t < nlst; ++t) {
-      const int pp = lst[t];
-      const bool pa = (long long)pp >= ka && (long long)pp < ka + L.dega;
-      const int sp = pa ? L.a : L.b;
-      const int xp = a.col[pp];
-      const unsigned lo_e = (unsigned)min(sp, xp), hi_e = (unsigned)max(sp, xp);
-      const unsigned long long o = ((unsigned long long)lo_e << 32) | hi_e;
-      const float ww = a.w ? a.w[pp] : 1.0f;
-      int u = t;
-      while (u > 0 && ord[u - 1] > o) {
-        ord[u] = ord[u - 1];
-        wv[u] = wv[u - 1];
-        --u;
+    int2 slot[kLI];
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      slot[j] = make_int2(-1, -1);
+      if (D[j] < 0) continue;
+      const LongRow& L = a.lrows[at[j].r];
+      const int2* tb = a.table + L.toff;
+      const unsigned long long mask = (1ull << L.tbits) - 1;
+      unsigned long long h = tbl_hash(D[j], L.tbits);
+      int2 t = tb[h];
+      while (t.x != D[j]) {
+        h = (h + 1) & mask;
+        t = tb[h];
       }
-      ord[u] = o;
-      wv[u] = ww;
+      slot[j] = t;
     }
-    float sum = wv[0];
-    for (int t = 1; t < nlst; ++t) sum += wv[t];
-    a.scr[k] = make_int2(D, __float_as_int(sum));
-    atomicAdd(&a.cnt[s], 1);
+    int nxt[kLI];
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) nxt[j] = D[j] >= 0 ? a.next[slot[j].y] : -1;
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      if (at[j].k < 0) continue;
+      if (D[j] < 0) {
+        a.scr[at[j].k] = make_int2(-1, 0);
+        continue;
+      }
+      const LongRow& L = a.lrows[at[j].r];
+      const long long ka = a.rp[L.a];
+      const long long kb = L.b >= 0 ? a.rp[L.b] : 0;
+      // the group's entries; row order is a's part, then b's part
+      int lst[kCMaxDup + 1];
+      int nlst = 0;
+      int p = slot[j].y;
+      int pn = nxt[j];
+      bool first = true;
+      for (;;) {
+        lst[nlst++] = p;
+        const bool pa = (long long)p >= ka && (long long)p < ka + L.dega;
+        const long long pos_p = pa ? p - ka : L.dega + (p - kb);
+        first = first && pos_p >= at[j].off;
+        if (pn < 0 || nlst > kCMaxDup) break;
+        p = pn;
+        pn = a.next[p];
+      }
+      if (nlst > kCMaxDup) err |= kCErrDup;
+      if (!first || nlst > kCMaxDup) {
+        a.scr[at[j].k] = make_int2(-1, 0);
+        continue;
+      }
+      float sum = wself[j];
+      if (nlst > 1) {
+        unsigned long long ord[kCMaxDup];
+        float wv[kCMaxDup];
+        for (int t = 0; t < nlst; ++t) {
+          const int pp = lst[t];
+          const bool pa = (long long)pp >= ka && (long long)pp < ka + L.dega;
+          const int sp = pa ? L.a : L.b;
+          const int xp = pp == at[j].k ? x[j] : a.col[pp];
+          ord[t] = edge_order(sp, xp);
+          wv[t] = pp == at[j].k ? wself[j] : (a.w ? a.w[pp] : 1.0f);
+        }
+        sum = group_sum(ord, wv, nlst);
+      }
+      a.scr[at[j].k] = make_int2(D[j], __float_as_int(sum));
+      atomicAdd(&a.cnt[at[j].side ? L.b : L.a], 1);
+    }
   }
   if (err) atomicOr(&a.tot->err, err);
 }
@@ -619,14 +814,14 @@ __device__ __forceinline__ long long coarse_deg(const CArgs& a, long long c) {
   return (long long)a.cnt[r] + (m >= 0 ? a.cnt[m] : 0);
 }
 
-// (4a) Coarse row lengths, summed per block.
+// (4a) Coarse row lengths, summed per block (coalesced).
 __global__ __launch_bounds__(kBlock) void k_c_deg_count(CArgs a, long long nc) {
   __shared__ long long sm[kWaves];
   if (a.tot->err) return;
-  const long long c0 = (long long)blockIdx.x * kCBlockV + (long long)threadIdx.x * kCV;
+  const long long base = (long long)blockIdx.x * kCBlockV;
   long long s = 0;
   for (int i = 0; i < kCV; ++i) {
-    const long long c = c0 + i;
+    const long long c = base + (long long)i * kBlock + threadIdx.x;
     if (c >= nc) break;
     s += coarse_deg(a, c);
   }
@@ -637,22 +832,21 @@ __global__ __launch_bounds__(kBlock) void k_c_deg_count(CArgs a, long long nc) {
 
 // (4c) Coarse row offsets.
 __global__ __launch_bounds__(kBlock) void k_c_deg_write(CArgs a, long long nc) {
+  __shared__ long long val[kCBlockV];
   __shared__ long long sm[kWaves];
   if (a.tot->err) return;
-  const long long c0 = (long long)blockIdx.x * kCBlockV + (long long)threadIdx.x * kCV;
-  long long s = 0;
+  const long long base = (long long)blockIdx.x * kCBlockV;
+#pragma unroll
   for (int i = 0; i < kCV; ++i) {
-    const long long c = c0 + i;
-    if (c >= nc) break;
-    s += coarse_deg(a, c);
+    const long long c = base + (long long)i * kBlock + threadIdx.x;
+    val[i * kBlock + threadIdx.x] = c < nc ? coarse_deg(a, c) : 0ll;
   }
-  long long total;
-  long long off = a.bsum[blockIdx.x] + block_excl_sum<long long>(s, sm, total);
+  __syncthreads();
+  (void)block_stage_scan(val, a.bsum[blockIdx.x], sm);
+#pragma unroll
   for (int i = 0; i < kCV; ++i) {
-    const long long c = c0 + i;
-    if (c >= nc) break;
-    a.crp[c] = off;
-    off += coarse_deg(a, c);
+    const long long c = base + (long long)i * kBlock + threadIdx.x;
+    if (c < nc) a.crp[c] = val[i * kBlock + threadIdx.x];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.crp[nc] = a.tot->nnz_c;
 }
@@ -690,7 +884,7 @@ int tile_blocks_per_cu() {
   static int cached = 0;
   if (cached) return cached;
   int nb = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_c_tiles<0>, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_c_group, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
   cached = nb;
   return nb;
 }
@@ -857,7 +1051,7 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
   if (grid > by_cost) grid = by_cost;
   if (grid < 1) grid = 1;
   const long long per_wg = (cost + grid - 1) / grid;
-  hipLaunchKernelGGL(k_c_tiles<0>, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
+  hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
   hipLaunchKernelGGL(k_c_long_prep, dim3(1), dim3(kCTopThreads), 0, s, a);
   LMC_HIP(hipGetLastError());
   LMC_HIP(hipMemcpyAsync(cs.h_tot, a.tot, sizeof(CTot), hipMemcpyDeviceToHost, s));
@@ -875,7 +1069,7 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
     a.table = (int2*)cs.table.p;
     const long long fill_grid = std::min<long long>((t1.long_slots + kBlock - 1) / kBlock, 8192);
     hipLaunchKernelGGL(k_c_fill, dim3((unsigned)fill_grid), dim3(kBlock), 0, s, a.table, t1.long_slots);
-    const long long lg = std::min<long long>((t1.long_entries + kBlock - 1) / kBlock, 16384);
+    const long long lg = std::min<long long>((t1.long_entries + kBlock * kLI - 1) / (kBlock * kLI), 16384);
     hipLaunchKernelGGL(k_c_long_insert, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
     hipLaunchKernelGGL(k_c_long_keep, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
   }
@@ -885,7 +1079,7 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
     hipLaunchKernelGGL(k_c_scan_top, dim3(1), dim3(kCTopThreads), 0, s, a.bsum, nb_c, &a.tot->nnz_c);
     hipLaunchKernelGGL(k_c_deg_write, dim3((unsigned)nb_c), dim3(kBlock), 0, s, a, nc);
   }
-  hipLaunchKernelGGL(k_c_tiles<1>, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
+  hipLaunchKernelGGL(k_c_copy, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
   if (nl > 0) {
     const long long pg = std::min<long long>(2 * nl, kCPackGrid);
     hipLaunchKernelGGL(k_c_long_pack, dim3((unsigned)pg), dim3(kBlock), 0, s, a, nl);
