@@ -73,8 +73,15 @@ typedef int32_t lm_status;
 /* flags */
 #define LM_IN_DEVICE 0x1u    /* row_ptr, col, w are device pointers */
 #define LM_OUT_DEVICE 0x2u   /* mate is a device pointer */
-#define LM_CHECK_GRAPH 0x4u  /* validate ids, self-loops, weights (and, for host
-                                inputs, symmetry and duplicates) before solving */
+#define LM_CHECK_GRAPH 0x4u  /* validate the input contract (Section 1: a simple undirected
+                                graph) before solving: offsets, ids, self-loops, finite weights,
+                                symmetry with equal weights both ways, no duplicate entries.
+                                Host inputs are checked exactly on the host. Device inputs:
+                                symmetry by comparing a 64-bit fingerprint of all entries with
+                                one of their mirrors (a violation escapes with probability
+                                about 2^-64), duplicates exactly by grouping every row's
+                                entries by neighbour on the device (device memory of the
+                                context, one extra synchronisation) */
 #define LM_PROFILE 0x8u      /* time every kernel launch with HIP events */
 #define LM_GRAPH 0x10u       /* run the whole solve as one captured HIP graph launch: set-up,
                                 a fixed number of phases that do nothing once the tail kernel
@@ -181,7 +188,9 @@ lm_status lm_match_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, in
  * loops, harnesses that forbid allocation). Same result, statistics and
  * errors as lm_match with the same flags, with these limits:
  *  - flags must include LM_IN_DEVICE | LM_OUT_DEVICE (host buffers would need
- *    staging) and may add LM_CHECK_GRAPH; any other flag gives LM_EINVAL;
+ *    staging) and may add LM_CHECK_GRAPH, which here checks everything but
+ *    duplicate entries (that check needs device memory of its own); any other
+ *    flag gives LM_EINVAL;
  *  - the working buffers come from one device array of
  *    LM_NOALLOC_SCRATCH_BYTES per GPU (held from the first lm_create on that
  *    GPU until the process ends), not from the context's pool; a graph needs

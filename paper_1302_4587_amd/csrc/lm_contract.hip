@@ -93,6 +93,8 @@ struct CArgs {
   long long* crp;
   int* ccol;
   float* cw;
+  int dup_limit;  // fine edges one coarse edge may merge (4; 1 for the duplicate check)
+  int identity;   // every vertex free, cmap the identity (the duplicate check of LM_CHECK_GRAPH)
 };
 
 __device__ __forceinline__ unsigned long long tbl_hash(int d, int bits) {
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_c_count(CArgs a) {
   for (int i = 0; i < kCV; ++i) {
     const long long v = base + (long long)i * kBlock + threadIdx.x;
     if (v >= a.n) break;
-    const int m = a.mate[v];
+    const int m = a.identity ? -1 : a.mate[v];
     if (m != -1) {
       if (m < 0 || m >= a.n || m == v)
         err |= kCErrMate;
@@ -220,14 +222,14 @@ struct RowHead {
 };
 __device__ __forceinline__ RowHead row_head(const CArgs& a, long long v) {
   RowHead h;
-  h.m = a.mate[v];
+  h.m = a.identity ? -1 : a.mate[v];
   h.rep = (h.m == -1 || v < h.m);
   h.c = 0;
   h.dega = h.ub = 0;
   h.ka = h.kb = 0;
   h.lng = false;
   if (h.rep) {
-    h.c = a.cmap[v];
+    h.c = a.identity ? (int)v : a.cmap[v];
     h.ka = a.rp[v];
     h.dega = (int)(a.rp[v + 1] - h.ka);
     h.ub = h.dega;
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
         if ((unsigned)xr[i] >= (unsigned)a.n)
           err |= kCErrCol;
         else
-          Dr[i] = a.cmap[xr[i]];
+          Dr[i] = a.identity ? xr[i] : a.cmap[xr[i]];
       }
 #pragma unroll
       for (int i = 0; i < kCTI; ++i) {
@@ -460,8 +462,8 @@ __global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
             first = first && p >= q;
             p = sm.enext[p];
           }
-          if (nl > kCMaxDup) err |= kCErrDup;
-          if (first && nl <= kCMaxDup) {
+          if (nl > a.dup_limit) err |= kCErrDup;
+          if (first && nl <= a.dup_limit) {
             keep[i] = true;
             const int r = sm.erow[q];
             if (nl == 1) {
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
 #pragma unroll
       for (int i = 0; i < kCTI; ++i) {
         const int q = i * kBlock + tid;
-        if (q >= len || !keep[i]) continue;
+        if (q >= len || !keep[i] || !a.scr) continue;
         const int r = sm.erow[q];
         const int off = lo + q - sm.st[r];
         const bool side = off >= sm.rdega[r];
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
       {
         const int r = tid;
         const int s0 = sm.st[r] - lo;
-        if (sm.rut[r] > 0 && sm.st[r] >= lo && sm.st[r] < hi) {
+        if (a.cnt && sm.rut[r] > 0 && sm.st[r] >= lo && sm.st[r] < hi) {
           const int pb = s0 + sm.rdega[r];
           const int pe = s0 + sm.rut[r];
           const int rb_ = pe < len ? sm.erank[pe] : sm.erank[kCT];
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_c_long_insert(CArgs a, long long nl,
       if ((unsigned)x[j] >= (unsigned)a.n)
         err |= kCErrCol;
       else
-        D[j] = a.cmap[x[j]];
+        D[j] = a.identity ? x[j] : a.cmap[x[j]];
     }
 #pragma unroll
     for (int j = 0; j < kLI; ++j) {
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(kBlock) void k_c_long_keep(CArgs a, long long nl, l
 #pragma unroll
     for (int j = 0; j < kLI; ++j) {
       D[j] = -1;
-      if (at[j].k >= 0 && (unsigned)x[j] < (unsigned)a.n) D[j] = a.cmap[x[j]];
+      if (at[j].k >= 0 && (unsigned)x[j] < (unsigned)a.n) D[j] = a.identity ? x[j] : a.cmap[x[j]];
       if (D[j] >= 0 && D[j] == a.lrows[at[j].r].c) D[j] = -1;
     }
     int2 slot[kLI];
@@ -761,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_c_long_keep(CArgs a, long long nl, l
     for (int j = 0; j < kLI; ++j) {
       if (at[j].k < 0) continue;
       if (D[j] < 0) {
-        a.scr[at[j].k] = make_int2(-1, 0);
+        if (a.scr) a.scr[at[j].k] = make_int2(-1, 0);
         continue;
       }
       const LongRow& L = a.lrows[at[j].r];
@@ -782,8 +784,9 @@ __global__ __launch_bounds__(kBlock) void k_c_long_keep(CArgs a, long long nl, l
         p = pn;
         pn = a.next[p];
       }
-      if (nlst > kCMaxDup) err |= kCErrDup;
-      if (!first || nlst > kCMaxDup) {
+      if (nlst > a.dup_limit) err |= kCErrDup;
+      if (!a.scr) continue;
+      if (!first || nlst > a.dup_limit) {
         a.scr[at[j].k] = make_int2(-1, 0);
         continue;
       }
@@ -915,6 +918,69 @@ void contract_release(Solver& S) {
 Solver& solver_of(lm_ctx* c);
 std::mutex& mutex_of(lm_ctx* c);
 
+// Duplicate entries within rows, for LM_CHECK_GRAPH on device input: the
+// grouping kernels of the contraction with every vertex free and a group
+// limit of one entry (any neighbour seen twice in a row is an error). Also
+// checks row_ptr. Synchronises the stream.
+lm_status check_row_duplicates(Solver& S, int64_t n, int64_t nnz, const long long* rp, const int* col,
+                               hipStream_t s) {
+  if (n == 0) return LM_OK;
+  if (!S.contract) S.contract = new ContractState();
+  ContractState& cs = *S.contract;
+  if (!cs.h_tot && hipHostMalloc((void**)&cs.h_tot, sizeof(CTot), hipHostMallocDefault) != hipSuccess)
+    return LM_ENOMEM;
+  Pool& P = S.pool;
+  const long long nb_v = (n + kCBlockV - 1) / kCBlockV;
+  const long long lrow_cap = nnz / (kCS + 1) + 1;
+  lm_status rs;
+  if ((rs = P.reserve(cs.bsum, a256(sizeof(long long) * (size_t)(nb_v + 1)))) != LM_OK) return rs;
+  if ((rs = P.reserve(cs.tot, a256(sizeof(CTot)))) != LM_OK) return rs;
+  if ((rs = P.reserve(cs.lrows, a256(sizeof(LongRow) * (size_t)lrow_cap))) != LM_OK) return rs;
+  CArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nnz = nnz;
+  a.rp = rp;
+  a.col = col;
+  a.bsum = (long long*)cs.bsum.p;
+  a.tot = (CTot*)cs.tot.p;
+  a.lrows = (LongRow*)cs.lrows.p;
+  a.lrow_cap = lrow_cap;
+  a.dup_limit = 1;
+  a.identity = 1;
+  if (hipMemsetAsync(a.tot, 0, sizeof(CTot), s) != hipSuccess) return LM_EDEVICE;
+  hipLaunchKernelGGL(k_c_count, dim3((unsigned)nb_v), dim3(kBlock), 0, s, a);
+  const long long cost = nnz + (long long)kCCost * n;
+  long long grid = (long long)S.num_cus * tile_blocks_per_cu();
+  grid = std::max<long long>(1, std::min<long long>(grid, (cost + 2 * kCT - 1) / (2 * kCT)));
+  hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, (cost + grid - 1) / grid);
+  hipLaunchKernelGGL(k_c_long_prep, dim3(1), dim3(kCTopThreads), 0, s, a);
+  if (hipGetLastError() != hipSuccess) return LM_EDEVICE;
+  if (hipMemcpyAsync(cs.h_tot, a.tot, sizeof(CTot), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LM_EDEVICE;
+  const CTot t1 = *cs.h_tot;
+  if (t1.err) return LM_EGRAPH;
+  if (t1.nlong > 0) {
+    if (t1.nlong > lrow_cap) return LM_EDEVICE;
+    if ((rs = P.reserve(cs.next, a256(sizeof(int) * (size_t)nnz))) != LM_OK) return rs;
+    if ((rs = P.reserve(cs.table, a256(sizeof(int2) * (size_t)t1.long_slots))) != LM_OK) return rs;
+    a.next = (int*)cs.next.p;
+    a.table = (int2*)cs.table.p;
+    const long long fill_grid = std::min<long long>((t1.long_slots + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(k_c_fill, dim3((unsigned)fill_grid), dim3(kBlock), 0, s, a.table, t1.long_slots);
+    const long long lg = std::min<long long>((t1.long_entries + kBlock * kLI - 1) / (kBlock * kLI), 16384);
+    hipLaunchKernelGGL(k_c_long_insert, dim3((unsigned)lg), dim3(kBlock), 0, s, a, t1.nlong, t1.long_entries);
+    hipLaunchKernelGGL(k_c_long_keep, dim3((unsigned)lg), dim3(kBlock), 0, s, a, t1.nlong, t1.long_entries);
+    if (hipGetLastError() != hipSuccess) return LM_EDEVICE;
+    if (hipMemcpyAsync(cs.h_tot, a.tot, sizeof(CTot), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return LM_EDEVICE;
+    if (cs.h_tot->err) return LM_EGRAPH;
+  }
+  return LM_OK;
+}
+
 }  // namespace lm
 
 using namespace lm;
@@ -1039,6 +1105,8 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
   a.scr = (int2*)cs.scr.p;
   a.lrows = (LongRow*)cs.lrows.p;
   a.lrow_cap = lrow_cap;
+  a.dup_limit = kCMaxDup;
+  a.identity = 0;
 
   LMC_HIP(hipEventRecord(S.e0, s));
   LMC_HIP(hipMemsetAsync(a.tot, 0, sizeof(CTot), s));

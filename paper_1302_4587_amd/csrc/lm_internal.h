@@ -91,6 +91,7 @@ struct Totals {
   unsigned long long matched;
   int t;    // current phase (1-based): read by the mutual check, advanced by the plan kernel
   int tail_from;  // guarded phases: the live set R_t the tail kernel takes over (0 = none yet)
+  unsigned long long fp[2];  // LM_CHECK_GRAPH: fingerprints of the entries and of their mirrors
 };
 
 // What the host loop needs after each plan, written by the plan kernel into
@@ -124,6 +125,7 @@ enum : unsigned {
   kErrWeight = 16u,
   kErrInternal = 32u,
   kErrStall = 64u,  // a phase removed nothing: the input is not symmetric
+  kErrAsym = 128u,  // LM_CHECK_GRAPH: the entries and their mirrors differ (fingerprints)
 };
 
 // Inputs common to the phase kernels.

@@ -49,6 +49,8 @@ __global__ void k_zero(Ctl* ctl, int nctl, Totals* totals, TailCtl* tc) {
     totals->matched = 0;
     totals->t = 1;
     totals->tail_from = 0;
+    totals->fp[0] = 0;
+    totals->fp[1] = 0;
   }
 }
 
@@ -62,37 +64,83 @@ __global__ void k_add_i64(long long* p, long long n, long long delta) {
     p[i] += delta;
 }
 
-// Optional input check: ids in range, no self-loops, finite weights.
+// Fingerprint term of the entry (x, y) with weight bits wb of graph g: two
+// rounds of the SplitMix64 output function. -0 and +0 give the same term.
+__device__ __forceinline__ unsigned long long fp_term(long long g, long long x, long long y, unsigned wb) {
+  if (wb == 0x80000000u) wb = 0u;
+  const unsigned long long h = mix64((((unsigned long long)(unsigned)x << 32) | (unsigned)y) + 0x632BE59BD9B4E019ull);
+  return mix64(h ^ (((unsigned long long)wb << 32) | (unsigned long long)(unsigned)g));
+}
+
+// Optional input check: ids in range, no self-loops, finite weights, and the
+// symmetry of the entries with equal weights both ways: the sum (mod 2^64) of
+// a hash of every entry (v, u, w) must equal the sum over the mirrors (u, v,
+// w); the two multisets then agree except with probability about 2^-64.
+// Duplicate entries are found by check_row_duplicates.
 __global__ __launch_bounds__(kBlock) void k_check(CheckArgs a) {
+  constexpr long long kLongRow = 64;  // rows longer than this are walked by the whole wave
   unsigned err = 0;
-  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < a.n; v += (long long)gridDim.x * kBlock) {
-    long long base = 0, lim = a.n;
-    if (a.graphs > 1) {
-      int lo = 0, hi = a.graphs - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (a.vtx_off[mid] <= v) lo = mid;
-        else hi = mid - 1;
-      }
-      base = a.vtx_off[lo];
-      lim = a.vtx_off[lo + 1] - base;
+  unsigned long long f0 = 0, f1 = 0;
+  auto entry = [&](long long k, long long vl, long long lim, long long gi) {
+    const int u = a.col[k];
+    if (u < 0 || u >= lim) err |= kErrColRange;
+    if (u == vl) err |= kErrSelfLoop;
+    unsigned wb = 0x3f800000u;
+    if (a.w) {
+      const float x = a.w[k];
+      if (!(x == x) || x == __int_as_float(0x7f800000) || x == __int_as_float(0xff800000)) err |= kErrWeight;
+      wb = __float_as_uint(x);
     }
-    const long long b = a.row_ptr[v], e = a.row_ptr[v + 1];
-    if (b < 0 || e > a.nnz || e < b) {
-      err |= kErrRowPtr;
-      continue;
-    }
-    for (long long k = b; k < e; ++k) {
-      const int u = a.col[k];
-      if (u < 0 || u >= lim) err |= kErrColRange;
-      if (u == v - base) err |= kErrSelfLoop;
-      if (a.w) {
-        const float x = a.w[k];
-        if (!(x == x) || x == __int_as_float(0x7f800000) || x == __int_as_float(0xff800000)) err |= kErrWeight;
+    f0 += fp_term(gi, vl, u, wb);
+    f1 += fp_term(gi, u, vl, wb);
+  };
+  const long long stride = (long long)gridDim.x * kBlock;
+  const long long vend = ((a.n + stride - 1) / stride) * stride;  // every lane of a wave runs the same rounds
+  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < vend; v += stride) {
+    long long base = 0, lim = a.n, gi = 0, b = 0, e = 0;
+    if (v < a.n) {
+      if (a.graphs > 1) {
+        int lo = 0, hi = a.graphs - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (a.vtx_off[mid] <= v) lo = mid;
+          else hi = mid - 1;
+        }
+        base = a.vtx_off[lo];
+        lim = a.vtx_off[lo + 1] - base;
+        gi = lo;
       }
+      b = a.row_ptr[v];
+      e = a.row_ptr[v + 1];
+      if (b < 0 || e > a.nnz || e < b) {
+        err |= kErrRowPtr;
+        b = e = 0;
+      }
+    }
+    const bool lng = e - b > kLongRow;
+    if (!lng)
+      for (long long k = b; k < e; ++k) entry(k, v - base, lim, gi);
+    // long rows: the wave walks each one together
+    unsigned long long m = __ballot(lng);
+    while (m) {
+      const int l = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const long long vb = __shfl(b, l), ve = __shfl(e, l), vl = __shfl(v - base, l), lm = __shfl(lim, l),
+                      g = __shfl(gi, l);
+      for (long long k = vb + lane_id(); k < ve; k += 64) entry(k, vl, lm, g);
     }
   }
+  f0 = wave_incl_sum_u64(f0);
+  f1 = wave_incl_sum_u64(f1);
+  if (lane_id() == 63) {
+    atomicAdd(&a.totals->fp[0], f0);
+    atomicAdd(&a.totals->fp[1], f1);
+  }
   if (err) atomicOr(&a.totals->err, err);
+}
+
+__global__ void k_check_fp(Totals* t) {
+  if (threadIdx.x == 0 && t->fp[0] != t->fp[1]) atomicOr(&t->err, (unsigned)kErrAsym);
 }
 
 // ---------------------------------------------------------------- init
@@ -1442,6 +1490,7 @@ hipError_t launch_add_i64(long long* p, long long n, long long delta, hipStream_
 }
 hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_check, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_check_fp, dim3(1), dim3(64), 0, s, a.totals);
   return hipGetLastError();
 }
 // With ev = {start, stop} the launch goes through hipExtLaunchKernelGGL and

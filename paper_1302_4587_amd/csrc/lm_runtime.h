@@ -138,6 +138,10 @@ hipError_t launch_weight_sum(const long long* row_ptr, const int* col, const flo
 const char* status_text(lm_status st);
 // Frees the contraction's buffers (at context shutdown).
 void contract_release(Solver& S);
+// LM_CHECK_GRAPH on device input: offsets and duplicate entries within rows
+// (LM_EGRAPH), with the contraction's grouping kernels. Synchronises s.
+lm_status check_row_duplicates(Solver& S, int64_t n, int64_t nnz, const long long* rp, const int* col,
+                               hipStream_t s);
 // Looks up this device's copy of the allocation-free solve's scratch array
 // (lm_match_noalloc); called once per device with that device current.
 lm_status noalloc_setup(int dev);

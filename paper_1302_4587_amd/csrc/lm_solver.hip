@@ -662,7 +662,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
   const unsigned err = tot.err;
   if (err) {
     if (err & kErrWeight) return LM_EWEIGHT;
-    if (err & (kErrRowPtr | kErrColRange | kErrSelfLoop | kErrStall)) return LM_EGRAPH;
+    if (err & (kErrRowPtr | kErrColRange | kErrSelfLoop | kErrStall | kErrAsym)) return LM_EGRAPH;
     if (err & kErrDegree) return LM_ETOOBIG;
     return LM_EDEVICE;
   }
@@ -978,6 +978,10 @@ static lm_status solve_common(lm_ctx* c, int64_t N, int64_t nnz, int64_t G, cons
   lm_stats local;
   std::memset(&local, 0, sizeof(local));
   lm_stats* sp = st ? st : &local;
+  if (in_dev && (flags & LM_CHECK_GRAPH)) {  // host inputs were checked on the host
+    rs = check_row_duplicates(S, N, nnz, p.row_ptr, p.col, s);
+    if (rs != LM_OK) return rs;
+  }
   rs = S.run(p, S.pool_work(), s, flags, sp);
   if (rs != LM_OK) return rs;
   if (flags & LM_ASYNC) return LM_OK;  // enqueued; the result lands in order on the stream
