@@ -91,22 +91,54 @@ def test_batch_per_graph_seeds_and_host_inputs(ctx, torch_dev):
     assert np.array_equal(np.asarray(alone), ref_mate[a:e])
 
 
-def test_batch_full_size_sampled(ctx, torch_dev):
+def _oracle_parallel(jobs, threads=16):
+    """Runs oracle.local_max_graph(g, seed) for every (g, seed) on a thread
+    pool (the C oracle releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda js: oracle.local_max_graph(js[0], js[1]), jobs))
+
+
+def test_batch_full_size_all_graphs(ctx, torch_dev):
     """The bench's batch (4096 graphs, n log-uniform in [2^8, 2^16], average
-    degree U[4, 32]); 256 sampled graphs against the oracle alone."""
-    print("case: batch of 4096 ER graphs (full size), 256 sampled", flush=True)
+    degree U[4, 32]): every graph against the oracle solving it alone, mate[]
+    and phase count."""
+    print("case: batch of 4096 ER graphs (full size), every graph", flush=True)
     b = lmgen.er_batch(4096, 1)
     rp, col, w = _dev(torch_dev, b.row_ptr, b.col, b.w)
     mate, st, gph = ctx.match_batch(b.vtx_off, rp, col, w, seed0=1)
     got = mate.cpu().numpy()
     del rp, col, w
-    idx = np.random.default_rng(7).choice(b.graphs, 256, replace=False)
-    for k in sorted(idx):
-        a, e, g = _graph_slice(b, k)
-        ref_mate, ref_log = oracle.local_max_graph(g, 1)
-        assert np.array_equal(got[a:e], ref_mate), f"graph {k} differs"
-        assert gph[k] == len(ref_log), f"graph {k}: phases {gph[k]} vs {len(ref_log)}"
+    slices = [_graph_slice(b, k) for k in range(b.graphs)]
+    refs = _oracle_parallel([(g, 1) for _, _, g in slices])
+    bad = [k for k, ((a, e, _), (rm, rl)) in enumerate(zip(slices, refs))
+           if not np.array_equal(got[a:e], rm) or gph[k] != len(rl)]
+    assert not bad, f"{len(bad)} of {b.graphs} graphs differ, first {bad[:5]}"
     assert st.phases == int(gph.max())
+
+
+def test_server_request_sizes_up_to_2_22(ctx, torch_dev):
+    """Requests of the serving workload's full size range, n log-uniform in
+    [2^10, 2^22] with the largest size of both kinds included, RGG and R-MAT
+    half and half, several resident at once: every result equals the
+    oracle."""
+    import paper_1302_4587_amd as lm
+    rng = np.random.default_rng(23)
+    sizes = [("rgg", 1 << 22), ("rmat", 1 << 22)]
+    for _ in range(14):
+        sizes.append(("rgg" if rng.random() < 0.5 else "rmat", int(round(2.0 ** rng.uniform(10.0, 22.0)))))
+    reqs = [(lmgen.serving_graph(kind, n, seed=i + 1), int(rng.integers(0, 2**63))) for i, (kind, n) in
+            enumerate(sizes)]
+    print(f"case: server, {len(reqs)} requests up to n=2^22, nnz total {sum(g.nnz for g, _ in reqs)}", flush=True)
+    with lm.Server(ctx, hbm_budget_bytes=64 << 30, max_resident=8, mode=lm.LM_SERVE_BATCHED) as srv:
+        tickets = [srv.submit(g.row_ptr, g.col, g.w, seed=s) for g, s in reqs]
+        results = [srv.wait(t, 120000) for t in tickets]
+    refs = _oracle_parallel(reqs)
+    for i, ((g, s), r, (rm, rl)) in enumerate(zip(reqs, results, refs)):
+        assert r is not None, f"request {i} not done"
+        mate, info = r
+        assert np.array_equal(mate, rm), f"request {i} (n={g.n}) differs from the oracle"
+        assert info["phases"] == len(rl)
 
 
 def _request_mix(count, seed):
