@@ -320,9 +320,9 @@ def main():
                     help="run each solve as one captured HIP graph (LM_GRAPH)")
     ap.add_argument("--serve", action="store_true",
                     help="also run the serving trace: continuous-batching server vs FIFO (extra minutes)")
-    ap.add_argument("--serve-rates", type=str, default="50,150,300",
-                    help="Poisson arrival rates (requests/s) for --serve")
-    ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--serve-fractions", type=str, default="0.1,0.3,0.6,0.9,1.2",
+                    help="Poisson arrival rates for --serve, as fractions of the measured saturation rate")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--weight-array", action="store_true",
                     help="rmat: pass the all-ones weight array instead of no array (unweighted solve)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -393,8 +393,7 @@ def main():
             cpu[name] = cpu_oracle(graphs[name], args.seed, mates[name], 1 if name == "rmat" else 3)
     serve = None
     if args.serve:
-        serve = bench_serve(ctx, [float(x) for x in args.serve_rates.split(",") if x],
-                            args.serve_requests)
+        serve = bench_serve(ctx, args.serve_requests, [float(x) for x in args.serve_fractions.split(",") if x])
 
     head = "rmat" if "rmat" in results else "rgg"
     h = results[head]
@@ -515,70 +514,92 @@ def bench_batch(ctx, dev, replays, with_cpu):
     return out
 
 
-def bench_serve(ctx, rates, requests, pool=48, seed=1):
+def bench_serve(ctx, requests, fractions, pool=48, seed=1):
     """Serving trace: Poisson arrivals of host graphs (50/50 RGG avg degree 10
     and R-MAT edge factor 16, uniform weights, n log-uniform in [2^10, 2^22];
     a pool of `pool` pre-generated graphs is cycled, generation is not timed),
-    64 GB admission budget. The continuous-batching server and the FIFO
-    server (one lm_match per request) see the same trace; latency is submit
-    to result on the host, throughput is input edges over the makespan."""
+    64 GB admission budget. The saturation rate is the batched server's
+    throughput with every request submitted at once; the rates swept are the
+    given fractions of it. The continuous-batching server and the FIFO server
+    (one lm_match per request) see the same trace at each rate; latency is
+    submit to result on the host, split into the submit call (pinned copy),
+    queue (until admitted), device and copy back; throughput is input edges
+    over the makespan. Every result is compared with the oracle."""
     import threading
+    from concurrent.futures import ThreadPoolExecutor
 
     import lmgen
+    import oracle  # test infrastructure: results of the pool graphs, checked outside the timed loop
     import paper_1302_4587_amd as lm
 
     t0 = time.time()
     shapes = lmgen.serving_trace(pool, 1.0, seed)
     graphs = [lmgen.serving_graph(k, n, seed) for _, k, n in shapes]
-    print(f"bench: serving pool of {pool} graphs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    refs = {}
-    out = {"pool_graphs": pool, "requests_per_point": requests, "budget_gb": 64,
-           "pool_mean_edges": round(float(np.mean([g.nnz // 2 for g in graphs])), 1), "points": []}
-    for rate in rates:
-        arr = [a for a, _, _ in lmgen.serving_trace(requests, rate, seed + 1)]
-        point = {"rate_per_s": rate}
-        for name, mode in (("batched", lm.LM_SERVE_BATCHED), ("fifo", lm.LM_SERVE_FIFO)):
-            tickets = [None] * requests
-            with lm.Server(ctx, hbm_budget_bytes=64 << 30, max_resident=256, mode=mode) as srv:
-                sub_s = []
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        refs = list(ex.map(lambda g: oracle.local_max_graph(g, 1)[0], graphs))
+    print(f"bench: serving pool of {pool} graphs and their oracle results in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
 
-                def submitter(part, parts):
-                    for i in range(part, requests, parts):
-                        dt = arr[i] - (time.perf_counter() - t_start)
-                        if dt > 0:
-                            time.sleep(dt)
-                        g = graphs[i % pool]
-                        t_sub = time.perf_counter()
-                        tickets[i] = srv.submit(g.row_ptr, g.col, g.w, seed=1)
-                        sub_s.append(time.perf_counter() - t_sub)
-
-                t_start = time.perf_counter()
-                ths = [threading.Thread(target=submitter, args=(p, 4)) for p in range(4)]
-                for th in ths:
-                    th.start()
-                lat, qms, edges, bad = [], [], 0, 0
-                for i in range(requests):
-                    while tickets[i] is None:
-                        time.sleep(0.0002)
-                    mate, info = srv.wait(tickets[i], -1)
-                    lat.append(info["latency_ms"])
-                    qms.append(info["queue_ms"])
+    def run_point(mode, arr):
+        count = len(arr)
+        tickets = [None] * count
+        sub_s = [0.0] * count
+        with lm.Server(ctx, hbm_budget_bytes=64 << 30, max_resident=256, mode=mode) as srv:
+            def submitter(part, parts):
+                for i in range(part, count, parts):
+                    dt = arr[i] - (time.perf_counter() - t_start)
+                    if dt > 0:
+                        time.sleep(dt)
                     g = graphs[i % pool]
-                    edges += g.nnz // 2
-                    k = i % pool
-                    if k not in refs:
-                        refs[k] = mate.copy()
-                    elif not np.array_equal(refs[k], mate):
-                        bad += 1
-                makespan = time.perf_counter() - t_start
-                for th in ths:
-                    th.join()
-            point[name] = {"p50_ms": round(_percentile(lat, 50), 3), "p99_ms": round(_percentile(lat, 99), 3),
-                           "queue_p50_ms": round(_percentile(qms, 50), 3), "queue_p99_ms": round(_percentile(qms, 99), 3),
-                           "submit_ms_mean": round(1e3 * sum(sub_s) / max(len(sub_s), 1), 3),
-                           "edges_per_s": round(edges / makespan, 1), "requests_per_s": round(requests / makespan, 2),
-                           "mismatches": bad}
-            print(f"bench: serve rate={rate} {name}: {point[name]}", file=sys.stderr, flush=True)
+                    t_sub = time.perf_counter()
+                    tickets[i] = srv.submit(g.row_ptr, g.col, g.w, seed=1)
+                    sub_s[i] = time.perf_counter() - t_sub
+
+            t_start = time.perf_counter()
+            ths = [threading.Thread(target=submitter, args=(p, 4)) for p in range(4)]
+            for th in ths:
+                th.start()
+            lat, qms, dms, cms, edges, bad = [], [], [], [], 0, 0
+            for i in range(count):
+                while tickets[i] is None:
+                    time.sleep(0.0002)
+                mate, info = srv.wait(tickets[i], -1)
+                lat.append(info["latency_ms"])
+                qms.append(info["queue_ms"])
+                dms.append(info["device_ms"])
+                cms.append(info["copy_back_ms"])
+                edges += graphs[i % pool].nnz // 2
+                if not np.array_equal(refs[i % pool], mate):
+                    bad += 1
+            makespan = time.perf_counter() - t_start
+            for th in ths:
+                th.join()
+        sub_ms = [1e3 * x for x in sub_s]
+        q = lambda xs, p: round(_percentile(xs, p), 3)
+        return {"p50_ms": q(lat, 50), "p99_ms": q(lat, 99),
+                "split_p50_ms": {"submit": q(sub_ms, 50), "queue": q(qms, 50), "device": q(dms, 50),
+                                 "copy_back": q(cms, 50)},
+                "split_p99_ms": {"submit": q(sub_ms, 99), "queue": q(qms, 99), "device": q(dms, 99),
+                                 "copy_back": q(cms, 99)},
+                "edges_per_s": round(edges / makespan, 1), "requests_per_s": round(count / makespan, 2),
+                "mismatches_vs_oracle": bad}
+
+    nsat = min(requests, 400)
+    sat = {}
+    for name, mode in (("batched", lm.LM_SERVE_BATCHED), ("fifo", lm.LM_SERVE_FIFO)):
+        sat[name] = run_point(mode, [0.0] * nsat)
+        print(f"bench: serve saturation {name}: {sat[name]}", file=sys.stderr, flush=True)
+    sat_rate = sat["batched"]["requests_per_s"]
+    out = {"pool_graphs": pool, "requests_per_point": requests, "budget_gb": 64,
+           "pool_mean_edges": round(float(np.mean([g.nnz // 2 for g in graphs])), 1),
+           "saturation": {"requests": nsat, **sat}, "points": []}
+    for f in fractions:
+        rate = f * sat_rate
+        arr = [a for a, _, _ in lmgen.serving_trace(requests, rate, seed + 1)]
+        point = {"fraction_of_saturation": f, "rate_per_s": round(rate, 2)}
+        for name, mode in (("batched", lm.LM_SERVE_BATCHED), ("fifo", lm.LM_SERVE_FIFO)):
+            point[name] = run_point(mode, arr)
+            print(f"bench: serve rate={rate:.1f} {name}: {point[name]}", file=sys.stderr, flush=True)
         out["points"].append(point)
     return out
 

@@ -306,8 +306,12 @@ typedef struct {
 typedef struct {
   int32_t phases;           /* phases the request took */
   int64_t matched_edges;
-  double submit_to_admit_ms;/* time in the queue */
+  double submit_to_admit_ms;/* time in the queue (batched: until its host-to-device copy landed
+                               and it joined the resident graphs) */
   double submit_to_done_ms; /* latency until the result was on the host */
+  double admit_to_solved_ms;/* on the device: admission until its last phase was seen done
+                               (FIFO: the whole lm_match, copies included) */
+  double solved_to_done_ms; /* copying mate back to the host (FIFO: 0) */
 } lm_request_stats;
 
 /* Creates a server with its own scheduler thread on ctx's device. The

@@ -358,7 +358,8 @@ class Server:
         check(r, "lm_server result")
         self._n.pop(ticket, None)
         return mate[:n], {"phases": st.phases, "matched_edges": st.matched_edges,
-                          "queue_ms": st.submit_to_admit_ms, "latency_ms": st.submit_to_done_ms}
+                          "queue_ms": st.submit_to_admit_ms, "latency_ms": st.submit_to_done_ms,
+                          "device_ms": st.admit_to_solved_ms, "copy_back_ms": st.solved_to_done_ms}
 
     def poll(self, ticket: int):
         return self._result(self._lib.lm_server_poll, ticket)

@@ -92,7 +92,8 @@ class ServerOpts(ctypes.Structure):
 
 class RequestStats(ctypes.Structure):
     _fields_ = [("phases", ctypes.c_int32), ("matched_edges", ctypes.c_int64),
-                ("submit_to_admit_ms", ctypes.c_double), ("submit_to_done_ms", ctypes.c_double)]
+                ("submit_to_admit_ms", ctypes.c_double), ("submit_to_done_ms", ctypes.c_double),
+                ("admit_to_solved_ms", ctypes.c_double), ("solved_to_done_ms", ctypes.c_double)]
 
 
 _lib = None

@@ -506,6 +506,7 @@ lm_status BatchedState::sync_and_retire() {
   for (int sl = 0; sl < s_cap; ++sl) {
     std::shared_ptr<Request> r = slot_req[(size_t)sl];
     if (!r || h_gphase[sl] >= t) continue;  // still has a live row in R_t
+    r->t_solved = Clock::now();
     r->mate.resize((size_t)r->n);
     lm_status st = LM_OK;
     if (r->n > 0 &&

@@ -87,6 +87,7 @@ void ServerCore::finish(const std::shared_ptr<Request>& r, lm_status st) {
   std::lock_guard<std::mutex> lk(mu);
   r->status = st;
   r->t_done = Clock::now();
+  if (r->t_solved.time_since_epoch().count() == 0) r->t_solved = r->t_done;  // FIFO: solved with its copies
   r->done = true;
   running.erase(r->ticket);
   finished[r->ticket] = r;
@@ -388,6 +389,8 @@ static lm_status take_result(ServerCore& S, uint64_t ticket, int32_t* mate, lm_r
     st->matched_edges = r->matched;
     st->submit_to_admit_ms = ms_between(r->t_submit, r->t_admit);
     st->submit_to_done_ms = ms_between(r->t_submit, r->t_done);
+    st->admit_to_solved_ms = ms_between(r->t_admit, r->t_solved);
+    st->solved_to_done_ms = ms_between(r->t_solved, r->t_done);
   }
   return LM_OK;
 }

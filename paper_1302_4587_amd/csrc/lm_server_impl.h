@@ -46,7 +46,7 @@ struct Request {
   int64_t matched = 0;
   lm_status status = LM_OK;
   bool done = false;
-  std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+  std::chrono::steady_clock::time_point t_submit, t_admit, t_solved, t_done;
   // batched mode: placement on the device
   int slot = -1;        // graph index in the resident tables
   int64_t vbase = 0;    // first vertex of the request in the server's vertex space
