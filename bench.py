@@ -458,12 +458,26 @@ def bench_batch(ctx, dev, replays, with_cpu):
     mate = torch.empty(b.n_total, dtype=torch.int32, device=dev)
     _, st, gph = ctx.match_batch(vo, rp, col, w, mate=mate)
     torch.cuda.synchronize()
-    lat = []
-    for _ in range(replays):
-        t = time.perf_counter()
-        ctx.match_batch(vo, rp, col, w, mate=mate, want_graph_phases=False)
-        lat.append((time.perf_counter() - t) * 1e3)
+
+    def replay():
+        ls = []
+        for _ in range(replays):
+            t = time.perf_counter()
+            ctx.match_batch(vo, rp, col, w, mate=mate, want_graph_phases=False)
+            ls.append((time.perf_counter() - t) * 1e3)
+        return ls
+
+    lat_default = replay()
+    # the autotuner (range size, grid, queued phases, the kernels' long-piece
+    # threshold, the tail hand-over) picks the tuning the timed replays use
+    base = ctx.tuning()
+    t = time.perf_counter()
+    tuned = ctx.autotune_batch(vo, rp, col, w)
+    tune_s = time.perf_counter() - t
+    ctx.match_batch(vo, rp, col, w, mate=mate, want_graph_phases=False)
+    lat = replay()
     got = mate.cpu().numpy()
+    ctx.set_tuning(**base)
     # one graph per launch over the same graphs: the row offsets of every graph
     # rebased to 0 once, outside the timed loop
     rps = []
@@ -482,6 +496,9 @@ def bench_batch(ctx, dev, replays, with_cpu):
            "graphs": b.graphs, "n_total": b.n_total, "m_total": b.nnz // 2, "phases": st.phases,
            "replays": replays,
            "batched_ms": {"p50": round(_percentile(lat, 50), 3), "p99": round(_percentile(lat, 99), 3)},
+           "tuning": tuned, "autotune_s": round(tune_s, 2),
+           "batched_ms_default_tuning": {"p50": round(_percentile(lat_default, 50), 3),
+                                         "p99": round(_percentile(lat_default, 99), 3), "tuning": base},
            "batched_edges_per_s": round((b.nnz // 2) / (_percentile(lat, 50) / 1e3), 1),
            "one_graph_per_launch_ms": round(single_ms, 3),
            "one_graph_per_launch_edges_per_s": round((b.nnz // 2) / (single_ms / 1e3), 1)}

@@ -227,7 +227,9 @@ lm_status lm_get_tuning(lm_ctx* ctx, lm_tuning* out);
 lm_status lm_set_tuning(lm_ctx* ctx, const lm_tuning* t);
 
 /* Runs the autotuner: times candidate tunings on the given batch and keeps
- * the fastest in the context. If cache_path is not NULL, results are read
+ * the fastest in the context: block_entries x grid_per_cu x phases_per_sync,
+ * then tail_entries, each solve timed in the mode flags name (LM_GRAPH:
+ * captured launches). If cache_path is not NULL, results are read
  * from and appended to that JSON-lines file, keyed by device name and size
  * class. The chosen tuning is returned in out (may be NULL). */
 lm_status lm_autotune_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, int64_t nnz,

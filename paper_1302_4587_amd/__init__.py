@@ -309,13 +309,15 @@ class Context:
                                        gph.ctypes.data if gph is not None else None), "lm_match_batch")
         return mate, _stats_out(st, logbuf, weight_sum), gph
 
-    def autotune_batch(self, vtx_off, row_ptr, col, w, cache_path=None) -> dict:
+    def autotune_batch(self, vtx_off, row_ptr, col, w, cache_path=None, hip_graph=True) -> dict:
+        """lm_autotune_batch: keeps the fastest tuning for this batch in the
+        context (timed as captured launches unless hip_graph=False)."""
         vo = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
         rp, d0, k0 = _ptr(row_ptr, np.int64)
         cp, d1, k1 = _ptr(col, np.int32)
         wp, d2, k2 = _ptr(w, np.float32, d0)
         t = _lib.Tuning()
-        flags = LM_IN_DEVICE if d0 else 0
+        flags = (LM_IN_DEVICE if d0 else 0) | (LM_GRAPH if hip_graph else 0)
         check(self._lib.lm_autotune_batch(self._h, len(vo) - 1, vo.ctypes.data, int(col.shape[0]), rp, cp, wp, flags,
                                           cache_path.encode() if cache_path else None, ctypes.byref(t)),
               "lm_autotune_batch")

@@ -462,6 +462,8 @@ static bool cache_lookup(const char* path, const std::string& dev, const std::st
       t->block_entries = sm;
       t->grid_per_cu = gp;
       t->phases_per_sync = pp;
+      const char* te = std::strstr(line.c_str(), "\"tail_entries\": ");
+      if (te && std::atoi(te + 16) >= 0) t->tail_entries = std::atoi(te + 16);
       found = true;  // the last matching line wins
     }
   }
@@ -483,37 +485,49 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
     if (out) *out = best;
     return LM_OK;
   }
-  const uint32_t fl = flags & (LM_IN_DEVICE);
+  // the solves are timed in the mode the caller will use (LM_GRAPH: one captured launch)
+  const uint32_t fl = flags & (LM_IN_DEVICE | LM_GRAPH);
   int32_t* mate = nullptr;
   if (hipMalloc(&mate, (size_t)std::max<int64_t>(N, 1) * 4) != hipSuccess) return LM_ENOMEM;
   const lm_tuning saved = sv.tun;
   double best_ms = 1e300;
   lm_status rs = LM_OK;
-  const int bes[] = {2048, 8192, 32768};
-  for (int sm : bes) {
-    for (int gp = 1; gp <= std::max(1, sv.bpc_stream); ++gp) {
-      for (int pp : {1, 2}) {  // phases queued past the checked live set
-        lm_tuning t{sm, gp, pp, saved.tail_entries};
-        sv.tun = t;
-        std::vector<double> ms;
-        for (int rep = 0; rep < 3 && rs == LM_OK; ++rep) {
-          lm_stats st;
-          std::memset(&st, 0, sizeof(st));
-          rs = solve_locked(c, N, nnz, graphs, vtx_off, row_ptr, col, w, nullptr, 1, mate, fl | LM_OUT_DEVICE,
-                            (void*)sv.own, &st, nullptr);
-          ms.push_back(st.device_ms);
-        }
-        if (rs != LM_OK) break;
-        std::sort(ms.begin(), ms.end());
-        if (ms[1] < best_ms) {
-          best_ms = ms[1];
-          best = t;
-        }
-      }
-      if (rs != LM_OK) break;
+  auto trial = [&](const lm_tuning& t) {  // median of three solves; keeps the fastest tuning
+    sv.tun = t;
+    std::vector<double> ms;
+    for (int rep = 0; rep < 3 && rs == LM_OK; ++rep) {
+      lm_stats st;
+      std::memset(&st, 0, sizeof(st));
+      rs = solve_locked(c, N, nnz, graphs, vtx_off, row_ptr, col, w, nullptr, 1, mate, fl | LM_OUT_DEVICE,
+                        (void*)sv.own, &st, nullptr);
+      ms.push_back(st.device_ms);
     }
-    if (rs != LM_OK) break;
-  }
+    if (rs != LM_OK) return;
+    std::sort(ms.begin(), ms.end());
+    if (ms[1] < best_ms) {
+      best_ms = ms[1];
+      best = t;
+    }
+  };
+  // 1. range size, grid and queued phases; 2. the live-set size handed to the
+  // tail kernel (the stream kernels' per-piece bin threshold is a compile-time
+  // constant: as a kernel argument it costs registers and spills)
+  const int bes[] = {2048, 8192, 32768};
+  for (int sm : bes)
+    for (int gp = 1; gp <= std::max(1, sv.bpc_stream) && rs == LM_OK; ++gp)
+      for (int pp : {1, 2}) {  // phases queued past the checked live set
+        lm_tuning t = saved;
+        t.block_entries = sm;
+        t.grid_per_cu = gp;
+        t.phases_per_sync = pp;
+        if (rs == LM_OK) trial(t);
+      }
+  for (int te : {1 << 16, 1 << 18, 1 << 22})
+    if (rs == LM_OK) {
+      lm_tuning t = best;
+      t.tail_entries = te;
+      trial(t);
+    }
   (void)hipFree(mate);
   if (rs != LM_OK) {
     sv.tun = saved;
@@ -526,6 +540,7 @@ lm_status lm_autotune_batch(lm_ctx* c, int32_t graphs, const int64_t* vtx_off, i
     if (f)
       f << "{\"device\": \"" << sv.dev_name << "\", \"class\": \"" << cls << "\", \"block_entries\": " << best.block_entries
         << ", \"grid_per_cu\": " << best.grid_per_cu << ", \"phases_per_sync\": " << best.phases_per_sync
+        << ", \"tail_entries\": " << best.tail_entries
         << ", \"ms\": " << best_ms << "}\n";
   }
   return LM_OK;

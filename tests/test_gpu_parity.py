@@ -467,9 +467,10 @@ def test_autotune_batch_and_cache(ctx, torch_dev, tmp_path):
         print("case: autotune batch of 48", flush=True)
         t1 = ctx.autotune_batch(b.vtx_off, rp, col, w, cache_path=cache)
         assert 2048 <= t1["block_entries"] <= 4194304 and t1["grid_per_cu"] >= 1 and t1["phases_per_sync"] >= 1
+        assert t1["tail_entries"] >= 0
         assert ctx.tuning() == t1
         lines = open(cache).read().strip().splitlines()
-        assert len(lines) == 1 and '"block_entries"' in lines[0]
+        assert len(lines) == 1 and '"block_entries"' in lines[0] and '"tail_entries"' in lines[0]
         ctx.set_tuning(**base)
         t2 = ctx.autotune_batch(b.vtx_off, rp, col, w, cache_path=cache)  # answered from the cache
         assert t2 == t1 and len(open(cache).read().strip().splitlines()) == 1
