@@ -73,6 +73,10 @@ def _load():
         lib.lmo_greedy_certificate.restype = ctypes.c_int64
         lib.lmo_contract.argtypes = [ctypes.c_int64, _P64, _P32, _PF, _P32, _P64, _P32, _P64, _P32, _PF, _P64, _P64]
         lib.lmo_contract.restype = ctypes.c_int64
+        lib.lmo_hem.argtypes = [ctypes.c_int64, _P64, _P32, _PF, _P32, _P32]
+        lib.lmo_hem.restype = ctypes.c_int64
+        lib.lmo_gpa.argtypes = [ctypes.c_int64, _P64, _P32, _PF, _P32]
+        lib.lmo_gpa.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -186,3 +190,33 @@ def contract(n, row_ptr, col, w, mate, vw=None):
 
 def contract_graph(g, mate, vw=None, unweighted=False):
     return contract(g.n, g.row_ptr, g.col, None if unweighted else g.w, mate, vw)
+
+
+def hem(g, order, unweighted=False):
+    """Heavy edge matching visiting the vertices in `order` (Section 3's
+    comparison baseline; reporting only). Returns mate."""
+    rp = _c(g.row_ptr, np.int64)
+    cc = _c(g.col, np.int32)
+    ww = None if unweighted else _c(g.w, np.float32)
+    od = _c(order, np.int32)
+    mate = np.empty(max(g.n, 1), dtype=np.int32)
+    r = _load().lmo_hem(g.n, rp.ctypes.data_as(_P64), cc.ctypes.data_as(_P32),
+                        ww.ctypes.data_as(_PF) if ww is not None else None, od.ctypes.data_as(_P32),
+                        mate.ctypes.data_as(_P32))
+    if r < 0:
+        raise ValueError(f"hem rejected the input (code {r})")
+    return mate[:g.n].copy()
+
+
+def gpa(g, unweighted=False):
+    """Global path algorithm (Section 3's quality reference; reporting only).
+    Returns mate."""
+    rp = _c(g.row_ptr, np.int64)
+    cc = _c(g.col, np.int32)
+    ww = None if unweighted else _c(g.w, np.float32)
+    mate = np.empty(max(g.n, 1), dtype=np.int32)
+    r = _load().lmo_gpa(g.n, rp.ctypes.data_as(_P64), cc.ctypes.data_as(_P32),
+                        ww.ctypes.data_as(_PF) if ww is not None else None, mate.ctypes.data_as(_P32))
+    if r < 0:
+        raise ValueError(f"gpa rejected the input (code {r})")
+    return mate[:g.n].copy()

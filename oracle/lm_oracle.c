@@ -424,3 +424,204 @@ int64_t lmo_contract(int64_t n, const int64_t* row_ptr, const int32_t* col, cons
   *nc_out = nc;
   return out;
 }
+
+/*
+ * Quality baselines of the paper's Section 3 (reporting only, not part of
+ * the hot path):
+ *
+ * Heavy edge matching (HEM): the vertices are visited in a given order (the
+ * caller passes a permutation, for the randomised variant a random one); an
+ * unmatched vertex is matched to its heaviest unmatched neighbour (the first
+ * one in row order among equal weights).
+ *
+ * Global path algorithm (GPA): the edges are scanned by decreasing weight
+ * (ties by increasing (lo, hi)); an edge joins a subgraph G2 when both ends
+ * have degree below two in G2 and it closes no odd cycle; then a maximum
+ * weight matching of every path and even cycle of G2 is found by dynamic
+ * programming along it.
+ */
+int64_t lmo_hem(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, const int32_t* order,
+                int32_t* mate) {
+  if (n < 0 || !row_ptr || !order || !mate) return LMO_EINVAL;
+  for (int64_t v = 0; v < n; ++v) mate[v] = LMO_NONE;
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t v = order[i];
+    if (v < 0 || v >= n) return LMO_EINVAL;
+    if (mate[v] != LMO_NONE) continue;
+    int32_t best = LMO_NONE;
+    float bw = 0.0f;
+    for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+      const int32_t u = col[k];
+      if (u == v || mate[u] != LMO_NONE) continue;
+      const float x = w ? w[k] : 1.0f;
+      if (best == LMO_NONE || x > bw) {
+        best = u;
+        bw = x;
+      }
+    }
+    if (best != LMO_NONE) {
+      mate[v] = best;
+      mate[best] = v;
+      ++m;
+    }
+  }
+  return m;
+}
+
+typedef struct {
+  int32_t lo, hi;
+  float w;
+} lmo_wedge;
+
+static int wedge_heavier(const void* pa, const void* pb) {
+  const lmo_wedge* a = (const lmo_wedge*)pa;
+  const lmo_wedge* b = (const lmo_wedge*)pb;
+  if (a->w != b->w) return a->w > b->w ? -1 : 1;
+  if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+  if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+  return 0;
+}
+
+static int32_t uf_find(int32_t* parent, int32_t x) {
+  while (parent[x] != x) {
+    parent[x] = parent[parent[x]];
+    x = parent[x];
+  }
+  return x;
+}
+
+/* Maximum weight matching of the path x[0..len] with edge weights ew[0..len-1]
+ * (edge i joins x[i] and x[i+1]), written into mate. */
+static void path_dp(const int32_t* x, const float* ew, int64_t len, double* best, int8_t* take, int32_t* mate) {
+  if (len <= 0) return;
+  best[0] = 0.0;
+  for (int64_t i = 1; i <= len; ++i) {
+    const double skip = best[i - 1];
+    const double with = (i >= 2 ? best[i - 2] : 0.0) + (double)ew[i - 1];
+    take[i] = with > skip;
+    best[i] = take[i] ? with : skip;
+  }
+  for (int64_t i = len; i >= 1;) {
+    if (take[i]) {
+      mate[x[i - 1]] = x[i];
+      mate[x[i]] = x[i - 1];
+      i -= 2;
+    } else {
+      i -= 1;
+    }
+  }
+}
+
+int64_t lmo_gpa(int64_t n, const int64_t* row_ptr, const int32_t* col, const float* w, int32_t* mate) {
+  if (n < 0 || !row_ptr || !mate) return LMO_EINVAL;
+  const int64_t nnz = n > 0 ? row_ptr[n] : 0;
+  lmo_wedge* e = (lmo_wedge*)malloc((size_t)(nnz / 2 + 1) * sizeof(lmo_wedge));
+  int32_t* adj = (int32_t*)malloc((size_t)(2 * n + 2) * sizeof(int32_t));   /* two G2 neighbours */
+  float* adjw = (float*)malloc((size_t)(2 * n + 2) * sizeof(float));
+  int32_t* parent = (int32_t*)malloc((size_t)(n + 1) * sizeof(int32_t));
+  int64_t* cedges = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));  /* edges per component root */
+  int32_t* seq = (int32_t*)malloc((size_t)(n + 2) * sizeof(int32_t));
+  float* sw = (float*)malloc((size_t)(n + 2) * sizeof(float));
+  double* best = (double*)malloc((size_t)(n + 2) * sizeof(double));
+  int8_t* take = (int8_t*)malloc((size_t)(n + 2));
+  int8_t* seen = (int8_t*)calloc((size_t)(n + 1), 1);
+  if (!e || !adj || !adjw || !parent || !cedges || !seq || !sw || !best || !take || !seen) {
+    free(e); free(adj); free(adjw); free(parent); free(cedges); free(seq); free(sw); free(best); free(take);
+    free(seen);
+    return LMO_ENOMEM;
+  }
+  int64_t m = 0;
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k)
+      if (col[k] > v) {
+        e[m].lo = (int32_t)v;
+        e[m].hi = col[k];
+        e[m].w = w ? w[k] : 1.0f;
+        ++m;
+      }
+  qsort(e, (size_t)m, sizeof(lmo_wedge), wedge_heavier);
+  for (int64_t v = 0; v < n; ++v) {
+    adj[2 * v] = adj[2 * v + 1] = LMO_NONE;
+    parent[v] = (int32_t)v;
+    cedges[v] = 0;
+    mate[v] = LMO_NONE;
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    const int32_t a = e[i].lo, b = e[i].hi;
+    if (adj[2 * a + 1] != LMO_NONE || adj[2 * b + 1] != LMO_NONE) continue; /* degree two already */
+    const int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+    if (ra == rb) {
+      if (cedges[ra] % 2 == 0) continue; /* closing the path would make an odd cycle */
+      cedges[ra] += 1;
+    } else {
+      parent[rb] = ra;
+      cedges[ra] += cedges[rb] + 1;
+    }
+    adj[2 * a + (adj[2 * a] == LMO_NONE ? 0 : 1)] = b;
+    adjw[2 * a + (adj[2 * a + 1] == b ? 1 : 0)] = e[i].w;
+    adj[2 * b + (adj[2 * b] == LMO_NONE ? 0 : 1)] = a;
+    adjw[2 * b + (adj[2 * b + 1] == a ? 1 : 0)] = e[i].w;
+  }
+  /* paths first (from an end), then the cycles that remain */
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t s = 0; s < n; ++s) {
+      if (seen[s]) continue;
+      const int deg = (adj[2 * s] != LMO_NONE) + (adj[2 * s + 1] != LMO_NONE);
+      if (pass == 0 && deg == 2) continue;
+      int64_t len = 0;
+      int32_t prev = LMO_NONE, cur = (int32_t)s;
+      seq[0] = cur;
+      seen[cur] = 1;
+      for (;;) {
+        int32_t nxt = LMO_NONE;
+        float nw = 0.0f;
+        for (int j = 0; j < 2; ++j) {
+          const int32_t u = adj[2 * cur + j];
+          if (u != LMO_NONE && u != prev && !seen[u]) {
+            nxt = u;
+            nw = adjw[2 * cur + j];
+            break;
+          }
+        }
+        if (nxt == LMO_NONE) break;
+        sw[len] = nw;
+        seq[++len] = nxt;
+        seen[nxt] = 1;
+        prev = cur;
+        cur = nxt;
+      }
+      if (pass == 0 || len == 0) {
+        path_dp(seq, sw, len, best, take, mate);
+        continue;
+      }
+      /* an even cycle seq[0..len] plus the closing edge (seq[len], seq[0]) */
+      float wc = 0.0f;
+      for (int j = 0; j < 2; ++j)
+        if (adj[2 * seq[len] + j] == seq[0]) wc = adjw[2 * seq[len] + j];
+      /* without the closing edge: the path as it is */
+      path_dp(seq, sw, len, best, take, mate);
+      const double without = best[len];
+      /* with it: the path seq[1..len-1] plus the closing edge */
+      double with_c = (double)wc;
+      if (len >= 3) {
+        path_dp(seq + 1, sw + 1, len - 2, best, take, mate); /* overwritten below if worse */
+        with_c += best[len - 2];
+      }
+      if (with_c > without) {
+        for (int64_t i = 0; i <= len; ++i) mate[seq[i]] = LMO_NONE;
+        if (len >= 3) path_dp(seq + 1, sw + 1, len - 2, best, take, mate);
+        mate[seq[0]] = seq[len];
+        mate[seq[len]] = seq[0];
+      } else {
+        for (int64_t i = 0; i <= len; ++i) mate[seq[i]] = LMO_NONE;
+        path_dp(seq, sw, len, best, take, mate);
+      }
+    }
+  }
+  int64_t matched = 0;
+  for (int64_t v = 0; v < n; ++v) matched += mate[v] != LMO_NONE;
+  free(e); free(adj); free(adjw); free(parent); free(cedges); free(seq); free(sw); free(best); free(take);
+  free(seen);
+  return matched / 2;
+}
