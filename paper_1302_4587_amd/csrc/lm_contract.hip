@@ -299,23 +299,30 @@ __device__ __forceinline__ int start_at(const int* st, int t) {
 }
 
 // Sums the fine edges of one group in increasing (min end, max end).
-__device__ __forceinline__ float group_sum(const unsigned long long* ord_in, const float* w_in, int n) {
-  unsigned long long ord[kCMaxDup];
-  float wv[kCMaxDup];
-  for (int t = 0; t < n; ++t) {
-    const unsigned long long o = ord_in[t];
-    const float ww = w_in[t];
-    int u = t;
-    while (u > 0 && ord[u - 1] > o) {
-      ord[u] = ord[u - 1];
-      wv[u] = wv[u - 1];
-      --u;
-    }
-    ord[u] = o;
-    wv[u] = ww;
+// Sums the n <= 4 fine edges of one group in increasing (min end, max end):
+// slots n..3 hold ord = ~0 and sort last; a fixed sorting network keeps every
+// index static (no dynamic register indexing).
+static_assert(kCMaxDup == 4, "the sorting network below is for four slots");
+__device__ __forceinline__ void cswap(unsigned long long& oa, float& wa, unsigned long long& ob, float& wb) {
+  if (ob < oa) {
+    const unsigned long long t = oa;
+    oa = ob;
+    ob = t;
+    const float u = wa;
+    wa = wb;
+    wb = u;
   }
+}
+__device__ __forceinline__ float group_sum(unsigned long long* ord, float* wv, int n) {
+  cswap(ord[0], wv[0], ord[1], wv[1]);
+  cswap(ord[2], wv[2], ord[3], wv[3]);
+  cswap(ord[0], wv[0], ord[2], wv[2]);
+  cswap(ord[1], wv[1], ord[3], wv[3]);
+  cswap(ord[1], wv[1], ord[2], wv[2]);
   float sum = wv[0];
-  for (int t = 1; t < n; ++t) sum += wv[t];
+  if (n > 1) sum += wv[1];
+  if (n > 2) sum += wv[2];
+  if (n > 3) sum += wv[3];
   return sum;
 }
 
@@ -323,7 +330,272 @@ __device__ __forceinline__ unsigned long long edge_order(int s, int x) {
   return ((unsigned long long)(unsigned)min(s, x) << 32) | (unsigned)max(s, x);
 }
 
-// (2) Groups the entries of every short coarse row (bound <= kCS) in LDS and
+constexpr int kWT = 256;           // wave tile capacity in entries
+constexpr int kWS = 64;            // largest coarse-row bound one wave merges alone
+constexpr int kWStep = kWT - kWS;  // wave tiles take the rows that start in a window of this many entries
+constexpr int kWTI = kWT / 64;     // tile entries per lane
+
+struct WaveSmem {
+  int skey[2 * kWT];   // coarse neighbour of the slot, -1 if free
+  int shead[2 * kWT];  // last tile position inserted into the slot's list
+  short enext[kWT];
+  short eslot[kWT];
+  unsigned char erow[kWT];
+  int st[65];  // wave-local start of each lane's row; st[64] = the wave's total
+  int ra[64], rb[64], rc[64], rdega[64], rut[64];
+  int rrk[64][2];  // kept entries of the tile before the row's a part and b part
+  long long rka[64], rkb[64];
+};
+
+// Orders the wave's LDS accesses across lanes (a wave's LDS operations are
+// performed in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Start of the first of the wave's rows whose start is at least t (the
+// wave's total if none).
+__device__ __forceinline__ int wstart_at(const int* st, int t) {
+  if (st[0] >= t) return st[0];
+  int lo = 0, hi = 64;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (st[mid] >= t)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return st[hi];
+}
+__device__ __forceinline__ int wrow_of(const int* st, int pos) {
+  int lo = 0, hi = 64;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (st[mid] <= pos)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// (2a) The coarse rows with bound <= kWS, one wave at a time with no
+// workgroup barrier: each wave takes 64 fine vertices of every chunk of its
+// workgroup's range, lays their rows out back to back and groups them in
+// wave tiles of at most kWT entries (the same grouping as k_c_group, in the
+// wave's own LDS); ranks in row order come from the tile's ballots.
+__global__ __launch_bounds__(kBlock) void k_c_group_wave(CArgs a, long long per_wg) {
+  __shared__ WaveSmem wsm[kWaves];
+  __shared__ int lb[1];
+  if (a.tot->err & (kCErrMate | kCErrRowPtr)) return;
+  long long vb, ve;
+  wg_vertices(a, per_wg, vb, ve, lb);
+  WaveSmem& sm = wsm[wave_id()];
+  const int l = lane_id();
+  for (int i = l; i < 2 * kWT; i += 64) {
+    sm.skey[i] = -1;
+    sm.shead[i] = -1;
+  }
+  wave_sync();
+  unsigned err = 0;
+  for (long long cb = vb + (long long)wave_id() * 64; cb < ve; cb += kBlock) {
+    const long long v = cb + l;
+    RowHead h;
+    h.rep = false;
+    h.lng = false;
+    h.m = -1;
+    h.c = h.dega = h.ub = 0;
+    h.ka = h.kb = 0;
+    if (v < ve) h = row_head(a, v);
+    const int ut = (h.rep && !h.lng && h.ub <= kWS) ? h.ub : 0;
+    const int incl = wave_incl_sum<int>(ut);
+    const int U = __shfl(incl, 63);
+    sm.st[l] = incl - ut;
+    if (l == 63) sm.st[64] = U;
+    sm.ra[l] = (int)v;
+    sm.rb[l] = h.m;
+    sm.rc[l] = h.c;
+    sm.rdega[l] = h.dega;
+    sm.rut[l] = ut;
+    sm.rka[l] = h.ka;
+    sm.rkb[l] = h.kb;
+    wave_sync();
+    const int ntile = (U + kWStep - 1) / kWStep;
+    for (int j = 0; j < ntile; ++j) {
+      const int lo = wstart_at(sm.st, j * kWStep);
+      const int hi = wstart_at(sm.st, (j + 1) * kWStep);
+      const int len = hi - lo;
+      if (len <= 0) continue;
+      int Dr[kWTI], xr[kWTI], rr[kWTI];
+      float wr[kWTI];
+      long long kr[kWTI];
+      // 1: load every entry of the lane, then map them all, then insert
+#pragma unroll
+      for (int i = 0; i < kWTI; ++i) {
+        const int q = i * 64 + l;
+        rr[i] = 0;
+        kr[i] = -1;
+        Dr[i] = -1;
+        xr[i] = 0;
+        wr[i] = 0.f;
+        if (q < len) {
+          const int pos = lo + q;
+          const int r = wrow_of(sm.st, pos);
+          const int off = pos - sm.st[r];
+          const bool side = off >= sm.rdega[r];
+          rr[i] = r;
+          kr[i] = side ? sm.rkb[r] + (off - sm.rdega[r]) : sm.rka[r] + off;
+          sm.erow[q] = (unsigned char)r;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kWTI; ++i) {
+        if (kr[i] < 0) continue;
+        xr[i] = a.col[kr[i]];
+        wr[i] = a.w ? a.w[kr[i]] : 1.0f;
+      }
+#pragma unroll
+      for (int i = 0; i < kWTI; ++i) {
+        if (kr[i] < 0) continue;
+        if ((unsigned)xr[i] >= (unsigned)a.n)
+          err |= kCErrCol;
+        else
+          Dr[i] = a.identity ? xr[i] : a.cmap[xr[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < kWTI; ++i) {
+        const int q = i * 64 + l;
+        const int r = rr[i];
+        if (kr[i] < 0) continue;
+        if (Dr[i] == sm.rc[r]) Dr[i] = -1;
+        const int D = Dr[i];
+        if (D >= 0) {
+          const unsigned sb = 2u * (unsigned)(sm.st[r] - lo);
+          const unsigned range = 2u * (unsigned)sm.rut[r];
+          unsigned hh = (unsigned)(((unsigned long long)((unsigned)D * 0x9E3779B1u) * range) >> 32);
+          for (;;) {
+            const int old = atomicCAS(&sm.skey[sb + hh], -1, D);
+            if (old == -1 || old == D) break;
+            hh = hh + 1 == range ? 0u : hh + 1;
+          }
+          sm.eslot[q] = (short)(sb + hh);
+          sm.enext[q] = (short)atomicExch(&sm.shead[sb + hh], q);
+        }
+      }
+      wave_sync();
+      // 2: the first entry of every group keeps it, with the group's sum
+      bool keep[kWTI];
+      float sumr[kWTI];
+      unsigned long long bal[kWTI];
+#pragma unroll
+      for (int i = 0; i < kWTI; ++i) {
+        const int q = i * 64 + l;
+        keep[i] = false;
+        sumr[i] = 0.f;
+        if (q < len && Dr[i] >= 0) {
+          int lst[kCMaxDup + 1];
+          int nl = 0;
+          int p = sm.shead[sm.eslot[q]];
+          bool first = true;
+#pragma unroll
+          for (int t = 0; t <= kCMaxDup; ++t) {  // static indices: at most five nodes matter
+            if (p >= 0) {
+              lst[t] = p;
+              nl = t + 1;
+              first = first && p >= q;
+              p = sm.enext[p];
+            }
+          }
+          if (nl > a.dup_limit) err |= kCErrDup;
+          if (first && nl <= a.dup_limit) {
+            keep[i] = true;
+            const int r = rr[i];
+            if (nl == 1) {
+              sumr[i] = wr[i];
+            } else {
+              unsigned long long ord[kCMaxDup];
+              float wg[kCMaxDup];
+#pragma unroll
+              for (int t = 0; t < kCMaxDup; ++t) {
+                ord[t] = ~0ull;
+                wg[t] = 0.f;
+                if (t >= nl) continue;
+                const int pp = lst[t];
+                const int off = lo + pp - sm.st[r];
+                const bool side = off >= sm.rdega[r];
+                const int s = side ? sm.rb[r] : sm.ra[r];
+                int xp = xr[i];
+                float wp = wr[i];
+                if (pp != q) {
+                  const long long kp = side ? sm.rkb[r] + (off - sm.rdega[r]) : sm.rka[r] + off;
+                  xp = a.col[kp];
+                  wp = a.w ? a.w[kp] : 1.0f;
+                }
+                ord[t] = edge_order(s, xp);
+                wg[t] = wp;
+              }
+              sumr[i] = group_sum(ord, wg, nl);
+            }
+          }
+        }
+        bal[i] = __ballot(keep[i]);
+      }
+      // 3: kept entries before a tile position, from the ballots: every row's
+      // lane finds its parts' starts, every kept entry its own rank
+      int pre[kWTI];
+      pre[0] = 0;
+#pragma unroll
+      for (int i = 1; i < kWTI; ++i) pre[i] = pre[i - 1] + (int)__popcll(bal[i - 1]);
+      auto rank_at = [&](int pos) -> int {  // any tile position (row lanes only)
+        const int ri = pos >> 6;
+        int base = pre[kWTI - 1] + (int)__popcll(bal[kWTI - 1]);
+        unsigned long long b = 0ull;
+#pragma unroll
+        for (int t = 0; t < kWTI; ++t)
+          if (t == ri) {
+            base = pre[t];
+            b = bal[t];
+          }
+        return base + (int)__popcll(b & ((1ull << (pos & 63)) - 1ull));
+      };
+      const bool row_here = sm.rut[l] > 0 && sm.st[l] >= lo && sm.st[l] < hi;
+      if (row_here) {
+        const int s0 = sm.st[l] - lo;
+        const int r0 = rank_at(s0), rb_ = rank_at(s0 + sm.rdega[l]);
+        sm.rrk[l][0] = r0;
+        sm.rrk[l][1] = rb_;
+        if (a.cnt) {
+          a.cnt[sm.ra[l]] = rb_ - r0;
+          if (sm.rb[l] >= 0) a.cnt[sm.rb[l]] = rank_at(s0 + sm.rut[l]) - rb_;
+        }
+      }
+      wave_sync();
+      if (a.scr) {
+#pragma unroll
+        for (int i = 0; i < kWTI; ++i) {
+          const int q = i * 64 + l;
+          if (q >= len || !keep[i]) continue;
+          const int r = rr[i];
+          const int off = lo + q - sm.st[r];
+          const bool side = off >= sm.rdega[r];
+          const int own = pre[i] + (int)__popcll(bal[i] & lanemask_lt());
+          a.scr[(side ? sm.rkb[r] : sm.rka[r]) + (own - sm.rrk[r][side ? 1 : 0])] =
+              make_int2(Dr[i], __float_as_int(sumr[i]));
+        }
+      }
+      for (int i = l; i < 2 * len; i += 64) {
+        sm.skey[i] = -1;
+        sm.shead[i] = -1;
+      }
+      wave_sync();
+    }
+    wave_sync();
+  }
+  if (err) atomicOr(&a.tot->err, err);
+}
+
+// (2b) Groups the entries of every medium coarse row (kWS < bound <= kCS) in LDS and
 // keeps, compacted in place at the start of each row part, the first entry of
 // every group with the group's sum; sets the parts' kept counts. Queues the
 // long rows.
@@ -365,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
         }
       }
     }
-    const int ut = (h.rep && !h.lng) ? h.ub : 0;
+    const int ut = (h.rep && !h.lng && h.ub > kWS) ? h.ub : 0;  // shorter rows: k_c_group_wave
     int U;
     const int st = block_excl_sum<int>(ut, sm.smi, U);
     sm.st[tid] = st;
@@ -457,10 +729,14 @@ __global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
           int nl = 0;
           int p = sm.shead[sm.eslot[q]];
           bool first = true;
-          while (p >= 0 && nl <= kCMaxDup) {
-            lst[nl++] = p;
-            first = first && p >= q;
-            p = sm.enext[p];
+#pragma unroll
+          for (int t = 0; t <= kCMaxDup; ++t) {  // static indices: at most five nodes matter
+            if (p >= 0) {
+              lst[t] = p;
+              nl = t + 1;
+              first = first && p >= q;
+              p = sm.enext[p];
+            }
           }
           if (nl > a.dup_limit) err |= kCErrDup;
           if (first && nl <= a.dup_limit) {
@@ -471,7 +747,11 @@ __global__ __launch_bounds__(kBlock) void k_c_group(CArgs a, long long per_wg) {
             } else {
               unsigned long long ord[kCMaxDup];
               float wg[kCMaxDup];
-              for (int t = 0; t < nl; ++t) {
+#pragma unroll
+              for (int t = 0; t < kCMaxDup; ++t) {
+                ord[t] = ~0ull;
+                wg[t] = 0.f;
+                if (t >= nl) continue;
                 const int pp = lst[t];
                 const int off = lo + pp - sm.st[r];
                 const bool side = off >= sm.rdega[r];
@@ -775,14 +1055,16 @@ __global__ __launch_bounds__(kBlock) void k_c_long_keep(CArgs a, long long nl, l
       int p = slot[j].y;
       int pn = nxt[j];
       bool first = true;
-      for (;;) {
-        lst[nlst++] = p;
+#pragma unroll
+      for (int t = 0; t <= kCMaxDup; ++t) {  // static indices: at most five nodes matter
+        if (p < 0) continue;
+        lst[t] = p;
+        nlst = t + 1;
         const bool pa = (long long)p >= ka && (long long)p < ka + L.dega;
         const long long pos_p = pa ? p - ka : L.dega + (p - kb);
         first = first && pos_p >= at[j].off;
-        if (pn < 0 || nlst > kCMaxDup) break;
         p = pn;
-        pn = a.next[p];
+        if (p >= 0 && t < kCMaxDup) pn = a.next[p];
       }
       if (nlst > a.dup_limit) err |= kCErrDup;
       if (!a.scr) continue;
@@ -794,7 +1076,11 @@ __global__ __launch_bounds__(kBlock) void k_c_long_keep(CArgs a, long long nl, l
       if (nlst > 1) {
         unsigned long long ord[kCMaxDup];
         float wv[kCMaxDup];
-        for (int t = 0; t < nlst; ++t) {
+#pragma unroll
+        for (int t = 0; t < kCMaxDup; ++t) {
+          ord[t] = ~0ull;
+          wv[t] = 0.f;
+          if (t >= nlst) continue;
           const int pp = lst[t];
           const bool pa = (long long)pp >= ka && (long long)pp < ka + L.dega;
           const int sp = pa ? L.a : L.b;
@@ -953,6 +1239,7 @@ lm_status check_row_duplicates(Solver& S, int64_t n, int64_t nnz, const long lon
   const long long cost = nnz + (long long)kCCost * n;
   long long grid = (long long)S.num_cus * tile_blocks_per_cu();
   grid = std::max<long long>(1, std::min<long long>(grid, (cost + 2 * kCT - 1) / (2 * kCT)));
+  hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)grid), dim3(kBlock), 0, s, a, (cost + grid - 1) / grid);
   hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, (cost + grid - 1) / grid);
   hipLaunchKernelGGL(k_c_long_prep, dim3(1), dim3(kCTopThreads), 0, s, a);
   if (hipGetLastError() != hipSuccess) return LM_EDEVICE;
@@ -1119,6 +1406,7 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
   if (grid > by_cost) grid = by_cost;
   if (grid < 1) grid = 1;
   const long long per_wg = (cost + grid - 1) / grid;
+  hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
   hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
   hipLaunchKernelGGL(k_c_long_prep, dim3(1), dim3(kCTopThreads), 0, s, a);
   LMC_HIP(hipGetLastError());
