@@ -253,9 +253,12 @@ typedef struct {
   double device_ms;     /* stream time from the first kernel to the last */
   double bytes_alg;     /* algorithmic HBM bytes: 8(n+1) + 8n + (eb + 4) nnz + 8(nc+1) + 8 nnz_c
                            (+ 8n in, 8nc out with vertex weights), eb = 8 weighted, 4 unweighted */
-  int64_t long_rows;    /* coarse rows with deg(a) + deg(b) > 512, merged through device-memory
-                           hash tables instead of LDS */
+  int64_t long_rows;    /* coarse rows with deg(a) + deg(b) > 512: their entries are sorted into
+                           buckets of about 512 by a hash of the coarse neighbour and each
+                           bucket is merged in LDS */
   int64_t long_entries; /* the fine entries of those rows */
+  int64_t table_rows;   /* long rows merged through per-row hash tables in device memory
+                           instead (all of them, when a bucket outgrew LDS; normally 0) */
 } lm_contract_stats;
 
 /* Contracts a graph by a matching: the coarsening step of multilevel graph

@@ -77,8 +77,9 @@ class MatchStats:
 class ContractStats:
     device_ms: float
     bytes_alg: float
-    long_rows: int      # coarse rows merged through device-memory hash tables
+    long_rows: int      # coarse rows with deg(a) + deg(b) > 512 (bucketed, merged in LDS)
     long_entries: int   # their fine entries
+    table_rows: int = 0  # long rows merged through device-memory hash tables instead
 
 
 def _stats_out(st: _lib.Stats, logbuf, weight_sum=False) -> MatchStats:
@@ -235,7 +236,8 @@ class Context:
                                     ctypes.byref(st)), "lm_contract")
         nc, mc = int(out.n), int(out.nnz)
         return (cmap[:n], crp[:nc + 1], ccol[:mc], cw[:mc], cvw[:nc] if cvw is not None else None,
-                ContractStats(float(st.device_ms), float(st.bytes_alg), int(st.long_rows), int(st.long_entries)))
+                ContractStats(float(st.device_ms), float(st.bytes_alg), int(st.long_rows), int(st.long_entries),
+                              int(st.table_rows)))
 
     def match_noalloc(self, row_ptr, col, w, seed: int = 1, mate=None, *, check_graph=False, stream=None,
                       log_cap: int = 4096):

@@ -82,7 +82,7 @@ class Coarse(ctypes.Structure):
 
 class ContractStats(ctypes.Structure):
     _fields_ = [("device_ms", ctypes.c_double), ("bytes_alg", ctypes.c_double), ("long_rows", ctypes.c_int64),
-                ("long_entries", ctypes.c_int64)]
+                ("long_entries", ctypes.c_int64), ("table_rows", ctypes.c_int64)]
 
 
 class ServerOpts(ctypes.Structure):

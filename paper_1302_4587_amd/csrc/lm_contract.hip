@@ -48,6 +48,8 @@ constexpr int kCCost = 4;               // cost of a fine vertex when ranges are
 constexpr int kCTopThreads = 1024;
 constexpr int kCPackGrid = 4096;
 constexpr unsigned long long kEmpty = ~0ull;
+constexpr int kLB = 512;      // average entries of a long row's bucket
+constexpr int kLBCap = 1024;  // entries a bucket may hold in LDS (more: the table path)
 
 constexpr unsigned kCErrMate = 1u;    // mate is not an involution with -1 for free vertices
 constexpr unsigned kCErrRowPtr = 2u;  // row_ptr is not a valid offset array
@@ -62,14 +64,21 @@ struct CTot {
   long long nlong;         // coarse rows merged through device-memory tables
   long long long_entries;  // the sum of their bounds
   long long long_slots;    // hash slots their tables take
+  long long long_buckets;  // LDS-sized buckets their entries are sorted into
+  long long long_kept;     // their entries that are not the matched edge
+  unsigned overflow;       // a bucket outgrew LDS: the long rows take the table path
+  unsigned pad2;
 };
 
 struct LongRow {
   int a, b, c, dega;
   int ub;     // deg(a) + deg(b)
   int tbits;  // table of 2^tbits slots
+  int nb;     // buckets of the row (about kLB entries each)
+  int pad;
   long long eoff;  // first flat index of the row's entries among all long rows
   long long toff;  // first slot of its table
+  long long boff;  // first bucket of the row
 };
 
 struct CArgs {
@@ -90,6 +99,9 @@ struct CArgs {
   LongRow* lrows;
   long long lrow_cap;
   int2* table;  // (key, list head) per slot of the long rows' tables
+  long long* bstart;  // per bucket: entry count, then (scanned) first record
+  int* bfill;         // per bucket: records placed so far
+  int* rec;           // fine entry indices of the long rows, grouped by bucket
   long long* crp;
   int* ccol;
   float* cw;
@@ -878,30 +890,36 @@ __global__ __launch_bounds__(kCTopThreads) void k_c_long_prep(CArgs a) {
   __shared__ long long sm[kCTopThreads / 64];
   if (a.tot->err) return;
   const long long nl = a.tot->nlong < a.lrow_cap ? a.tot->nlong : a.lrow_cap;
-  long long ce = 0, cs = 0;
+  long long ce = 0, cs = 0, cb = 0;
   for (long long base = 0; base < nl; base += kCTopThreads) {
     const long long i = base + threadIdx.x;
-    long long ub = 0, slots = 0;
+    long long ub = 0, slots = 0, nb = 0;
     int bits = 1;
     if (i < nl) {
       ub = a.lrows[i].ub;
       while ((1ll << bits) < 2 * ub) ++bits;
       slots = 1ll << bits;
+      nb = (ub + kLB - 1) / kLB;
     }
-    long long te, ts;
+    long long te, ts, tb;
     const long long ee = top_excl_sum(ub, sm, te);
     const long long es = top_excl_sum(slots, sm, ts);
+    const long long eb = top_excl_sum(nb, sm, tb);
     if (i < nl) {
       a.lrows[i].eoff = ce + ee;
       a.lrows[i].toff = cs + es;
       a.lrows[i].tbits = bits;
+      a.lrows[i].nb = (int)nb;
+      a.lrows[i].boff = cb + eb;
     }
     ce += te;
     cs += ts;
+    cb += tb;
   }
   if (threadIdx.x == 0) {
     a.tot->long_entries = ce;
     a.tot->long_slots = cs;
+    a.tot->long_buckets = cb;
   }
 }
 
@@ -1097,6 +1115,211 @@ __global__ __launch_bounds__(kBlock) void k_c_long_keep(CArgs a, long long nl, l
   if (err) atomicOr(&a.tot->err, err);
 }
 
+// ---- long rows through LDS buckets: every entry of a long row goes to one
+// of the row's buckets by a hash of its coarse neighbour (so a group never
+// spans buckets), the entries are sorted by bucket (counts, scan, scatter of
+// fine entry indices), and one workgroup groups each bucket in LDS.
+
+__device__ __forceinline__ long long bucket_of(const LongRow& L, int D) {
+  return L.boff + (long long)(((unsigned long long)((unsigned)D * 0x9E3779B1u) * (unsigned)L.nb) >> 32);
+}
+
+// (3b') Maps every long-row entry (its coarse neighbour into next[k], -1 for
+// the matched edge, whose output is written as dropped now) and counts the
+// buckets.
+__global__ __launch_bounds__(kBlock) void k_c_lb_count(CArgs a, long long nl, long long total) {
+  unsigned err = 0;
+  const long long step = (long long)gridDim.x * kBlock * kLI;
+  for (long long i0 = (long long)blockIdx.x * kBlock * kLI; i0 < total; i0 += step) {
+    const long long r0 = long_row_of(a.lrows, nl, i0);
+    LongAt at[kLI];
+    int x[kLI];
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      const long long i = i0 + (long long)j * kBlock + threadIdx.x;
+      at[j].k = -1;
+      if (i < total) at[j] = long_at(a, nl, r0, i);
+    }
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) x[j] = at[j].k >= 0 ? a.col[at[j].k] : -1;
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      if (at[j].k < 0) continue;
+      int D = -1;
+      if ((unsigned)x[j] >= (unsigned)a.n)
+        err |= kCErrCol;
+      else
+        D = a.identity ? x[j] : a.cmap[x[j]];
+      const LongRow& L = a.lrows[at[j].r];
+      if (D == L.c) D = -1;
+      a.next[at[j].k] = D;
+      if (D < 0) {
+        a.scr[at[j].k] = make_int2(-1, 0);
+        continue;
+      }
+      atomicAdd((unsigned long long*)&a.bstart[bucket_of(L, D)], 1ull);
+    }
+  }
+  if (err) atomicOr(&a.tot->err, err);
+}
+
+// (3c') Places every mapped long-row entry's index in its bucket.
+__global__ __launch_bounds__(kBlock) void k_c_lb_scatter(CArgs a, long long nl, long long total) {
+  const long long step = (long long)gridDim.x * kBlock * kLI;
+  for (long long i0 = (long long)blockIdx.x * kBlock * kLI; i0 < total; i0 += step) {
+    const long long r0 = long_row_of(a.lrows, nl, i0);
+    LongAt at[kLI];
+    int D[kLI];
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      const long long i = i0 + (long long)j * kBlock + threadIdx.x;
+      at[j].k = -1;
+      if (i < total) at[j] = long_at(a, nl, r0, i);
+    }
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) D[j] = at[j].k >= 0 ? a.next[at[j].k] : -1;
+#pragma unroll
+    for (int j = 0; j < kLI; ++j) {
+      if (D[j] < 0) continue;
+      const long long b = bucket_of(a.lrows[at[j].r], D[j]);
+      const long long pos = a.bstart[b] + atomicAdd(&a.bfill[b], 1);
+      a.rec[pos] = (int)at[j].k;
+    }
+  }
+}
+
+struct BucketSmem {
+  int skey[2 * kLBCap];
+  int shead[2 * kLBCap];
+  int ek[kLBCap];
+  int epos[kLBCap];
+  int eD[kLBCap];
+  short enext[kLBCap];
+  short eslot[kLBCap];
+  int kept[2];
+  int row;
+};
+
+// (3d') Groups every bucket in LDS, one workgroup per bucket at a time: the
+// first entry of a group in row order keeps it with the group's sum (written
+// at its fine entry), the others are written as dropped; the parts' kept
+// counts grow by the bucket's. A bucket above kLBCap entries sets overflow.
+__global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, long long nbk) {
+  __shared__ BucketSmem sm;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * kLBCap; i += kBlock) {
+    sm.skey[i] = -1;
+    sm.shead[i] = -1;
+  }
+  unsigned err = 0;
+  for (long long b = blockIdx.x; b < nbk; b += gridDim.x) {
+    const long long s0 = a.bstart[b], s1 = a.bstart[b + 1];
+    const int ne = (int)(s1 - s0);
+    if (ne == 0) continue;  // uniform
+    if (ne > kLBCap) {
+      if (tid == 0) atomicOr(&a.tot->overflow, 1u);
+      continue;
+    }
+    if (tid == 0) {
+      long long lo = 0, hi = nl;  // the row: largest boff <= b
+      while (hi - lo > 1) {
+        const long long mid = (lo + hi) >> 1;
+        if (a.lrows[mid].boff <= b)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      sm.row = (int)lo;
+      sm.kept[0] = sm.kept[1] = 0;
+    }
+    __syncthreads();
+    const LongRow L = a.lrows[sm.row];
+    const long long ka = a.rp[L.a];
+    const long long kb = L.b >= 0 ? a.rp[L.b] : 0;
+    for (int q = tid; q < ne; q += kBlock) {
+      const int k = a.rec[s0 + q];
+      const int D = a.next[k];
+      const bool pa = (long long)k >= ka && (long long)k < ka + L.dega;
+      sm.ek[q] = k;
+      sm.epos[q] = pa ? (int)(k - ka) : L.dega + (int)(k - kb);
+      sm.eD[q] = D;
+      const unsigned h0 = (unsigned)D * 0x85EBCA77u;
+      unsigned hh = (h0 ^ (h0 >> 15)) & (2u * kLBCap - 1u);
+      for (;;) {
+        const int old = atomicCAS(&sm.skey[hh], -1, D);
+        if (old == -1 || old == D) break;
+        hh = (hh + 1) & (2u * kLBCap - 1u);
+      }
+      sm.eslot[q] = (short)hh;
+      sm.enext[q] = (short)atomicExch(&sm.shead[hh], q);
+    }
+    __syncthreads();
+    for (int q = tid; q < ne; q += kBlock) {
+      const int k = sm.ek[q];
+      const int my = sm.epos[q];
+      int lst[kCMaxDup + 1];
+      int nlst = 0;
+      int p = sm.shead[sm.eslot[q]];
+      bool first = true;
+#pragma unroll
+      for (int t = 0; t <= kCMaxDup; ++t) {
+        if (p >= 0) {
+          lst[t] = p;
+          nlst = t + 1;
+          first = first && sm.epos[p] >= my;
+          p = sm.enext[p];
+        }
+      }
+      if (nlst > a.dup_limit) err |= kCErrDup;
+      if (!first || nlst > a.dup_limit) {
+        a.scr[k] = make_int2(-1, 0);
+        continue;
+      }
+      float sum;
+      if (nlst == 1) {
+        sum = a.w ? a.w[k] : 1.0f;
+      } else {
+        unsigned long long ord[kCMaxDup];
+        float wv[kCMaxDup];
+#pragma unroll
+        for (int t = 0; t < kCMaxDup; ++t) {
+          ord[t] = ~0ull;
+          wv[t] = 0.f;
+          if (t >= nlst) continue;
+          const int pp = lst[t];
+          const int kp = sm.ek[pp];
+          const int sp = sm.epos[pp] < L.dega ? L.a : L.b;
+          ord[t] = edge_order(sp, a.col[kp]);
+          wv[t] = a.w ? a.w[kp] : 1.0f;
+        }
+        sum = group_sum(ord, wv, nlst);
+      }
+      a.scr[k] = make_int2(sm.eD[q], __float_as_int(sum));
+      atomicAdd(&sm.kept[my < L.dega ? 0 : 1], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      if (sm.kept[0]) atomicAdd(&a.cnt[L.a], sm.kept[0]);
+      if (sm.kept[1]) atomicAdd(&a.cnt[L.b], sm.kept[1]);
+    }
+    for (int q = tid; q < ne; q += kBlock) {
+      sm.skey[sm.eslot[q]] = -1;
+      sm.shead[sm.eslot[q]] = -1;
+    }
+    __syncthreads();
+  }
+  if (err) atomicOr(&a.tot->err, err);
+}
+
+// Clears the kept counts of the long rows' parts (before the table path
+// redoes them after a bucket overflow).
+__global__ __launch_bounds__(kBlock) void k_c_long_clear_cnt(CArgs a, long long nl) {
+  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < nl; r += (long long)gridDim.x * kBlock) {
+    a.cnt[a.lrows[r].a] = 0;
+    if (a.lrows[r].b >= 0) a.cnt[a.lrows[r].b] = 0;
+  }
+}
+
 __device__ __forceinline__ long long coarse_deg(const CArgs& a, long long c) {
   const int r = a.crep[c];
   const int m = a.mate[r];
@@ -1184,7 +1407,7 @@ size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Buffers of the contraction, kept in the context between calls.
 struct ContractState {
-  DevBuf bsum, tot, crep, cnt, scr, next, lrows, table;
+  DevBuf bsum, tot, crep, cnt, scr, next, lrows, table, bstart, bfill, rec;
   DevBuf in_rp, in_col, in_w, in_mate, in_vw, o_cmap, o_crp, o_ccol, o_cw, o_cvw;
   CTot* h_tot = nullptr;
 };
@@ -1192,9 +1415,9 @@ struct ContractState {
 void contract_release(Solver& S) {
   ContractState* cs = S.contract;
   if (!cs) return;
-  DevBuf* all[] = {&cs->bsum,  &cs->tot,    &cs->crep,    &cs->cnt,    &cs->scr,    &cs->next,   &cs->lrows,
-                   &cs->table, &cs->in_rp,  &cs->in_col,  &cs->in_w,   &cs->in_mate, &cs->in_vw, &cs->o_cmap,
-                   &cs->o_crp, &cs->o_ccol, &cs->o_cw,    &cs->o_cvw};
+  DevBuf* all[] = {&cs->bsum,  &cs->tot,    &cs->crep,  &cs->cnt,  &cs->scr,     &cs->next,  &cs->lrows,
+                   &cs->table, &cs->bstart, &cs->bfill, &cs->rec,  &cs->in_rp,   &cs->in_col, &cs->in_w,
+                   &cs->in_mate, &cs->in_vw, &cs->o_cmap, &cs->o_crp, &cs->o_ccol, &cs->o_cw, &cs->o_cvw};
   for (DevBuf* b : all) S.pool.release(*b);
   if (cs->h_tot) (void)hipHostFree(cs->h_tot);
   delete cs;
@@ -1418,16 +1641,43 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
   const long long nc = t1.nc;
   const long long nl = t1.nlong;
   if (nl > lrow_cap) return LM_EDEVICE;  // cannot happen: the bounds of the rows sum to nnz
+  long long overflow_rows = 0;
   if (nl > 0) {
+    // long rows: entries sorted into LDS-sized buckets by a hash of their
+    // coarse neighbour, each bucket grouped in LDS by one workgroup
+    const long long nbk = t1.long_buckets;
     LMC_TRY(P.reserve(cs.next, a256(sizeof(int) * (size_t)nnz)));
-    LMC_TRY(P.reserve(cs.table, a256(sizeof(int2) * (size_t)t1.long_slots)));
+    LMC_TRY(P.reserve(cs.bstart, a256(sizeof(long long) * (size_t)(nbk + 1))));
+    LMC_TRY(P.reserve(cs.bfill, a256(sizeof(int) * (size_t)nbk)));
+    LMC_TRY(P.reserve(cs.rec, a256(sizeof(int) * (size_t)t1.long_entries)));
     a.next = (int*)cs.next.p;
-    a.table = (int2*)cs.table.p;
-    const long long fill_grid = std::min<long long>((t1.long_slots + kBlock - 1) / kBlock, 8192);
-    hipLaunchKernelGGL(k_c_fill, dim3((unsigned)fill_grid), dim3(kBlock), 0, s, a.table, t1.long_slots);
+    a.bstart = (long long*)cs.bstart.p;
+    a.bfill = (int*)cs.bfill.p;
+    a.rec = (int*)cs.rec.p;
+    LMC_HIP(hipMemsetAsync(a.bstart, 0, sizeof(long long) * (size_t)(nbk + 1), s));
+    LMC_HIP(hipMemsetAsync(a.bfill, 0, sizeof(int) * (size_t)nbk, s));
     const long long lg = std::min<long long>((t1.long_entries + kBlock * kLI - 1) / (kBlock * kLI), 16384);
-    hipLaunchKernelGGL(k_c_long_insert, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
-    hipLaunchKernelGGL(k_c_long_keep, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
+    hipLaunchKernelGGL(k_c_lb_count, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
+    hipLaunchKernelGGL(k_c_scan_top, dim3(1), dim3(kCTopThreads), 0, s, a.bstart, nbk + 1, &a.tot->long_kept);
+    hipLaunchKernelGGL(k_c_lb_scatter, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
+    const long long gg = std::max<long long>(1, std::min<long long>(nbk, (long long)S.num_cus * 8));
+    hipLaunchKernelGGL(k_c_lb_group, dim3((unsigned)gg), dim3(kBlock), 0, s, a, nl, nbk);
+    LMC_HIP(hipGetLastError());
+    LMC_HIP(hipMemcpyAsync(cs.h_tot, a.tot, sizeof(CTot), hipMemcpyDeviceToHost, s));
+    LMC_HIP(hipStreamSynchronize(s));
+    if (cs.h_tot->err & kCErrMate) return LM_EINVAL;
+    if (cs.h_tot->err) return LM_EGRAPH;
+    if (cs.h_tot->overflow) {  // a bucket outgrew LDS: every long row through per-row tables
+      overflow_rows = nl;
+      LMC_TRY(P.reserve(cs.table, a256(sizeof(int2) * (size_t)t1.long_slots)));
+      a.table = (int2*)cs.table.p;
+      const long long cg = std::min<long long>((nl + kBlock - 1) / kBlock, 4096);
+      hipLaunchKernelGGL(k_c_long_clear_cnt, dim3((unsigned)cg), dim3(kBlock), 0, s, a, nl);
+      const long long fill_grid = std::min<long long>((t1.long_slots + kBlock - 1) / kBlock, 8192);
+      hipLaunchKernelGGL(k_c_fill, dim3((unsigned)fill_grid), dim3(kBlock), 0, s, a.table, t1.long_slots);
+      hipLaunchKernelGGL(k_c_long_insert, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
+      hipLaunchKernelGGL(k_c_long_keep, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
+    }
   }
   const long long nb_c = (nc + kCBlockV - 1) / kCBlockV;
   if (nb_c > 0) {
@@ -1467,6 +1717,7 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
                     (vwgt ? 8.0 * n : 0.0) + (out->vwgt ? 8.0 * nc : 0.0);
     st->long_rows = nl;
     st->long_entries = t1.long_entries;
+    st->table_rows = overflow_rows;
   }
   return LM_OK;
 }

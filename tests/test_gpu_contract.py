@@ -162,6 +162,30 @@ def test_contract_long_and_tiled_rows(ctx, torch_dev):
     _case(ctx, torch_dev, g, mate2.cpu().numpy(), "hubs and bounds, solved")
 
 
+def test_contract_bucket_overflow_falls_back(ctx, torch_dev):
+    """A long row whose coarse neighbours all hash into one bucket (more
+    entries than a bucket holds in LDS): the long rows take the per-row
+    table path, with the same result."""
+    nb = 3
+    want = 1100
+    leaves = []
+    v = 2
+    while len(leaves) < want:
+        d = v - 1  # the coarse id of leaf v once vertices 0 and 1 are one pair
+        if (((d * 0x9E3779B1) & 0xFFFFFFFF) * nb) >> 32 == 0:
+            leaves.append(v)
+        v += 1
+    n = v
+    edges = [[0, 1]] + [[0, x] for x in leaves]
+    w = np.random.default_rng(3).random(len(edges)).astype(np.float32)
+    g = lmgen.from_edges(n, np.array(edges), w)
+    mate = np.full(n, -1, np.int32)
+    mate[0], mate[1] = 1, 0
+    assert (g.row_ptr[1] - g.row_ptr[0]) + (g.row_ptr[2] - g.row_ptr[1]) == want + 2  # bound 1102: 3 buckets
+    st = _case(ctx, torch_dev, g, mate, "bucket overflow")
+    assert st.long_rows == 1 and st.table_rows == 1
+
+
 def test_contract_host_buffers(ctx, torch_dev):
     g = lmgen.rmat(12, 16, seed=3, weights="uniform")
     mate, _ = oracle.local_max_graph(g, 1)
