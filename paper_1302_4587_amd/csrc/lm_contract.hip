@@ -50,6 +50,8 @@ constexpr int kCPackGrid = 4096;
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr int kLB = 512;      // average entries of a long row's bucket
 constexpr int kLBCap = 1024;  // entries a bucket may hold in LDS (more: the table path)
+constexpr int kLC = 8192;     // entries of a long row per counting / scatter chunk
+constexpr int kLHist = 4096;  // buckets a row may have for the chunks' LDS histograms
 
 constexpr unsigned kCErrMate = 1u;    // mate is not an involution with -1 for free vertices
 constexpr unsigned kCErrRowPtr = 2u;  // row_ptr is not a valid offset array
@@ -65,6 +67,7 @@ struct CTot {
   long long long_entries;  // the sum of their bounds
   long long long_slots;    // hash slots their tables take
   long long long_buckets;  // LDS-sized buckets their entries are sorted into
+  long long long_chunks;   // row-aligned chunks of kLC entries
   long long long_kept;     // their entries that are not the matched edge
   unsigned overflow;       // a bucket outgrew LDS: the long rows take the table path
   unsigned pad2;
@@ -79,6 +82,7 @@ struct LongRow {
   long long eoff;  // first flat index of the row's entries among all long rows
   long long toff;  // first slot of its table
   long long boff;  // first bucket of the row
+  long long coff;  // first chunk of the row (kLC entries each)
 };
 
 struct CArgs {
@@ -890,36 +894,41 @@ __global__ __launch_bounds__(kCTopThreads) void k_c_long_prep(CArgs a) {
   __shared__ long long sm[kCTopThreads / 64];
   if (a.tot->err) return;
   const long long nl = a.tot->nlong < a.lrow_cap ? a.tot->nlong : a.lrow_cap;
-  long long ce = 0, cs = 0, cb = 0;
+  long long ce = 0, cs = 0, cb = 0, cc = 0;
   for (long long base = 0; base < nl; base += kCTopThreads) {
     const long long i = base + threadIdx.x;
-    long long ub = 0, slots = 0, nb = 0;
+    long long ub = 0, slots = 0, nb = 0, nc = 0;
     int bits = 1;
     if (i < nl) {
       ub = a.lrows[i].ub;
       while ((1ll << bits) < 2 * ub) ++bits;
       slots = 1ll << bits;
       nb = (ub + kLB - 1) / kLB;
+      nc = (ub + kLC - 1) / kLC;
     }
-    long long te, ts, tb;
+    long long te, ts, tb, tc;
     const long long ee = top_excl_sum(ub, sm, te);
     const long long es = top_excl_sum(slots, sm, ts);
     const long long eb = top_excl_sum(nb, sm, tb);
+    const long long ec = top_excl_sum(nc, sm, tc);
     if (i < nl) {
       a.lrows[i].eoff = ce + ee;
       a.lrows[i].toff = cs + es;
       a.lrows[i].tbits = bits;
       a.lrows[i].nb = (int)nb;
       a.lrows[i].boff = cb + eb;
+      a.lrows[i].coff = cc + ec;
     }
     ce += te;
     cs += ts;
     cb += tb;
+    cc += tc;
   }
   if (threadIdx.x == 0) {
     a.tot->long_entries = ce;
     a.tot->long_slots = cs;
     a.tot->long_buckets = cb;
+    a.tot->long_chunks = cc;
   }
 }
 
@@ -1124,67 +1133,151 @@ __device__ __forceinline__ long long bucket_of(const LongRow& L, int D) {
   return L.boff + (long long)(((unsigned long long)((unsigned)D * 0x9E3779B1u) * (unsigned)L.nb) >> 32);
 }
 
+struct ChunkSmem {
+  int hist[kLHist];      // per bucket of the row: entries of the chunk, then their first record
+  unsigned erec[kLC];    // per chunk entry: bucket << 13 | rank in the bucket within the chunk
+  int row;
+};
+static_assert(kLC <= (1 << 13) && kLHist <= (1 << 19), "bucket and rank fit the packed word");
+
+// The row of long-row chunk c (largest coff <= c), found by thread 0.
+__device__ __forceinline__ int chunk_row(const CArgs& a, long long nl, long long c) {
+  long long lo = 0, hi = nl;
+  while (hi - lo > 1) {
+    const long long mid = (lo + hi) >> 1;
+    if (a.lrows[mid].coff <= c)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return (int)lo;
+}
+
 // (3b') Maps every long-row entry (its coarse neighbour into next[k], -1 for
 // the matched edge, whose output is written as dropped now) and counts the
-// buckets.
-__global__ __launch_bounds__(kBlock) void k_c_lb_count(CArgs a, long long nl, long long total) {
+// buckets. A workgroup takes a chunk of kLC entries of one row at a time and
+// counts in LDS, so each (chunk, bucket) costs one device atomic (rows with
+// more than kLHist buckets count straight in device memory).
+__global__ __launch_bounds__(kBlock) void k_c_lb_count(CArgs a, long long nl, long long nchunks) {
+  struct CountSmem {
+    int hist[kLHist];
+    int row;
+  };
+  __shared__ CountSmem sm;
   unsigned err = 0;
-  const long long step = (long long)gridDim.x * kBlock * kLI;
-  for (long long i0 = (long long)blockIdx.x * kBlock * kLI; i0 < total; i0 += step) {
-    const long long r0 = long_row_of(a.lrows, nl, i0);
-    LongAt at[kLI];
-    int x[kLI];
+  const int tid = threadIdx.x;
+  for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (tid == 0) sm.row = chunk_row(a, nl, c);
+    __syncthreads();
+    const LongRow L = a.lrows[sm.row];
+    const bool lds = L.nb <= kLHist;
+    if (lds)
+      for (int i = tid; i < L.nb; i += kBlock) sm.hist[i] = 0;
+    __syncthreads();
+    const long long e0 = (c - L.coff) * kLC;
+    const int ne = (int)min((long long)kLC, (long long)L.ub - e0);
+    const long long ka = a.rp[L.a];
+    const long long kb = L.b >= 0 ? a.rp[L.b] : 0;
+    for (int q0 = 0; q0 < ne; q0 += kBlock * kLI) {
+      long long k[kLI];
+      int x[kLI];
 #pragma unroll
-    for (int j = 0; j < kLI; ++j) {
-      const long long i = i0 + (long long)j * kBlock + threadIdx.x;
-      at[j].k = -1;
-      if (i < total) at[j] = long_at(a, nl, r0, i);
-    }
-#pragma unroll
-    for (int j = 0; j < kLI; ++j) x[j] = at[j].k >= 0 ? a.col[at[j].k] : -1;
-#pragma unroll
-    for (int j = 0; j < kLI; ++j) {
-      if (at[j].k < 0) continue;
-      int D = -1;
-      if ((unsigned)x[j] >= (unsigned)a.n)
-        err |= kCErrCol;
-      else
-        D = a.identity ? x[j] : a.cmap[x[j]];
-      const LongRow& L = a.lrows[at[j].r];
-      if (D == L.c) D = -1;
-      a.next[at[j].k] = D;
-      if (D < 0) {
-        a.scr[at[j].k] = make_int2(-1, 0);
-        continue;
+      for (int j = 0; j < kLI; ++j) {
+        const int q = q0 + j * kBlock + tid;
+        const long long off = e0 + q;
+        k[j] = q < ne ? (off < L.dega ? ka + off : kb + (off - L.dega)) : -1;
       }
-      atomicAdd((unsigned long long*)&a.bstart[bucket_of(L, D)], 1ull);
+#pragma unroll
+      for (int j = 0; j < kLI; ++j) x[j] = k[j] >= 0 ? a.col[k[j]] : -1;
+#pragma unroll
+      for (int j = 0; j < kLI; ++j) {
+        if (k[j] < 0) continue;
+        int D = -1;
+        if ((unsigned)x[j] >= (unsigned)a.n)
+          err |= kCErrCol;
+        else
+          D = a.identity ? x[j] : a.cmap[x[j]];
+        if (D == L.c) D = -1;
+        a.next[k[j]] = D;
+        if (D < 0) {
+          a.scr[k[j]] = make_int2(-1, 0);
+          continue;
+        }
+        const long long bb = bucket_of(L, D);
+        if (lds)
+          atomicAdd(&sm.hist[bb - L.boff], 1);
+        else
+          atomicAdd((unsigned long long*)&a.bstart[bb], 1ull);
+      }
     }
+    __syncthreads();
+    if (lds)
+      for (int i = tid; i < L.nb; i += kBlock)
+        if (sm.hist[i]) atomicAdd((unsigned long long*)&a.bstart[L.boff + i], (unsigned long long)sm.hist[i]);
+    __syncthreads();
   }
   if (err) atomicOr(&a.tot->err, err);
 }
 
-// (3c') Places every mapped long-row entry's index in its bucket.
-__global__ __launch_bounds__(kBlock) void k_c_lb_scatter(CArgs a, long long nl, long long total) {
-  const long long step = (long long)gridDim.x * kBlock * kLI;
-  for (long long i0 = (long long)blockIdx.x * kBlock * kLI; i0 < total; i0 += step) {
-    const long long r0 = long_row_of(a.lrows, nl, i0);
-    LongAt at[kLI];
-    int D[kLI];
+// (3c') Places every mapped long-row entry's index in its bucket: per chunk,
+// ranks within (chunk, bucket) from LDS atomics, one device atomic per
+// (chunk, bucket) for the range, then the writes.
+__global__ __launch_bounds__(kBlock) void k_c_lb_scatter(CArgs a, long long nl, long long nchunks) {
+  __shared__ ChunkSmem sm;
+  const int tid = threadIdx.x;
+  for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (tid == 0) sm.row = chunk_row(a, nl, c);
+    __syncthreads();
+    const LongRow L = a.lrows[sm.row];
+    const bool lds = L.nb <= kLHist;
+    if (lds)
+      for (int i = tid; i < L.nb; i += kBlock) sm.hist[i] = 0;
+    __syncthreads();
+    const long long e0 = (c - L.coff) * kLC;
+    const int ne = (int)min((long long)kLC, (long long)L.ub - e0);
+    const long long ka = a.rp[L.a];
+    const long long kb = L.b >= 0 ? a.rp[L.b] : 0;
+    auto kof = [&](int q) {
+      const long long off = e0 + q;
+      return off < L.dega ? ka + off : kb + (off - L.dega);
+    };
+    for (int q0 = 0; q0 < ne; q0 += kBlock * kLI) {
+      int D[kLI];
 #pragma unroll
-    for (int j = 0; j < kLI; ++j) {
-      const long long i = i0 + (long long)j * kBlock + threadIdx.x;
-      at[j].k = -1;
-      if (i < total) at[j] = long_at(a, nl, r0, i);
+      for (int j = 0; j < kLI; ++j) {
+        const int q = q0 + j * kBlock + tid;
+        D[j] = q < ne ? a.next[kof(q)] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kLI; ++j) {
+        const int q = q0 + j * kBlock + tid;
+        if (D[j] < 0) {
+          if (lds && q < ne) sm.erec[q] = ~0u;  // the matched edge: no record
+          continue;
+        }
+        const long long bb = bucket_of(L, D[j]);
+        if (lds) {
+          const int lb = (int)(bb - L.boff);
+          sm.erec[q] = ((unsigned)lb << 13) | (unsigned)atomicAdd(&sm.hist[lb], 1);
+        } else {
+          a.rec[a.bstart[bb] + atomicAdd(&a.bfill[bb], 1)] = (int)kof(q);
+        }
+      }
     }
-#pragma unroll
-    for (int j = 0; j < kLI; ++j) D[j] = at[j].k >= 0 ? a.next[at[j].k] : -1;
-#pragma unroll
-    for (int j = 0; j < kLI; ++j) {
-      if (D[j] < 0) continue;
-      const long long b = bucket_of(a.lrows[at[j].r], D[j]);
-      const long long pos = a.bstart[b] + atomicAdd(&a.bfill[b], 1);
-      a.rec[pos] = (int)at[j].k;
+    if (lds) {
+      __syncthreads();
+      for (int i = tid; i < L.nb; i += kBlock) {
+        const int h = sm.hist[i];
+        if (h) sm.hist[i] = (int)(a.bstart[L.boff + i] + atomicAdd(&a.bfill[L.boff + i], h));
+      }
+      __syncthreads();
+      for (int q = tid; q < ne; q += kBlock) {
+        const unsigned r = sm.erec[q];
+        if (r == ~0u) continue;
+        a.rec[sm.hist[r >> 13] + (int)(r & 8191u)] = (int)kof(q);
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -1657,9 +1750,11 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
     LMC_HIP(hipMemsetAsync(a.bstart, 0, sizeof(long long) * (size_t)(nbk + 1), s));
     LMC_HIP(hipMemsetAsync(a.bfill, 0, sizeof(int) * (size_t)nbk, s));
     const long long lg = std::min<long long>((t1.long_entries + kBlock * kLI - 1) / (kBlock * kLI), 16384);
-    hipLaunchKernelGGL(k_c_lb_count, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
+    const long long nch = t1.long_chunks;
+    const long long cgd = std::max<long long>(1, std::min<long long>(nch, (long long)S.num_cus * 8));
+    hipLaunchKernelGGL(k_c_lb_count, dim3((unsigned)cgd), dim3(kBlock), 0, s, a, nl, nch);
     hipLaunchKernelGGL(k_c_scan_top, dim3(1), dim3(kCTopThreads), 0, s, a.bstart, nbk + 1, &a.tot->long_kept);
-    hipLaunchKernelGGL(k_c_lb_scatter, dim3((unsigned)lg), dim3(kBlock), 0, s, a, nl, t1.long_entries);
+    hipLaunchKernelGGL(k_c_lb_scatter, dim3((unsigned)cgd), dim3(kBlock), 0, s, a, nl, nch);
     const long long gg = std::max<long long>(1, std::min<long long>(nbk, (long long)S.num_cus * 8));
     hipLaunchKernelGGL(k_c_lb_group, dim3((unsigned)gg), dim3(kBlock), 0, s, a, nl, nbk);
     LMC_HIP(hipGetLastError());
