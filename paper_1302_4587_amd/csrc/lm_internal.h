@@ -92,7 +92,18 @@ struct Totals {
   int t;    // current phase (1-based): read by the mutual check, advanced by the plan kernel
   int tail_from;  // guarded phases: the live set R_t the tail kernel takes over (0 = none yet)
   unsigned long long fp[2];  // LM_CHECK_GRAPH: fingerprints of the entries and of their mirrors
+  unsigned far, samp;        // sampled first entries of R_1 whose neighbour id is far from the row's
 };
+
+// One graph whose neighbour ids are mostly far from their row's id (sampled
+// by k_init): the mutual check also sets a bit per matched vertex and the
+// compactions read a neighbour's matched state from these bits (N / 8 bytes,
+// which stay in L2) instead of the byte array.
+constexpr long long kBitsMinN = 1ll << 22;  // smaller state arrays fit L2 as bytes
+constexpr unsigned kFarIds = 1u << 15;      // "far": |u - v| at least this
+__host__ __device__ __forceinline__ bool bits_on(const Totals* t) {
+  return t->samp > 0 && 4ull * t->far > 3ull * t->samp;
+}
 
 // What the host loop needs after each plan, written by the plan kernel into
 // mapped coherent pinned host memory: the record is stored, made visible to
@@ -141,6 +152,8 @@ struct Common {
   int graphs;                       // 1: every piece belongs to graph 0 (no table lookups)
   int guard = 0;                    // phase kernels of a device-controlled solve: do nothing
                                     // once the tail kernel has taken the live set over
+  unsigned* mbits = nullptr;        // matched bits (one graph, N >= kBitsMinN): cleared by k_init,
+                                    // set by the mutual check while bits_on(totals)
   int renew = 0;                    // renewed keys: the candidates of phase t break ties with
                                     // phase_seed(seed, t) instead of the seed
 };
@@ -236,6 +249,7 @@ struct InitArgs {
   int rows_base, runs_base;
   Run* runs_out;
   int4* rows_out;
+  const int* col = nullptr;  // with c.mbits: the input column ids, for the locality sample
   int csr;           // 1: no piece records (R_1 read from the CSR): C[v] = -1 for every vertex,
                      // bstat[b].pieces_out = non-empty rows of workgroup b
   BlockStat* bstat;
@@ -307,6 +321,7 @@ struct CheckArgs {
 
 hipError_t launch_zero(Ctl* ctl, int nctl, Totals* totals, hipStream_t s, TailCtl* tc = nullptr);
 hipError_t launch_fill_i32(int* p, long long n, int value, hipStream_t s);
+
 hipError_t launch_add_i64(long long* p, long long n, long long delta, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, int grid, hipStream_t s);
 // Optional ev[2] = {start, stop} timing events: recorded by the dispatch itself

@@ -51,6 +51,8 @@ __global__ void k_zero(Ctl* ctl, int nctl, Totals* totals, TailCtl* tc) {
     totals->tail_from = 0;
     totals->fp[0] = 0;
     totals->fp[1] = 0;
+    totals->far = 0;
+    totals->samp = 0;
   }
 }
 
@@ -197,6 +199,18 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
       }
       const unsigned long long bal = __ballot(ok);
       rank[jj] = (unsigned)__popcll(bal & lt);
+      if (jj == 0 && c0 == vb && a.col && a.c.mbits && wv == 0 && (b & 15) == 0) {
+        // locality sample: the first entry of the non-empty rows of the first
+        // wave of every 16th workgroup (two same-address atomics per wave)
+        const long long vgs = a.vfirst + v;
+        const int u = ok ? a.col[r0[0]] : 0;
+        const long long dist = (long long)u - vgs;
+        const unsigned long long farb = __ballot(ok && (dist >= (long long)kFarIds || dist <= -(long long)kFarIds));
+        if (lane == 0 && bal) {
+          atomicAdd(&a.c.totals->far, (unsigned)__popcll(farb));
+          atomicAdd(&a.c.totals->samp, (unsigned)__popcll(bal));
+        }
+      }
       if (lane == 0) s_cnt[jj * kWaves + wv] = (unsigned)__popcll(bal);
       okm |= (ok ? 1u : 0u) << jj;
     }
@@ -215,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a) {
         const long long vg = a.vfirst + v;
         a.c.mate[vg] = -1;
         a.c.state[vg] = 0;
+        if (a.c.mbits && (vg & 31) == 0) a.c.mbits[vg >> 5] = 0u;
         if (a.csr) {
           a.c.C[vg] = -1;  // the mutual check reads C of every vertex, empty rows too
         } else if ((okm >> jj) & 1u) {
@@ -495,6 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
   __shared__ unsigned s32[kWaves];
   __shared__ RunCache rc;
   if (block_failed(a.c, &s_err)) return;
+  const bool use_bits = a.c.mbits != nullptr && bits_on(a.c.totals);
   const Ctl ctl = *a.in.ctl;
   const int t = a.c.totals->t;
   // R_1 read from the CSR: piece k is vertex k, every vertex is its own head,
@@ -555,6 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_mutual(MutualArgs a) {
             const int g = rec[i].w & kGraphMask;
             a.c.mate[v] = cv[i] - a.c.gbase[g];
             a.c.state[v] = 1;
+            if (use_bits) atomicOr(&a.c.mbits[v >> 5], 1u << (v & 31));
             if (!csr) a.in.rows[row[i]].w = rec[i].w | kMatchedBit;
             ++cnt;
           }
@@ -757,6 +774,8 @@ template <bool FIRST, int PPL, bool UNW, int VIEW>
 __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamSmem<kBlock * PPL, stream_items<FIRST, UNW>()>& sm,
                              unsigned long long seed0) {
   constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f (0x3f800000 | sign bit)
+  // neighbour state from the matched bits (scattered ids of one large graph)
+  const bool use_bits = !FIRST && a.c.mbits != nullptr && bits_on(a.c.totals);
   constexpr int kItems = stream_items<FIRST, UNW>();  // (shadows the defaults of the other kernels)
   constexpr int kCap = kBlock * kItems;
   constexpr int kPPL = PPL;
@@ -1015,7 +1034,10 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
       unsigned char st[kItems];
       if (!FIRST) {
 #pragma unroll
-        for (int jj = 0; jj < kItems; ++jj) st[jj] = a.c.state[ok[jj] ? ug[jj] : 0u];
+        for (int jj = 0; jj < kItems; ++jj) {
+          const unsigned uu = ok[jj] ? ug[jj] : 0u;
+          st[jj] = use_bits ? (unsigned char)((a.c.mbits[uu >> 5] >> (uu & 31u)) & 1u) : a.c.state[uu];
+        }
       }
       unsigned rank[kItems];
       unsigned kpm = 0;

@@ -54,6 +54,7 @@ struct Work {
   long long* vtxoff = nullptr;
   Totals* totals = nullptr;
   TailCtl* tail = nullptr;
+  unsigned* mbits = nullptr;  // matched bits, (N + 31) / 32 words
 };
 
 // Lays the working buffers of a solve of N vertices, nnz entries and G graphs
@@ -95,7 +96,7 @@ struct Solver {
 
   DevBuf C, state, rows[2], ecol[2], ew[2], runs[2], epre[2], rpre[2];
   DevBuf ctl, parts, bstat, mcount;
-  DevBuf gbase, gseed, vtxoff, gphase, totals, tailc;
+  DevBuf gbase, gseed, vtxoff, gphase, totals, tailc, mbits;
   DevBuf in_rp, in_col, in_w, out_mate;
   DevBuf wsum;  // kWeightSumMaxGrid partial sums, then the total
   ContractState* contract = nullptr;

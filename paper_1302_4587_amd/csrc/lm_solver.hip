@@ -82,6 +82,7 @@ size_t solve_footprint(int64_t N, int64_t nnz, int64_t G) {
   size_t b = 0;
   b += (size_t)N * 4 + 256;                                // C
   b += (size_t)N + 256;                                    // state
+  b += (size_t)((N + 31) / 32 + 16) * 4 + 256;             // matched bits
   b += 2 * (((size_t)N + 2 * kMaxBlocks + 16) * 16 + 256); // piece buffers
   b += 2 * 2 * ((size_t)nnz * 4 + 256);                    // entry ping-pong (col, w)
   b += 2 * ((size_t)kMaxBlocks * (sizeof(Run) + 8 + 4) + 1024);
@@ -122,6 +123,7 @@ lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
   if (want_gphase) RES(gphase, (size_t)G * 4);
   RES(totals, sizeof(Totals));
   RES(tailc, sizeof(TailCtl));
+  RES(mbits, (size_t)((N + 31) / 32 + 16) * 4);
 #undef RES
   return LM_OK;
 }
@@ -147,6 +149,7 @@ Work Solver::pool_work() const {
   w.vtxoff = (long long*)vtxoff.p;
   w.totals = (Totals*)totals.p;
   w.tail = (TailCtl*)tailc.p;
+  w.mbits = (unsigned*)mbits.p;
   return w;
 }
 
@@ -177,6 +180,7 @@ size_t carve_work(int64_t N, int64_t nnz, int64_t G, void* base, Work* w) {
   x.vtxoff = (long long*)take((size_t)(G + 1) * 8);
   x.totals = (Totals*)take(sizeof(Totals));
   x.tail = (TailCtl*)take(sizeof(TailCtl));
+  x.mbits = (unsigned*)take((size_t)((N + 31) / 32 + 16) * 4);
   if (w) *w = x;
   return off;
 }
@@ -234,7 +238,7 @@ void Solver::shutdown() {
   DevBuf* all[] = {&C,       &state,   &rows[0], &rows[1], &ecol[0], &ecol[1], &ew[0],   &ew[1],
                    &runs[0], &runs[1], &epre[0], &epre[1], &rpre[0], &rpre[1], &ctl,     &parts,
                    &bstat,   &mcount,  &gbase,   &gseed,   &vtxoff,  &gphase,  &totals,  &in_rp,
-                   &in_col,  &in_w,    &out_mate, &wsum,   &tailc};
+                   &in_col,  &in_w,    &out_mate, &wsum,   &tailc,   &mbits};
   for (DevBuf* b : all) pool.release(*b);
   contract_release(*this);
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
@@ -335,6 +339,9 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
   c.graphs = (int)p.G;
   c.guard = 0;
   c.renew = (flags & LM_RENEW_KEYS) ? 1 : 0;
+  // one large graph: the compactions may read the matched state from bits,
+  // if k_init's sample finds its neighbour ids scattered
+  c.mbits = (p.G == 1 && p.N >= kBitsMinN) ? wk.mbits : nullptr;
   // A device-controlled solve (LM_GRAPH, LM_ASYNC) enqueues a fixed number of
   // guarded phases and then the tail kernel; the plan that produces a live set
   // of at most tail_at entries hands it to the tail, and the guarded phases
@@ -409,6 +416,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     ia.runs_out = wk.runs[0];
     ia.rows_out = wk.rows[0];
     ia.csr = csr1 ? 1 : 0;
+    ia.col = c.mbits ? p.col : nullptr;
     ia.bstat = wk.bstat;
     ENQ(launch_init(ia, s, timing(LM_K_INIT)));
     PlanArgs pa = plan_base();  // R_1: split for the first compaction and, apart, the first argmax

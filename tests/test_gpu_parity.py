@@ -194,6 +194,26 @@ def test_tuning_invariance(ctx, torch_dev, block_entries):
         ctx.set_tuning(**base)
 
 
+@pytest.mark.parametrize("kind", ["rmat22", "rgg22"])
+def test_large_graph_matched_bits(ctx, torch_dev, kind):
+    """At 2^22 vertices and more the compactions of one graph read the matched
+    state from bits when k_init's sample finds the neighbour ids scattered
+    (R-MAT) and from the byte array when they are local (RGG): both equal the
+    oracle, in the host-polled and the captured solve."""
+    import torch
+    g = lmgen.rmat(22, 16, seed=3) if kind == "rmat22" else lmgen.rgg(1 << 22, 10.0, seed=3)
+    unw = kind == "rmat22"
+    gg = lmgen.Graph(g.n, g.row_ptr, g.col, np.ones(g.nnz, np.float32)) if unw else g
+    ref_mate, ref_log = oracle.local_max_graph(gg, 2)
+    rp, col = (torch.from_numpy(x).to(torch_dev) for x in (g.row_ptr, g.col))
+    w = None if unw else torch.from_numpy(g.w).to(torch_dev)
+    for kw in ({}, {"hip_graph": True}):
+        print(f"case: {kind} {kw}", flush=True)
+        mate, st = ctx.match(rp, col, w, seed=2, **kw)
+        assert np.array_equal(mate.cpu().numpy(), ref_mate), f"{kind} {kw}"
+        assert st.phases == len(ref_log)
+
+
 def test_edge_cases(ctx, torch_dev):
     cases = [
         ("isolated", lmgen.from_edges(7, np.zeros((0, 2)), np.zeros(0))),
