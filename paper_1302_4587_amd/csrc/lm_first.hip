@@ -1,6 +1,6 @@
-// First argmax of a single weighted graph read straight from its CSR (R_1),
-// gfx950. (Unweighted graphs keep the piece-window kernel of lm_kernels.hip,
-// which measured faster on R-MAT scale 24: 2.5 ms against 3.2 ms.)
+// First argmax of a single graph read straight from its CSR (R_1), gfx950:
+// k_first_csr for a weighted graph, k_first_unw (further below) for an
+// unweighted one.
 //
 // Every vertex v with a live entry gets C[v] = the neighbour u maximising the
 // key (w, H(seed, lo, hi)) over its row (Section 2, first pass of the
@@ -14,8 +14,9 @@
 // largest ordered weight first, then the largest hash among the segments
 // that reach it; the winner is the neighbour whose hash that is (the hash is
 // a bijection of the neighbour for a fixed vertex). An unweighted graph skips
-// the weight pass. Rows cut at range boundaries leave a partial result for
-// the plan kernel, as the other stream kernels do.
+// the weight pass (k_first_unw is faster for those). Rows cut at range
+// boundaries leave a partial result for the plan kernel, as the other stream
+// kernels do.
 #include <hip/hip_ext.h>
 
 #include "lm_device.h"
@@ -325,6 +326,364 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
   __syncthreads();
 }
 
+// ---- unweighted first argmax of one graph: one wave per range ----
+//
+// Every entry is a candidate (all weights tie), so the row's winner is the
+// neighbour of largest hash. A one-wave workgroup walks its range of R_1 in
+// steps of kUStep consecutive entries, four per lane (one 16-byte load, the
+// next step's issued before the current one is hashed). The rows of a step
+// come from a window of 64 consecutive row ends held one per lane (the next
+// 64 are loaded while this window is in use): a step never passes the
+// window's last row. When the whole step lies in one row (long rows) every
+// lane only folds its hashes into a running maximum held in registers; the
+// row's lanes are combined once, when it ends. Otherwise each entry's row is
+// found from boundary markers in LDS (a max-scan over the step), and every
+// row that ends inside the step is combined by LDS 64-bit atomic max in a
+// slot of its window row; the row still open at the step's end stays in
+// the registers. No workgroup barrier couples waves.
+constexpr int kUIt = 4;                // entries per lane per step
+constexpr int kUStep = 64 * kUIt;      // entries per step
+static_assert(kUIt % 4 == 0, "entries are loaded 16 bytes at a time");
+constexpr int kUnwPerCu = 32;          // one-wave ranges per CU (8 per SIMD: at most 64 VGPRs)
+constexpr int kUSlots = 65;            // 64 window rows + the open row of the previous step
+
+struct UnwSmem {
+  unsigned mark[kUStep];               // 1 + window index of the row starting at step position x, 0 none
+  unsigned long long slot[kUSlots];    // largest hash per row combined in LDS
+  unsigned hit[kUSlots];               // the slot holds a hash
+};
+
+// Smallest i in [lo, hi) with pred(i) true (pred monotone), hi if none; every
+// lane gets the answer. 64 points per round, one memory access per lane.
+template <typename Pred>
+__device__ __forceinline__ long long wave_lower_bound(long long lo, long long hi, Pred pred) {
+  const int lane = lane_id();
+  while (hi > lo) {
+    const long long n = hi - lo;
+    const long long step = (n + 63) >> 6;
+    const long long idx = lo + (long long)lane * step;
+    const bool p = idx < hi ? pred(idx) : true;
+    const unsigned long long bal = __ballot(p);
+    if (bal == 0ull) {  // false at every sampled point: the answer lies past the last one
+      lo = lo + 63 * step + 1;
+      continue;
+    }
+    const int f = __ffsll((long long)bal) - 1;
+    if (f == 0) return lo;
+    // false at lo + (f-1) step, true at lo + f step (or that point is past hi)
+    const long long nhi = lo + (long long)f * step < hi ? lo + (long long)f * step : hi;
+    lo = lo + (long long)(f - 1) * step + 1;
+    hi = nhi;
+  }
+  return lo;
+}
+
+// The entry position of cost c over R_1 read from the CSR (the split of the
+// other first-argmax kernels: kPieceCostFirst units per row, one per entry).
+__device__ __forceinline__ long long wave_csr_entry_at(const long long* rp, long long n, long long c) {
+  constexpr long long K = kPieceCostFirst;
+  const long long v1 = wave_lower_bound(0, n + 1, [&](long long v) { return rp[v] + K * v > c; });
+  const long long v = v1 - 1;
+  const long long u = c - (rp[v] + K * v);
+  if (u < K || v >= n) return rp[v];
+  const long long deg = rp[v + 1] - rp[v];
+  return rp[v] + min(u - K, deg);
+}
+
+struct UnwCols {
+  int c[kUIt];
+};
+
+// The lane's kUIt entries of the step starting at s with 16-byte loads
+// (the caller guarantees alignment and s + kUStep <= nnz).
+__device__ __forceinline__ UnwCols unw_load_vec(const int* col, long long s) {
+  const long long q = s + kUIt * lane_id();
+  UnwCols r;
+#pragma unroll
+  for (int j = 0; j < kUIt; j += 4) {
+    const int4 x = *reinterpret_cast<const int4*>(col + q + j);
+    r.c[j] = x.x;
+    r.c[j + 1] = x.y;
+    r.c[j + 2] = x.z;
+    r.c[j + 3] = x.w;
+  }
+  return r;
+}
+
+// The same one entry at a time, clamped to the last entry (positions past
+// E1 are never used; nnz > 0 since the range is not empty).
+__device__ __forceinline__ UnwCols unw_load_slow(const int* col, long long s, long long nnz) {
+  const long long q = s + kUIt * lane_id();
+  UnwCols r;
+#pragma unroll
+  for (int j = 0; j < kUIt; ++j) r.c[j] = col[min(q + j, nnz - 1)];
+  return r;
+}
+
+__device__ __forceinline__ Part unw_part(long long v, int flags, bool any, unsigned long long h,
+                                         unsigned long long S) {
+  constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f
+  Part p;
+  p.v = (int)v;
+  p.flags = flags;
+  p.kept = 0;
+  p.out_row = -1;
+  p.w = any ? kUnitOrd : 0u;
+  p.hhi = any ? (unsigned)(h >> 32) : 0u;
+  p.hlo = any ? (unsigned)h : 0u;
+  p.u = any ? hash_neighbour(h, S, (unsigned)v) : -1;
+  return p;
+}
+
+// The workgroup is one wave: LDS accesses of its lanes are carried out in
+// issue order, so lanes exchange data through LDS with no s_barrier and no
+// wait for the stores; this only keeps the compiler from moving LDS accesses
+// across the point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One lane to the left across the wave (lane 63 gets ident).
+__device__ __forceinline__ unsigned dpp_wave_shl1(unsigned x, unsigned ident) {
+  return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x130, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ long long rdl64(long long x, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)x >> 32), l);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// VEC: 16-byte loads (an aligned entry array of at least kUStep entries);
+// otherwise every step loads its entries one by one.
+template <bool VEC>
+__device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, UnwSmem& sm, unsigned long long S) {
+  const int lane = lane_id();
+  const long long* rp = a.in.csr_rp;
+  const int* col = a.in.col;
+  int* C = a.c.C;
+  const long long n = ctl.pieces;
+  const long long nnz = rp[n];
+  const long long cost = ctl.L + (long long)kPieceCostFirst * n;
+  const long long E0 = wave_csr_entry_at(rp, n, cost * b / P);
+  const long long E1 = wave_csr_entry_at(rp, n, cost * (b + 1) / P);
+  Part pf, pl;
+  pf.v = pl.v = -1;
+  pf.flags = pl.flags = 0;
+  pf.kept = pl.kept = 0;
+  pf.out_row = pl.out_row = -1;
+  pf.w = pl.w = pf.hhi = pl.hhi = pf.hlo = pl.hlo = 0u;
+  pf.u = pl.u = -1;
+  if (E0 < E1) {
+    // the row holding E0 (empty rows before it are skipped)
+    const long long v0 = wave_lower_bound(0, n, [&](long long v) { return rp[v + 1] > E0; });
+    const bool cut_left = rp[v0] < E0;
+    long long R0 = v0 & ~63ll;                      // window: rows R0 .. R0 + 63, lane i holds the end of row R0 + i
+    long long ce = rp[min(R0 + lane + 1, n)];
+    long long ne = rp[min(R0 + 64 + lane + 1, n)];  // the next window
+    long long pos = E0;
+    long long orow = -1;                            // the row open at the end of the previous step
+    unsigned long long acc = 0ull;                  // the lane's largest hash in it
+    bool ahit = false;
+    // a row of the range is finished: its winner, or its part when it began before E0
+    auto finish = [&](long long r, bool any, unsigned long long h) {
+      if (r == v0 && cut_left) {
+        pf = unw_part(r, 0, any, h, S);
+      } else if (any && lane == 0) {
+        C[r] = hash_neighbour(h, S, (unsigned)r);
+      }
+    };
+    // one step over the entries cv holds (loaded by the step before); the
+    // next step's entries are loaded into nxt first. Two buffers alternate,
+    // so a load in flight is never copied (a copy would wait for it).
+    auto step = [&](UnwCols& cv, bool cvfast, UnwCols& nxt, bool& nxfast) {
+      if (pos >= rdl64(ce, 63)) {  // the row of pos lies past the window
+        R0 += 64;
+        ce = ne;
+        ne = rp[min(R0 + 64 + lane + 1, n)];
+        while (pos >= rdl64(ce, 63)) {  // (64 or more empty rows)
+          R0 += 64;
+          ce = rp[min(R0 + lane + 1, n)];
+          ne = rp[min(R0 + 64 + lane + 1, n)];
+        }
+      }
+      const long long s = pos & ~3ll;
+      const long long se = min(min(s + kUStep, E1), rdl64(ce, 63));
+      // The next step's entries are loaded before this step's are used, by
+      // the same single load on every path (a load on some paths only makes
+      // every use wait for all loads): at the range's end, or where 16-byte
+      // loads would not do, it reads the first kUStep entries instead and
+      // the next step loads its own entries one by one, before that load.
+      const long long sn = min(se, E1 - 1) & ~3ll;
+      if (VEC) {
+        if (!cvfast) cv = unw_load_slow(col, s, nnz);
+        nxfast = sn + kUStep <= nnz;
+        nxt = unw_load_vec(col, nxfast ? sn : 0ll);
+      } else {
+        nxt = unw_load_slow(col, sn, nnz);
+      }
+      const int xlo = (int)(pos - s), xhi = (int)(se - s);  // valid step positions [xlo, xhi)
+      const int rpos = __popcll(__ballot(ce <= pos));       // window row of pos
+      const int rlast = __popcll(__ballot(ce < se));        // window row of se - 1
+      const bool carry = orow >= 0 && orow != R0 + rpos;    // the open row ended at pos
+      if (rpos == rlast && !carry) {
+        // ---- the step lies in one row: fold into the running maximum
+        const unsigned v = (unsigned)(R0 + rpos);
+#pragma unroll
+        for (int j = 0; j < kUIt; ++j) {
+          const int x = kUIt * lane + j;
+          const bool ok = x >= xlo && x < xhi && (unsigned)cv.c[j] < (unsigned)n;
+          const unsigned long long h = edge_hash(S, v, (unsigned)cv.c[j]);
+          acc = ok && h > acc ? h : acc;
+          ahit = ahit || ok;
+        }
+        orow = R0 + rpos;
+      } else {
+        // ---- rows from the boundary markers (all zero between steps)
+        if (carry) {  // the previous step's open row: its lanes meet in slot 64
+          if (ahit) atomicMax(&sm.slot[64], acc);
+          if (ahit) sm.hit[64] = 1u;
+        }
+        {
+          // row R0 + lane + 1 starts at ce; only the last of several rows
+          // starting there (the others are empty) marks it
+          const long long cn = (long long)(((unsigned long long)dpp_wave_shl1((unsigned)((unsigned long long)ce >> 32), 0u) << 32) |
+                                           dpp_wave_shl1((unsigned)ce, 0u));
+          const bool last_start = lane == 63 || cn > ce;
+          if (ce > pos && ce < se && last_start) sm.mark[(int)(ce - s)] = (unsigned)(lane + 2);
+        }
+        wave_lds_sync();
+        unsigned m[kUIt];
+#pragma unroll
+        for (int j = 0; j < kUIt; j += 4) {
+          const uint4 mk = *reinterpret_cast<const uint4*>(&sm.mark[kUIt * lane + j]);
+          m[j] = mk.x;
+          m[j + 1] = mk.y;
+          m[j + 2] = mk.z;
+          m[j + 3] = mk.w;
+          *reinterpret_cast<uint4*>(&sm.mark[kUIt * lane + j]) = make_uint4(0u, 0u, 0u, 0u);  // (the lane's own)
+        }
+#pragma unroll
+        for (int j = 1; j < kUIt; ++j) m[j] = max(m[j], m[j - 1]);
+        const unsigned incl = wave_incl_max_u32(m[kUIt - 1]);
+        const unsigned excl = dpp_wave_shr1(incl, 0u);
+        int rr[kUIt];
+        unsigned long long hv[kUIt];
+        bool okv[kUIt];
+#pragma unroll
+        for (int j = 0; j < kUIt; ++j) {
+          const unsigned mm = max(excl, m[j]);
+          rr[j] = max(rpos, (int)mm - 1);  // window row of the entry
+          const int x = kUIt * lane + j;
+          okv[j] = x >= xlo && x < xhi && (unsigned)cv.c[j] < (unsigned)n;
+          hv[j] = edge_hash(S, (unsigned)(R0 + rr[j]), (unsigned)cv.c[j]);
+        }
+        // the step's last row stays open in the registers; earlier rows go
+        // to their slots, one LDS atomic per run of the lane
+        unsigned long long accl = 0ull, runh = 0ull;
+        bool hitl = false, runok = false;
+        int runr = -1;
+#pragma unroll
+        for (int j = 0; j < kUIt; ++j) {
+          const bool ok = okv[j];
+          if (rr[j] == rlast) {
+            accl = ok && hv[j] > accl ? hv[j] : accl;
+            hitl = hitl || ok;
+          } else {
+            if (rr[j] != runr) {
+              if (runok) {
+                atomicMax(&sm.slot[runr], runh);
+                sm.hit[runr] = 1u;
+              }
+              runr = rr[j];
+              runh = 0ull;
+              runok = false;
+            }
+            runh = ok && hv[j] > runh ? hv[j] : runh;
+            runok = runok || ok;
+          }
+        }
+        if (!carry && ahit) {  // the lane's running maximum belongs to the row of pos, which ends here
+          if (runr == rpos) {
+            runh = acc > runh ? acc : runh;
+            runok = true;
+          } else {
+            atomicMax(&sm.slot[rpos], acc);
+            sm.hit[rpos] = 1u;
+          }
+        }
+        if (runok) {
+          atomicMax(&sm.slot[runr], runh);
+          sm.hit[runr] = 1u;
+        }
+        wave_lds_sync();
+        // rows of the window that ended inside the step: rpos .. rlast - 1
+        if (carry) {
+          const bool any = sm.hit[64] != 0u;
+          const unsigned long long h = sm.slot[64];
+          finish(orow, any, h);
+        }
+        if (rpos < rlast) {
+          // (the row of pos finishes here when the step goes past it)
+          const bool mine = lane >= rpos && lane < rlast;
+          const bool any = mine && sm.hit[lane] != 0u;
+          const unsigned long long h = any ? sm.slot[lane] : 0ull;
+          const long long r = R0 + lane;
+          const bool firstcut = r == v0 && cut_left;
+          if (any && !firstcut) C[r] = hash_neighbour(h, S, (unsigned)r);
+          if (__ballot(mine && firstcut) != 0ull) {  // v0 is in this window: its part
+            const int l0 = (int)(v0 - R0);
+            const bool a0 = __builtin_amdgcn_readlane((int)(any ? 1 : 0), l0) != 0;
+            const unsigned long long h0 =
+                ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(h >> 32), l0) << 32) |
+                (unsigned)__builtin_amdgcn_readlane((int)(unsigned)h, l0);
+            pf = unw_part(v0, 0, a0, h0, S);
+          }
+          if (mine) {
+            sm.slot[lane] = 0ull;
+            sm.hit[lane] = 0u;
+          }
+        }
+        if (carry && lane == 0) {
+          sm.slot[64] = 0ull;
+          sm.hit[64] = 0u;
+        }
+        wave_lds_sync();  // the cleared slots before the next step's atomics
+        acc = accl;
+        ahit = hitl;
+        orow = R0 + rlast;
+      }
+      pos = se;
+    };
+    bool fastA = VEC && (pos & ~3ll) + kUStep <= nnz, fastB = false;
+    UnwCols bufA = VEC ? unw_load_vec(col, fastA ? pos & ~3ll : 0ll) : unw_load_slow(col, pos & ~3ll, nnz), bufB;
+    for (;;) {
+      step(bufA, fastA, bufB, fastB);
+      if (pos >= E1) break;
+      step(bufB, fastB, bufA, fastA);
+      if (pos >= E1) break;
+    }
+    // the row open at the range's end
+    const bool any = __ballot(ahit) != 0ull;
+    const unsigned long long h = any ? wave_max_u64(ahit ? acc : 0ull) : 0ull;
+    const long long er = rp[orow + 1];
+    const bool cl = orow == v0 && cut_left;
+    if (er > E1) {  // it goes on past the range
+      const Part p = unw_part(orow, cl ? kPartSingle : 0, any, h, S);
+      if (cl) pf = p;
+      else pl = p;
+    } else {
+      finish(orow, any, h);
+    }
+  }
+  if (lane == 0) {
+    a.parts[2 * b] = pf;
+    a.parts[2 * b + 1] = pl;
+  }
+}
+
 }  // namespace
 
 template <bool UNW>
@@ -349,6 +708,49 @@ hipError_t launch_first_csr(const StreamArgs& a, int grid, hipStream_t s, bool u
     else hipLaunchKernelGGL(k_first_csr<false>, dim3(grid), dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(64) void k_first_unw(StreamArgs a) {
+  __shared__ UnwSmem sm;
+  if (a.c.totals->err) return;
+  Ctl ctl = *a.in.ctl;
+  const int P = ctl.Pf > 0 ? ctl.Pf : ctl.P;  // the first argmax's own split of R_1
+  const unsigned long long S = cand_seed(a.c.gseed[0], a.c.renew, a.cand_phase);
+  for (int i = lane_id(); i < kUSlots; i += 64) {
+    sm.slot[i] = 0ull;
+    sm.hit[i] = 0u;
+  }
+  for (int i = lane_id(); i < kUStep; i += 64) sm.mark[i] = 0u;
+  __syncthreads();
+  for (int b = blockIdx.x; b < P; b += gridDim.x) unw_range<VEC>(a, ctl, P, b, sm, S);
+}
+
+// vec_ok: the entry array is 16-byte aligned and holds at least kUStep
+// entries (what a step's placeholder load reads).
+hipError_t launch_first_unw(const StreamArgs& a, int grid, hipStream_t s, bool vec_ok, hipEvent_t* ev) {
+  if (vec_ok) {
+    if (ev) hipExtLaunchKernelGGL(k_first_unw<true>, dim3(grid), dim3(64), 0, s, ev[0], ev[1], 0, a);
+    else hipLaunchKernelGGL(k_first_unw<true>, dim3(grid), dim3(64), 0, s, a);
+  } else {
+    if (ev) hipExtLaunchKernelGGL(k_first_unw<false>, dim3(grid), dim3(64), 0, s, ev[0], ev[1], 0, a);
+    else hipLaunchKernelGGL(k_first_unw<false>, dim3(grid), dim3(64), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+int first_unw_min_entries() { return kUStep; }
+
+// kUnwPerCu, or fewer if the kernels' registers leave fewer waves resident
+// (every range's wave is resident from the start).
+int first_unw_ranges_per_cu() {
+  int n1 = 0, n0 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, k_first_unw<true>, 64, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n0, k_first_unw<false>, 64, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return std::max(1, std::min(kUnwPerCu, std::min(n1, n0)));
 }
 
 int first_csr_blocks_per_cu(bool unweighted) {

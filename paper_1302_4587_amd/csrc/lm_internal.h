@@ -34,6 +34,7 @@ constexpr int kLatePPLUnw = 2;              // the same for unweighted graphs (e
 constexpr int late_ppl(bool unweighted) { return unweighted ? kLatePPLUnw : kLatePPL; }
 constexpr int kMutualRound = kBlock * 4;    // pieces per mutual-check round of a workgroup
 constexpr int kMaxBlocks = 4096;       // run table capacity
+constexpr int kMaxFirstRanges = 8192;  // ranges of a first argmax (partial-result capacity)
 constexpr int kPieceCost = 8;          // entries one piece weighs when R_1 is split from the CSR (compaction)
 constexpr int kPieceCostFirst = 4;     // the same for the first argmax (measured on R-MAT and RGG)
 constexpr int kPlanThreads = 1024;
@@ -331,13 +332,21 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s, hipEvent_t* ev = nullpt
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
 // unweighted: the graph has no weight array (every edge weighs 1); the
 // kernels then neither load nor store weights.
+// nnz: entries of R_1 when it is read from the CSR of one graph (sizes the
+// loads of the unweighted kernel), else unused.
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted = false,
-                               hipEvent_t* ev = nullptr);
+                               hipEvent_t* ev = nullptr, long long nnz = 0);
 hipError_t launch_compact(const StreamArgs& a, int grid, hipStream_t s, bool late = false, bool unweighted = false,
                           hipEvent_t* ev = nullptr);
 // First argmax of R_1 of one graph read from its CSR (a.in.csr_rp set).
 hipError_t launch_first_csr(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev = nullptr);
 int first_csr_blocks_per_cu(bool unweighted);
+// First argmax of R_1 of one unweighted graph from its CSR: one-wave
+// workgroups, one range each (first_unw_ranges_per_cu() ranges per CU).
+// vec_ok: col is 16-byte aligned and nnz >= first_unw_min_entries().
+hipError_t launch_first_unw(const StreamArgs& a, int grid, hipStream_t s, bool vec_ok, hipEvent_t* ev = nullptr);
+int first_unw_ranges_per_cu();
+int first_unw_min_entries();
 hipError_t launch_mutual(const MutualArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 // grid must not exceed tail_blocks_per_cu() * CUs (every workgroup resident)
 hipError_t launch_tail(const TailArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);

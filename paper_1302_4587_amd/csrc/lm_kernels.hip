@@ -1546,8 +1546,15 @@ static hipError_t launch_stream(const StreamArgs& a, int grid, hipStream_t s, hi
   if (a.c.graphs == 1) return launch_timed(k_stream<FIRST, PPL, UNW, kViewOne>, dim3(grid), dim3(kBlock), s, ev, a);
   return launch_timed(k_stream<FIRST, PPL, UNW, kViewTables>, dim3(grid), dim3(kBlock), s, ev, a);
 }
-hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev) {
-  if (a.c.graphs == 1 && a.in.csr_rp && !unweighted) return launch_first_csr(a, grid, s, false, ev);
+hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev,
+                               long long nnz) {
+  if (a.c.graphs == 1 && a.in.csr_rp) {
+    if (unweighted) {
+      const bool vec_ok = ((unsigned long long)a.in.col & 15ull) == 0ull && nnz >= first_unw_min_entries();
+      return launch_first_unw(a, grid, s, vec_ok, ev);
+    }
+    return launch_first_csr(a, grid, s, false, ev);
+  }
   if (unweighted) return launch_stream<true, 1, true>(a, grid, s, ev);
   return launch_stream<true, 1, false>(a, grid, s, ev);
 }

@@ -88,6 +88,7 @@ struct Solver {
   int bpc_stream_u = 1, bpc_first_u = 1, bpc_late_u = 1;  // the same for unweighted graphs
   int bpc_tail = 1;              // resident tail workgroups per CU
   int bpc_first_csr = 1;         // the first argmax of one weighted graph read from its CSR
+  int bpc_first_unw = 1;         // one-wave ranges per CU of the first argmax of one unweighted graph
   unsigned long long clock_khz = 100000;  // constant wall clock of the device (barrier time-outs)
   hipEvent_t e_async = nullptr;  // end of the last LM_ASYNC solve
   bool async_pending = false;    // an LM_ASYNC solve may still be running on the context's buffers

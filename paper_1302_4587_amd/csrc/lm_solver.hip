@@ -86,7 +86,7 @@ size_t solve_footprint(int64_t N, int64_t nnz, int64_t G) {
   b += 2 * (((size_t)N + 2 * kMaxBlocks + 16) * 16 + 256); // piece buffers
   b += 2 * 2 * ((size_t)nnz * 4 + 256);                    // entry ping-pong (col, w)
   b += 2 * ((size_t)kMaxBlocks * (sizeof(Run) + 8 + 4) + 1024);
-  b += (size_t)kMaxBlocks * (2 * sizeof(Part) + sizeof(BlockStat) + 4) + 1024;
+  b += (size_t)kMaxFirstRanges * 2 * sizeof(Part) + (size_t)kMaxBlocks * (sizeof(BlockStat) + 4) + 1024;
   b += (size_t)G * 16 + (size_t)(G + 1) * 8 + 1024;
   b += 2 * sizeof(Ctl) + sizeof(Totals) + 1024;
   return b;
@@ -112,7 +112,7 @@ lm_status Solver::prepare(int64_t N, int64_t nnz, int64_t G, bool want_gphase) {
     RES(rpre[i], (size_t)(kMaxBlocks + 1) * 4);
   }
   RES(ctl, 2 * sizeof(Ctl));
-  RES(parts, (size_t)kMaxBlocks * 2 * sizeof(Part));
+  RES(parts, (size_t)kMaxFirstRanges * 2 * sizeof(Part));
   RES(bstat, (size_t)kMaxBlocks * sizeof(BlockStat));
   RES(mcount, (size_t)kMaxBlocks * 4);
   const size_t tb0 = gbase.bytes + gseed.bytes + vtxoff.bytes;
@@ -172,7 +172,7 @@ size_t carve_work(int64_t N, int64_t nnz, int64_t G, void* base, Work* w) {
     x.rpre[i] = (int*)take((size_t)(kMaxBlocks + 1) * 4);
   }
   x.ctl = (Ctl*)take(2 * sizeof(Ctl));
-  x.parts = (Part*)take((size_t)kMaxBlocks * 2 * sizeof(Part));
+  x.parts = (Part*)take((size_t)kMaxFirstRanges * 2 * sizeof(Part));
   x.bstat = (BlockStat*)take((size_t)kMaxBlocks * sizeof(BlockStat));
   x.mcount = (int*)take((size_t)kMaxBlocks * 4);
   x.gbase = (int*)take((size_t)G * 4);
@@ -223,6 +223,7 @@ lm_status Solver::init_device(int device, size_t budget) {
   bpc_late_u = max_blocks_per_cu_stream(StreamKind::kLateCompact, true);
   bpc_tail = tail_blocks_per_cu();
   bpc_first_csr = first_csr_blocks_per_cu(false);
+  bpc_first_unw = first_unw_ranges_per_cu();
   tun.block_entries = kCap;  // one batch: small phases still spread over every CU
   tun.grid_per_cu = 16;  // at most: the resident count of each kernel caps it
   tun.phases_per_sync = 1;  // phases queued past the live set the host checks
@@ -315,13 +316,13 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
 
   // resident workgroups per CU of the kernels this solve uses
   const int bs = unweighted ? bpc_stream_u : bpc_stream;
-  const int bf = (csr1 && !unweighted) ? bpc_first_csr : (unweighted ? bpc_first_u : bpc_first);
+  const int bf = csr1 ? (unweighted ? bpc_first_unw : bpc_first_csr) : (unweighted ? bpc_first_u : bpc_first);
   const int bl = unweighted ? bpc_late_u : bpc_late;
   const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bs))));
   // R_1 feeds the first argmax and the first compaction, each split to its
   // own resident count; later live sets feed compactions with the wider piece
   // window, which fit fewer workgroups per CU
-  const int pcap_first = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, bf)));
+  const int pcap_first = std::max(1, std::min(kMaxFirstRanges, num_cus * std::max(1, bf)));
   const int pcap_late = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bl))));
   const int pmcap = std::max(1, std::min(kMaxBlocks, num_cus * 8));
   Ctl* dctl = wk.ctl;
@@ -441,7 +442,7 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     sa.cand_phase = 1;
     const int gx =
         (int)std::max<int64_t>(1, std::min<int64_t>(pcap_first, p.nnz / std::max(kCap, tun.block_entries) + 1));
-    ENQ(launch_first_argmax(sa, gx, s, unweighted, timing(LM_K_ARGMAX)));
+    ENQ(launch_first_argmax(sa, gx, s, unweighted, timing(LM_K_ARGMAX), p.nnz));
     PlanArgs pf = plan_base();
     pf.mode = kPlanFix;
     pf.first = 1;

@@ -156,6 +156,14 @@ def test_unweighted_equals_unit_weights(ctx, torch_dev):
     col = torch.from_numpy(g.col).to(torch_dev)
     mate, st = ctx.match(rp, col, None, seed=7, hip_graph=True)
     _assert_parity(g, 7, mate.cpu().numpy(), st, "unweighted hip graph")
+    # an entry array that is not 16-byte aligned (a view one entry in) takes
+    # the one-graph kernel's entry-by-entry loads
+    big = lmgen.rmat(13, 16, seed=6)
+    colx = torch.zeros(big.nnz + 1, dtype=torch.int32, device=torch_dev)
+    colx[1:] = torch.from_numpy(big.col).to(torch_dev)
+    print("case: unweighted unaligned col", flush=True)
+    mate, st = ctx.match(torch.from_numpy(big.row_ptr).to(torch_dev), colx[1:], None, seed=3)
+    _assert_parity(big, 3, mate.cpu().numpy(), st, "unweighted unaligned col")
     # tuning shapes cut rows at other workgroup boundaries
     base = ctx.tuning()
     try:
