@@ -349,8 +349,8 @@ constexpr int kUSlots = 65;            // 64 window rows + the open row of the p
 
 struct UnwSmem {
   unsigned mark[kUStep];               // 1 + window index of the row starting at step position x, 0 none
-  unsigned long long slot[kUSlots];    // largest hash per row combined in LDS
-  unsigned hit[kUSlots];               // the slot holds a hash
+  unsigned long long slot[kUSlots + 64];  // largest hash per row combined in LDS (+ a dummy per lane)
+  unsigned hit[kUSlots + 64];             // the slot holds a hash
 };
 
 // Smallest i in [lo, hi) with pred(i) true (pred monotone), hi if none; every
@@ -450,6 +450,14 @@ __device__ __forceinline__ unsigned dpp_wave_shl1(unsigned x, unsigned ident) {
   return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x130, 0xf, 0xf, false);
 }
 
+// The value, computed on every lane whatever later uses it: an empty asm
+// statement (no instruction) that the compiler cannot move into the branch
+// of a later select, so the kUIt hashes of a lane run interleaved, unmasked.
+__device__ __forceinline__ unsigned long long keep(unsigned long long x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 __device__ __forceinline__ long long rdl64(long long x, int l) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)x >> 32), l);
@@ -531,20 +539,22 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
       if (rpos == rlast && !carry) {
         // ---- the step lies in one row: fold into the running maximum
         const unsigned v = (unsigned)(R0 + rpos);
+        unsigned long long hv[kUIt];
+#pragma unroll
+        for (int j = 0; j < kUIt; ++j) hv[j] = keep(edge_hash(S, v, (unsigned)cv.c[j]));
 #pragma unroll
         for (int j = 0; j < kUIt; ++j) {
           const int x = kUIt * lane + j;
           const bool ok = x >= xlo && x < xhi && (unsigned)cv.c[j] < (unsigned)n;
-          const unsigned long long h = edge_hash(S, v, (unsigned)cv.c[j]);
-          acc = ok && h > acc ? h : acc;
+          acc = ok && hv[j] > acc ? hv[j] : acc;
           ahit = ahit || ok;
         }
         orow = R0 + rpos;
       } else {
         // ---- rows from the boundary markers (all zero between steps)
         if (carry) {  // the previous step's open row: its lanes meet in slot 64
-          if (ahit) atomicMax(&sm.slot[64], acc);
-          if (ahit) sm.hit[64] = 1u;
+          atomicMax(&sm.slot[ahit ? 64 : kUSlots + lane], acc);
+          sm.hit[ahit ? 64 : kUSlots + lane] = 1u;
         }
         {
           // row R0 + lane + 1 starts at ce; only the last of several rows
@@ -578,46 +588,39 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
           rr[j] = max(rpos, (int)mm - 1);  // window row of the entry
           const int x = kUIt * lane + j;
           okv[j] = x >= xlo && x < xhi && (unsigned)cv.c[j] < (unsigned)n;
-          hv[j] = edge_hash(S, (unsigned)(R0 + rr[j]), (unsigned)cv.c[j]);
+          hv[j] = keep(edge_hash(S, (unsigned)(R0 + rr[j]), (unsigned)cv.c[j]));
         }
-        // the step's last row stays open in the registers; earlier rows go
-        // to their slots, one LDS atomic per run of the lane
-        unsigned long long accl = 0ull, runh = 0ull;
-        bool hitl = false, runok = false;
-        int runr = -1;
+        // Runs of one row among the lane's entries (rows never decrease along
+        // them). The lane's running maximum from earlier steps heads the
+        // first run (it belongs to the row of pos, which ends in this step)
+        // unless the open row ended at pos. Every run but the one of the
+        // step's last row, which stays open in the registers, ends in an LDS
+        // atomic max on its row's slot; lanes with nothing to add write their
+        // own dummy slot instead, so no branch splits the wave.
+        const int dummy = kUSlots + lane;
+        unsigned long long rm = carry ? 0ull : acc;  // the current run's largest hash
+        bool rh = !carry && ahit;                     // the current run has one
+        int prow = carry ? -1 : rpos;                 // the current run's row
 #pragma unroll
         for (int j = 0; j < kUIt; ++j) {
-          const bool ok = okv[j];
-          if (rr[j] == rlast) {
-            accl = ok && hv[j] > accl ? hv[j] : accl;
-            hitl = hitl || ok;
-          } else {
-            if (rr[j] != runr) {
-              if (runok) {
-                atomicMax(&sm.slot[runr], runh);
-                sm.hit[runr] = 1u;
-              }
-              runr = rr[j];
-              runh = 0ull;
-              runok = false;
-            }
-            runh = ok && hv[j] > runh ? hv[j] : runh;
-            runok = runok || ok;
-          }
+          const bool same = rr[j] == prow;
+          const bool fl = !same && rh;  // the run before entry j ends (its row < rlast)
+          atomicMax(&sm.slot[fl ? prow : dummy], rm);
+          sm.hit[fl ? prow : dummy] = 1u;
+          rm = same ? rm : 0ull;
+          rh = same && rh;
+          rm = okv[j] && hv[j] > rm ? hv[j] : rm;
+          rh = rh || okv[j];
+          prow = rr[j];
         }
-        if (!carry && ahit) {  // the lane's running maximum belongs to the row of pos, which ends here
-          if (runr == rpos) {
-            runh = acc > runh ? acc : runh;
-            runok = true;
-          } else {
-            atomicMax(&sm.slot[rpos], acc);
-            sm.hit[rpos] = 1u;
-          }
+        const bool lastopen = prow == rlast;
+        {
+          const bool fl = !lastopen && rh;
+          atomicMax(&sm.slot[fl ? prow : dummy], rm);
+          sm.hit[fl ? prow : dummy] = 1u;
         }
-        if (runok) {
-          atomicMax(&sm.slot[runr], runh);
-          sm.hit[runr] = 1u;
-        }
+        const unsigned long long accl = lastopen ? rm : 0ull;
+        const bool hitl = lastopen && rh;
         wave_lds_sync();
         // rows of the window that ended inside the step: rpos .. rlast - 1
         if (carry) {
@@ -641,10 +644,8 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
                 (unsigned)__builtin_amdgcn_readlane((int)(unsigned)h, l0);
             pf = unw_part(v0, 0, a0, h0, S);
           }
-          if (mine) {
-            sm.slot[lane] = 0ull;
-            sm.hit[lane] = 0u;
-          }
+          sm.slot[mine ? lane : kUSlots + lane] = 0ull;
+          sm.hit[mine ? lane : kUSlots + lane] = 0u;
         }
         if (carry && lane == 0) {
           sm.slot[64] = 0ull;
@@ -711,7 +712,7 @@ hipError_t launch_first_csr(const StreamArgs& a, int grid, hipStream_t s, bool u
 }
 
 template <bool VEC>
-__global__ __launch_bounds__(64) void k_first_unw(StreamArgs a) {
+__global__ __launch_bounds__(64, 8) void k_first_unw(StreamArgs a) {  // 8 waves per SIMD
   __shared__ UnwSmem sm;
   if (a.c.totals->err) return;
   Ctl ctl = *a.in.ctl;
