@@ -9,6 +9,15 @@
 namespace lm {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// The value, computed on every lane whatever later uses it: an empty asm
+// statement (no instruction) that the compiler cannot move into the branch
+// of a later select, so a lane's hashes run unmasked and interleaved instead
+// of one exec-masked block each.
+__device__ __forceinline__ unsigned long long keep(unsigned long long x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const int l = lane_id();

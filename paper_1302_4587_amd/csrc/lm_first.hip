@@ -450,14 +450,6 @@ __device__ __forceinline__ unsigned dpp_wave_shl1(unsigned x, unsigned ident) {
   return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, 0x130, 0xf, 0xf, false);
 }
 
-// The value, computed on every lane whatever later uses it: an empty asm
-// statement (no instruction) that the compiler cannot move into the branch
-// of a later select, so the kUIt hashes of a lane run interleaved, unmasked.
-__device__ __forceinline__ unsigned long long keep(unsigned long long x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-
 __device__ __forceinline__ long long rdl64(long long x, int l) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)x >> 32), l);
@@ -711,10 +703,15 @@ hipError_t launch_first_csr(const StreamArgs& a, int grid, hipStream_t s, bool u
   return hipGetLastError();
 }
 
+// A failed solve, or a guarded launch whose phases the device tail took over.
+__device__ __forceinline__ bool wave_failed(const Common& c) {
+  return (c.totals->err | ((c.guard && c.totals->tail_from) ? 0x80000000u : 0u)) != 0u;
+}
+
 template <bool VEC>
 __global__ __launch_bounds__(64, 8) void k_first_unw(StreamArgs a) {  // 8 waves per SIMD
   __shared__ UnwSmem sm;
-  if (a.c.totals->err) return;
+  if (wave_failed(a.c)) return;
   Ctl ctl = *a.in.ctl;
   const int P = ctl.Pf > 0 ? ctl.Pf : ctl.P;  // the first argmax's own split of R_1
   const unsigned long long S = cand_seed(a.c.gseed[0], a.c.renew, a.cand_phase);

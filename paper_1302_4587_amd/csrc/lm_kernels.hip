@@ -1031,13 +1031,22 @@ __device__ void stream_range(const StreamArgs& a, const Ctl& ctl, int b, StreamS
         // ids outside the graph are dropped
         ok[jj] = tid + kBlock * jj < NLD && cc[jj] >= 0 && ug[jj] < (unsigned)a.c.n;
       }
+      // The neighbours' matched flags: every gather is issued before any is
+      // used (one branch around the loads, the bit extracted afterwards), so
+      // the kItems round trips overlap.
       unsigned char st[kItems];
       if (!FIRST) {
+        unsigned gw[kItems];
+        if (use_bits) {
 #pragma unroll
-        for (int jj = 0; jj < kItems; ++jj) {
-          const unsigned uu = ok[jj] ? ug[jj] : 0u;
-          st[jj] = use_bits ? (unsigned char)((a.c.mbits[uu >> 5] >> (uu & 31u)) & 1u) : a.c.state[uu];
+          for (int jj = 0; jj < kItems; ++jj) gw[jj] = a.c.mbits[(ok[jj] ? ug[jj] : 0u) >> 5];
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < kItems; ++jj) gw[jj] = a.c.state[ok[jj] ? ug[jj] : 0u];
         }
+#pragma unroll
+        for (int jj = 0; jj < kItems; ++jj)
+          st[jj] = use_bits ? (unsigned char)((gw[jj] >> ((ok[jj] ? ug[jj] : 0u) & 31u)) & 1u) : (unsigned char)gw[jj];
       }
       unsigned rank[kItems];
       unsigned kpm = 0;
