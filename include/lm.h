@@ -194,7 +194,7 @@ lm_status lm_match_batch(lm_ctx* ctx, int32_t graphs, const int64_t* vtx_off, in
  *  - the working buffers come from one device array of
  *    LM_NOALLOC_SCRATCH_BYTES per GPU (held from the first lm_create on that
  *    GPU until the process ends), not from the context's pool; a graph needs
- *    37.2 n + 16 nnz bytes plus about 0.85 MiB of tables (each piece rounded up
+ *    37.2 n + 16 nnz bytes plus about 1.1 MiB of tables (each piece rounded up
  *    to 256 bytes), and a larger one gives LM_ETOOBIG before any device work
  *    (for example n = 2^19 with nnz up to 2.9 M entries fits);
  *  - the call makes no hipMalloc, hipFree, pinned or other device allocation.
