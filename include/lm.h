@@ -297,7 +297,9 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
 
 /* ---------------- serving: continuous batching at phase granularity ----- */
 
-#define LM_SERVE_BATCHED 0  /* continuous batching: resident graphs share every phase launch */
+#define LM_SERVE_BATCHED 0  /* continuous batching: resident graphs share every phase launch; a
+                               request that finds the server idle (nothing resident, staged or
+                               queued behind it) is solved alone, as lm_match would */
 #define LM_SERVE_FIFO 1     /* baseline: one request at a time through lm_match */
 
 typedef struct {

@@ -579,14 +579,25 @@ static void batch_loop(ServerCore* S) {
   const int k = std::max(1, S->opts.phases_per_step);
   for (;;) {
     std::vector<std::shared_ptr<Request>> fresh;
+    std::shared_ptr<Request> solo;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       if (B.resident == 0 && B.staged.empty())
         S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
       if (S->stopping && S->queue.empty() && B.staged.empty() && B.resident == 0) return;
+      // A request that finds the server idle (nothing resident, staged or
+      // queued behind it) is solved alone on the single-graph path, with its
+      // device tail and no phase steps shared with others: batching only
+      // pays once requests wait for each other.
+      if (B.resident == 0 && B.staged.empty() && S->queue.size() == 1 && !S->queue.front()->no_solo) {
+        solo = S->queue.front();
+        S->queue.pop_front();
+        solo->t_admit = Clock::now();
+        S->running[solo->ticket] = solo;
+      }
       // start the host-to-device copies of queued requests while the staging
       // area has room; they overlap the phases of the resident graphs
-      while (!S->queue.empty()) {
+      while (!solo && !S->queue.empty()) {
         auto& r = S->queue.front();
         int64_t off = 0;
         if (!B.stage_alloc((int64_t)r->block_used, &off)) break;
@@ -595,6 +606,28 @@ static void batch_loop(ServerCore* S) {
         B.staged.push_back(r);
         S->queue.pop_front();
       }
+    }
+    if (solo) {
+      lm_status st;
+      {
+        std::lock_guard<std::mutex> ck(mutex_of(S->ctx));
+        lm_stats stats;
+        std::memset(&stats, 0, sizeof(stats));
+        solo->mate.assign((size_t)solo->n, -1);
+        st = solve_locked(S->ctx, solo->n, solo->nnz, 1, nullptr, solo->h_rp, solo->h_col, solo->h_w, nullptr,
+                          solo->seed, solo->mate.data(), 0u, (void*)solver_of(S->ctx).own, &stats, nullptr);
+        solo->phases = stats.phases;
+        solo->matched = stats.matched_edges;
+      }
+      if (st == LM_ETOOBIG || st == LM_ENOMEM) {  // beyond the context's pool: the batch takes it
+        std::lock_guard<std::mutex> lk(S->mu);
+        solo->no_solo = true;
+        S->running.erase(solo->ticket);
+        S->queue.push_front(solo);
+        continue;
+      }
+      S->finish(solo, st);
+      continue;
     }
     lm_status st = LM_OK;
     for (auto& r : fresh) {

@@ -51,6 +51,7 @@ struct Request {
   int slot = -1;        // graph index in the resident tables
   int64_t vbase = 0;    // first vertex of the request in the server's vertex space
   int first_phase = 0;  // server phase in which the request was injected
+  bool no_solo = false; // the single-graph path refused it (size): batch it
   // layout of the pinned block: row_ptr at 0, col at off_col, w at off_w
   size_t off_col = 0, off_w = 0, block_used = 0;
   // staging copy on the device (batched mode)
