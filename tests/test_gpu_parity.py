@@ -409,6 +409,38 @@ def test_empty_rows_in_first_live_set(ctx, torch_dev):
         ctx.set_tuning(**base)
 
 
+def test_unweighted_empty_rows(ctx, torch_dev):
+    """The one-graph unweighted first argmax walks R_1 with a window of 64
+    row ends: runs of empty rows shorter and longer than the window (ids
+    spread by 2, 64 and 100, and a stretch of 197000 empty rows between two
+    dense blocks) and many range sizes. Every solve equals the oracle on the
+    same graph with unit weights."""
+    import torch
+    dense = lmgen.er(3000, 40000, seed=4, weights="unit")
+    lo, hi, _ = ref.undirected_edges(dense)
+    cases = []
+    for k in (2, 64, 100):
+        cases.append((f"ids x{k}", lmgen.from_edges(3000 * k, np.stack([k * lo, k * hi], 1), np.ones(len(lo)))))
+    lo2 = np.concatenate([lo, lo + 200000]).astype(np.int64)
+    hi2 = np.concatenate([hi, hi + 200000]).astype(np.int64)
+    cases.append(("empty stretch", lmgen.from_edges(203000, np.stack([lo2, hi2], 1), np.ones(len(lo2)))))
+    base = ctx.tuning()
+    try:
+        for name, g in cases:
+            rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr)).to(torch_dev)
+            col = torch.from_numpy(np.ascontiguousarray(g.col)).to(torch_dev)
+            for be in (2048, 65536, None):
+                if be is None:
+                    ctx.set_tuning(**base)
+                else:
+                    ctx.set_tuning(block_entries=be, grid_per_cu=1)
+                print(f"case: unweighted {name} block_entries={be}", flush=True)
+                mate, st = ctx.match(rp, col, None, seed=5)
+                _assert_parity(_unit(g), 5, mate.cpu().numpy(), st, f"unweighted {name} {be}")
+    finally:
+        ctx.set_tuning(**base)
+
+
 def _weight_tol(abs_sum, edges, exact):
     # Any order of 2|M| double additions (each matched edge from both ends,
     # then halved exactly) is within (2|M| - 1) 2^-53 sum|w| of the exact sum;
