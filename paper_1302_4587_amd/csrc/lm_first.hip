@@ -53,34 +53,45 @@ template <>
 struct Seg<false> {
   Best b;
   __device__ __forceinline__ void reset() { b = best_ident(); }
-  __device__ __forceinline__ void add(unsigned w, int u, unsigned v, unsigned long long S) {
-    best_update(b, w, u, v, S);
+  // one entry's ordered weight w (0: no candidate) and neighbour u; the hash
+  // only when w ties the best so far
+  __device__ __forceinline__ void add_key(unsigned w, int u, unsigned v, unsigned long long S, unsigned long long) {
+    if (w != 0u) best_update(b, w, u, v, S);
   }
-  __device__ __forceinline__ void add_hash(unsigned long long, int) {}
   __device__ __forceinline__ int u() const { return b.u; }
   __device__ __forceinline__ unsigned w() const { return b.w; }
   __device__ __forceinline__ unsigned long long h(unsigned v, unsigned long long S) const {
     return b.hv ? b.h : edge_hash(S, v, (unsigned)b.u);
+  }
+  // this = c ? o : this, field by field (a select of whole structs would go
+  // through private memory)
+  __device__ __forceinline__ void pick(bool c, const Seg& o) {
+    b.w = c ? o.b.w : b.w;
+    b.u = c ? o.b.u : b.u;
+    b.h = c ? o.b.h : b.h;
+    b.hv = c ? o.b.hv : b.hv;
   }
 };
 template <>
 struct Seg<true> {
   unsigned long long hb;
   int ub;
-  __device__ __forceinline__ void add(unsigned, int, unsigned, unsigned long long) {}
   __device__ __forceinline__ void reset() {
     hb = 0ull;
     ub = -1;
   }
-  __device__ __forceinline__ void add_hash(unsigned long long h, int u) {
-    if (ub < 0 || h > hb) {
-      hb = h;
-      ub = u;
-    }
+  __device__ __forceinline__ void add_key(unsigned w, int u, unsigned, unsigned long long, unsigned long long h) {
+    const bool gt = w != 0u && (ub < 0 || h > hb);
+    hb = gt ? h : hb;
+    ub = gt ? u : ub;
   }
   __device__ __forceinline__ int u() const { return ub; }
   __device__ __forceinline__ unsigned w() const { return 1u; }
   __device__ __forceinline__ unsigned long long h(unsigned, unsigned long long) const { return hb; }
+  __device__ __forceinline__ void pick(bool c, const Seg& o) {
+    hb = c ? o.hb : hb;
+    ub = c ? o.ub : ub;
+  }
 };
 
 __device__ __forceinline__ Part part_of(int v, int flags, unsigned w, unsigned long long h, unsigned long long S) {
@@ -184,8 +195,11 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
     int cv[kFIt];
     float wv[kFIt];
     load_entries<UNW>(col, wt, s0, lo, hi, nnz, vec, cv, wv);
-    // ---- stage 1: the row slot of each of the lane's entries (-1: not the lane's)
+    // ---- stage 1: the row slot of each of the lane's positions (positions
+    // outside [lo, hi) keep the slot before them) and whether it is a
+    // candidate (the lane's, with an id inside the graph)
     int rs[kFIt];
+    bool okv[kFIt];
     int r = 0;  // largest r with wrp[r] <= lo
     if (lo < hi) {
 #pragma unroll
@@ -200,14 +214,18 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
         const bool in = q >= lo && q < hi;
         if (in)
           while (q >= wrp[rr + 1]) ++rr;  // rows in between are empty
-        rs[i] = in && cv[i] >= 0 && cv[i] < n ? rr : -1;
+        rs[i] = rr;
+        okv[i] = in && cv[i] >= 0 && cv[i] < n;
       }
     }
-    // ---- stage 2 (unweighted): every hash at once, independent of each other
+    // ---- stage 2: every entry's ordered weight (0: no candidate) and, for an
+    // unweighted graph, its hash (all at once, out of masked branches)
     unsigned long long hv[kFIt];
-    if (UNW) {
+    unsigned kw[kFIt];
 #pragma unroll
-      for (int i = 0; i < kFIt; ++i) hv[i] = edge_hash(S, (unsigned)(vc + max(rs[i], 0)), (unsigned)cv[i]);
+    for (int i = 0; i < kFIt; ++i) {
+      hv[i] = UNW ? keep(edge_hash(S, (unsigned)(vc + rs[i]), (unsigned)cv[i])) : 0ull;
+      kw[i] = okv[i] ? (UNW ? kUnitOrd : ord_weight_bits(__float_as_uint(wv[i]))) : 0u;
     }
     // ---- stage 3: segments. A row inside the lane is finished here; only the
     // lane's first segment (its row began before lo) and its last (its row
@@ -219,24 +237,22 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
     if (lo < hi) {
       Seg<UNW> sg;
       sg.reset();
+      Seg<UNW> empty;
+      empty.reset();
       int cur = r;
       bool started = wrp[r] >= lo;
 #pragma unroll
       for (int i = 0; i < kFIt; ++i) {
-        if (rs[i] < 0) continue;
-        if (rs[i] != cur) {  // the entry opens another row
-          if (started) {
-            if (sg.u() >= 0) a.c.C[vc + cur] = sg.u();
-          } else {
-            rA = cur;
-            sA = sg;
-          }
-          cur = rs[i];
-          started = true;
-          sg.reset();
-        }
-        if (UNW) sg.add_hash(hv[i], cv[i]);
-        else sg.add(ord_weight_bits(__float_as_uint(wv[i])), cv[i], (unsigned)(vc + cur), S);
+        const bool nw = rs[i] != cur;  // the position opens another row
+        // the run before it ends: finished in the lane, or the lane's first segment
+        if (nw && started && sg.u() >= 0) a.c.C[vc + cur] = sg.u();
+        const bool fa = nw && !started;
+        rA = fa ? cur : rA;
+        sA.pick(fa, sg);
+        started = started || nw;
+        cur = rs[i];
+        sg.pick(nw, empty);
+        sg.add_key(kw[i], cv[i], (unsigned)(vc + rs[i]), S, hv[i]);
       }
       const bool ends = wrp[cur + 1] <= hi;
       if (started && ends) {
