@@ -361,7 +361,7 @@ constexpr int kUIt = 4;                // entries per lane per step
 constexpr int kUStep = 64 * kUIt;      // entries per step
 static_assert(kUIt % 4 == 0, "entries are loaded 16 bytes at a time");
 constexpr int kUnwPerCu = 32;          // one-wave ranges per CU (8 per SIMD: at most 64 VGPRs)
-constexpr int kUSlots = 65;            // 64 window rows + the open row of the previous step
+constexpr int kUSlots = 64;            // the window's rows
 
 struct UnwSmem {
   unsigned mark[kUStep];               // 1 + window index of the row starting at step position x, 0 none
@@ -543,8 +543,16 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
       const int xlo = (int)(pos - s), xhi = (int)(se - s);  // valid step positions [xlo, xhi)
       const int rpos = __popcll(__ballot(ce <= pos));       // window row of pos
       const int rlast = __popcll(__ballot(ce < se));        // window row of se - 1
-      const bool carry = orow >= 0 && orow != R0 + rpos;    // the open row ended at pos
-      if (rpos == rlast && !carry) {
+      if (orow >= 0 && orow != R0 + rpos) {
+        // the open row ended at pos (where a window or a range part ended):
+        // its lanes' maxima meet in one wave reduction
+        const bool any = __ballot(ahit) != 0ull;
+        const unsigned long long h = any ? wave_max_u64(ahit ? acc : 0ull) : 0ull;
+        finish(orow, any, h);
+        acc = 0ull;
+        ahit = false;
+      }
+      if (rpos == rlast) {
         // ---- the step lies in one row: fold into the running maximum
         const unsigned v = (unsigned)(R0 + rpos);
         unsigned long long hv[kUIt];
@@ -560,10 +568,6 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
         orow = R0 + rpos;
       } else {
         // ---- rows from the boundary markers (all zero between steps)
-        if (carry) {  // the previous step's open row: its lanes meet in slot 64
-          atomicMax(&sm.slot[ahit ? 64 : kUSlots + lane], acc);
-          sm.hit[ahit ? 64 : kUSlots + lane] = 1u;
-        }
         {
           // row R0 + lane + 1 starts at ce; only the last of several rows
           // starting there (the others are empty) marks it
@@ -600,15 +604,15 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
         }
         // Runs of one row among the lane's entries (rows never decrease along
         // them). The lane's running maximum from earlier steps heads the
-        // first run (it belongs to the row of pos, which ends in this step)
-        // unless the open row ended at pos. Every run but the one of the
+        // first run (it belongs to the row of pos, which ends in this step;
+        // it is empty when that row began at pos). Every run but the one of the
         // step's last row, which stays open in the registers, ends in an LDS
         // atomic max on its row's slot; lanes with nothing to add write their
         // own dummy slot instead, so no branch splits the wave.
         const int dummy = kUSlots + lane;
-        unsigned long long rm = carry ? 0ull : acc;  // the current run's largest hash
-        bool rh = !carry && ahit;                     // the current run has one
-        int prow = carry ? -1 : rpos;                 // the current run's row
+        unsigned long long rm = acc;  // the current run's largest hash
+        bool rh = ahit;               // the current run has one
+        int prow = rpos;              // the current run's row
 #pragma unroll
         for (int j = 0; j < kUIt; ++j) {
           const bool same = rr[j] == prow;
@@ -631,11 +635,6 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
         const bool hitl = lastopen && rh;
         wave_lds_sync();
         // rows of the window that ended inside the step: rpos .. rlast - 1
-        if (carry) {
-          const bool any = sm.hit[64] != 0u;
-          const unsigned long long h = sm.slot[64];
-          finish(orow, any, h);
-        }
         if (rpos < rlast) {
           // (the row of pos finishes here when the step goes past it)
           const bool mine = lane >= rpos && lane < rlast;
@@ -654,10 +653,6 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
           }
           sm.slot[mine ? lane : kUSlots + lane] = 0ull;
           sm.hit[mine ? lane : kUSlots + lane] = 0u;
-        }
-        if (carry && lane == 0) {
-          sm.slot[64] = 0ull;
-          sm.hit[64] = 0u;
         }
         wave_lds_sync();  // the cleared slots before the next step's atomics
         acc = accl;
