@@ -42,6 +42,12 @@ struct FirstSmem {
   Part pf, pl;                     // the range's cut rows
   int lb[1];
   unsigned err;
+  // several graphs (a batch): the graph of every row of the tile
+  unsigned long long rseed[kFRows];  // its tie-break seed
+  int rbase[kFRows];                 // its first vertex
+  int rlim[kFRows];                  // its vertex count (local ids below it)
+  int rgraph[kFRows + 1];            // its index; [kFRows]: the graph of row vc + kFRows
+  int g_cur;                         // the graph of row vc
 };
 
 // A lane's running best over one row segment. Weighted: the largest ordered
@@ -94,7 +100,9 @@ struct Seg<true> {
   }
 };
 
-__device__ __forceinline__ Part part_of(int v, int flags, unsigned w, unsigned long long h, unsigned long long S) {
+// (v global; base: its graph's first vertex, whose local ids the hash takes)
+__device__ __forceinline__ Part part_of(int v, int flags, unsigned w, unsigned long long h, unsigned long long S,
+                                        int base = 0) {
   Part p;
   p.v = v;
   p.flags = flags;
@@ -103,7 +111,7 @@ __device__ __forceinline__ Part part_of(int v, int flags, unsigned w, unsigned l
   p.w = w;
   p.hhi = (unsigned)(h >> 32);
   p.hlo = (unsigned)h;
-  p.u = hash_neighbour(h, S, (unsigned)v);
+  p.u = base + hash_neighbour(h, S, (unsigned)(v - base));
   return p;
 }
 
@@ -139,7 +147,11 @@ __device__ __forceinline__ void load_entries(const int* col, const float* wt, lo
   }
 }
 
-template <bool UNW>
+// MULTI: the CSR is the disjoint union of a batch's graphs (a.c.graphs of
+// them, graph k from vertex gbase[k] on, local neighbour ids, a seed each):
+// every tile looks up the graph of each of its rows, walking on from the
+// graph of its first row.
+template <bool UNW, bool MULTI>
 __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSmem& sm, unsigned long long S,
                             bool vec) {
   constexpr unsigned kUnitOrd = 0xBF800000u;  // ordered image of 1.0f
@@ -147,7 +159,12 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
   const long long* rp = a.in.csr_rp;
   const int* col = a.in.col;
   const float* wt = a.in.w;
-  const long long n = ctl.pieces;
+  const long long n = a.c.n;  // rows of the CSR (every vertex of the union)
+  const int G = a.c.graphs;
+  // per row slot of the current tile: graph seed, first vertex, vertex count
+  auto seed_of = [&](int i) -> unsigned long long { return MULTI ? sm.rseed[i] : S; };
+  auto base_of = [&](int i) -> int { return MULTI ? sm.rbase[i] : 0; };
+  auto lim_of = [&](int i) -> long long { return MULTI ? (long long)sm.rlim[i] : n; };
   const long long nnz = rp[n];
   const long long cost = ctl.L + (long long)kPieceCostFirst * n;
   const long long E0 = csr_entry_at<kPieceCostFirst>(a.in, n, cost * b / ctl.P, sm.lb);
@@ -165,6 +182,10 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
   const long long v0 = block_lower_bound(0, n, [&](long long v) { return rp[v + 1] > E0; }, sm.lb);
   const bool cut_left = rp[v0] < E0;
   long long vc = v0, e = E0;
+  if (MULTI) {  // the graph of v0: the last graph starting at or before it
+    const long long g1 = block_lower_bound(0, G, [&](long long g) { return (long long)a.c.gbase[g] > v0; }, sm.lb);
+    if (tid == 0) sm.g_cur = (int)g1 - 1;
+  }
   if (tid == 0) {
     sm.pf = none;
     sm.pl = none;
@@ -177,6 +198,21 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
     for (int i = tid; i < kFRows; i += kBlock) {
       sm.sw[i] = 0u;
       sm.sh[i] = 0ull;
+    }
+    if (MULTI) {
+      const int g0 = sm.g_cur;
+      for (int i = tid; i <= kFRows; i += kBlock) {
+        const long long v = min(vc + i, n - 1);
+        int g = g0;
+        while (g + 1 < G && (long long)a.c.gbase[g + 1] <= v) ++g;  // (graph boundaries inside the tile)
+        sm.rgraph[i] = g;
+        if (i < kFRows) {
+          const int base = a.c.gbase[g];
+          sm.rbase[i] = base;
+          sm.rlim[i] = (g + 1 < G ? a.c.gbase[g + 1] : (int)n) - base;
+          sm.rseed[i] = cand_seed(a.c.gseed[g], a.c.renew, a.cand_phase);
+        }
+      }
     }
     // the open row's partial key (from the previous tile): its weight joins
     // slot 0 in pass 1, its hash counts only if no segment of this tile
@@ -215,7 +251,7 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
         if (in)
           while (q >= wrp[rr + 1]) ++rr;  // rows in between are empty
         rs[i] = rr;
-        okv[i] = in && cv[i] >= 0 && cv[i] < n;
+        okv[i] = in && cv[i] >= 0 && cv[i] < lim_of(rr);
       }
     }
     // ---- stage 2: every entry's ordered weight (0: no candidate) and, for an
@@ -224,7 +260,7 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
     unsigned kw[kFIt];
 #pragma unroll
     for (int i = 0; i < kFIt; ++i) {
-      hv[i] = UNW ? keep(edge_hash(S, (unsigned)(vc + rs[i]), (unsigned)cv[i])) : 0ull;
+      hv[i] = UNW ? keep(edge_hash(seed_of(rs[i]), (unsigned)(vc + rs[i] - base_of(rs[i])), (unsigned)cv[i])) : 0ull;
       kw[i] = okv[i] ? (UNW ? kUnitOrd : ord_weight_bits(__float_as_uint(wv[i]))) : 0u;
     }
     // ---- stage 3: segments. A row inside the lane is finished here; only the
@@ -245,18 +281,18 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
       for (int i = 0; i < kFIt; ++i) {
         const bool nw = rs[i] != cur;  // the position opens another row
         // the run before it ends: finished in the lane, or the lane's first segment
-        if (nw && started && sg.u() >= 0) a.c.C[vc + cur] = sg.u();
+        if (nw && started && sg.u() >= 0) a.c.C[vc + cur] = base_of(cur) + sg.u();
         const bool fa = nw && !started;
         rA = fa ? cur : rA;
         sA.pick(fa, sg);
         started = started || nw;
         cur = rs[i];
         sg.pick(nw, empty);
-        sg.add_key(kw[i], cv[i], (unsigned)(vc + rs[i]), S, hv[i]);
+        sg.add_key(kw[i], cv[i], (unsigned)(vc + rs[i] - base_of(rs[i])), seed_of(rs[i]), hv[i]);
       }
       const bool ends = wrp[cur + 1] <= hi;
       if (started && ends) {
-        if (sg.u() >= 0) a.c.C[vc + cur] = sg.u();
+        if (sg.u() >= 0) a.c.C[vc + cur] = base_of(cur) + sg.u();
       } else if (!started && ends) {
         rA = cur;
         sA = sg;
@@ -296,14 +332,16 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
     }
     __syncthreads();
     // pass 2: the largest hash among the segments at that weight
-    if (rA >= 0 && sA.u() >= 0 && (UNW || sA.w() == sw[rA])) atomicMax(&sh[rA], sA.h((unsigned)(vc + rA), S));
+    if (rA >= 0 && sA.u() >= 0 && (UNW || sA.w() == sw[rA]))
+      atomicMax(&sh[rA], sA.h((unsigned)(vc + rA - base_of(rA)), seed_of(rA)));
     if (waveB) {
       const bool at = sB.u() >= 0 && (UNW || sB.w() == sw[rB0]);
-      const unsigned long long hm = wave_max_u64(at ? sB.h((unsigned)(vc + rB0), S) : 0ull);
+      const unsigned long long hm =
+          wave_max_u64(at ? sB.h((unsigned)(vc + rB0 - base_of(rB0)), seed_of(rB0)) : 0ull);
       const bool any = __ballot(at) != 0ull;  // (every lane takes part in the ballot)
       if (lane_id() == 0 && any) atomicMax(&sh[rB0], hm);
     } else if (rB >= 0 && sB.u() >= 0 && (UNW || sB.w() == sw[rB])) {
-      atomicMax(&sh[rB], sB.h((unsigned)(vc + rB), S));
+      atomicMax(&sh[rB], sB.h((unsigned)(vc + rB - base_of(rB)), seed_of(rB)));
     }
     __syncthreads();
     // ---- finish the rows that crossed lanes
@@ -314,11 +352,12 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
       const unsigned w = UNW ? kUnitOrd : sw[i];
       unsigned long long hh = sh[i];
       if (i == 0 && carry && sw[0] == cw_in) hh = max(hh, ch_in);
+      const int bs = base_of(i);
       if (wrp[i + 1] <= tend) {  // the row ends in this tile
-        if (cutl) sm.pf = part_of((int)v, 0, w, hh, S);
-        else a.c.C[v] = hash_neighbour(hh, S, (unsigned)v);
+        if (cutl) sm.pf = part_of((int)v, 0, w, hh, seed_of(i), bs);
+        else a.c.C[v] = bs + hash_neighbour(hh, seed_of(i), (unsigned)(v - bs));
       } else if (tend == E1) {  // the row goes on past the range
-        const Part p = part_of((int)v, cutl ? kPartSingle : 0, w, hh, S);
+        const Part p = part_of((int)v, cutl ? kPartSingle : 0, w, hh, seed_of(i), bs);
         if (cutl) sm.pf = p;
         else sm.pl = p;
       } else {  // the row goes on in the next tile
@@ -331,6 +370,7 @@ __device__ void first_range(const StreamArgs& a, const Ctl& ctl, int b, FirstSme
 #pragma unroll
     for (int step = kFRows; step > 0; step >>= 1)
       if (r2 + step <= kFRows && wrp[r2 + step] <= tend) r2 += step;
+    if (MULTI && tid == 0) sm.g_cur = sm.rgraph[r2];
     __syncthreads();
     vc += r2;
     e = tend;
@@ -690,7 +730,7 @@ __device__ void unw_range(const StreamArgs& a, const Ctl& ctl, int P, int b, Unw
 
 }  // namespace
 
-template <bool UNW>
+template <bool UNW, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_first_csr(StreamArgs a) {
   __shared__ FirstSmem sm;
   if (threadIdx.x == 0) sm.err = a.c.totals->err;
@@ -700,18 +740,21 @@ __global__ __launch_bounds__(kBlock) void k_first_csr(StreamArgs a) {
   if (ctl.Pf > 0) ctl.P = ctl.Pf;  // the first argmax's own split of R_1
   const unsigned long long S = cand_seed(a.c.gseed[0], a.c.renew, a.cand_phase);
   const bool vec = (((unsigned long long)a.in.col | (UNW ? 0ull : (unsigned long long)a.in.w)) & 15ull) == 0ull;
-  for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) first_range<UNW>(a, ctl, b, sm, S, vec);
+  for (int b = blockIdx.x; b < ctl.P; b += gridDim.x) first_range<UNW, MULTI>(a, ctl, b, sm, S, vec);
+}
+
+template <bool UNW, bool MULTI>
+static hipError_t launch_first_csr_t(const StreamArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
+  const auto kern = k_first_csr<UNW, MULTI>;
+  if (ev) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, ev[0], ev[1], 0, a);
+  else hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_first_csr(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev) {
-  if (unweighted) {
-    if (ev) hipExtLaunchKernelGGL(k_first_csr<true>, dim3(grid), dim3(kBlock), 0, s, ev[0], ev[1], 0, a);
-    else hipLaunchKernelGGL(k_first_csr<true>, dim3(grid), dim3(kBlock), 0, s, a);
-  } else {
-    if (ev) hipExtLaunchKernelGGL(k_first_csr<false>, dim3(grid), dim3(kBlock), 0, s, ev[0], ev[1], 0, a);
-    else hipLaunchKernelGGL(k_first_csr<false>, dim3(grid), dim3(kBlock), 0, s, a);
-  }
-  return hipGetLastError();
+  const bool multi = a.c.graphs > 1;
+  if (unweighted) return multi ? launch_first_csr_t<true, true>(a, grid, s, ev) : launch_first_csr_t<true, false>(a, grid, s, ev);
+  return multi ? launch_first_csr_t<false, true>(a, grid, s, ev) : launch_first_csr_t<false, false>(a, grid, s, ev);
 }
 
 // A failed solve, or a guarded launch whose phases the device tail took over.
@@ -762,13 +805,20 @@ int first_unw_ranges_per_cu() {
   return std::max(1, std::min(kUnwPerCu, std::min(n1, n0)));
 }
 
+// (the fewer of the one-graph and the batch instantiations)
 int first_csr_blocks_per_cu(bool unweighted) {
-  int nb = 0;
-  const hipError_t e = unweighted
-                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_first_csr<true>, kBlock, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_first_csr<false>, kBlock, 0);
-  if (e != hipSuccess || nb < 1) nb = 1;
-  return nb;
+  int n1 = 0, n2 = 0;
+  const hipError_t e =
+      unweighted ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, (k_first_csr<true, false>), kBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, (k_first_csr<false, false>), kBlock, 0);
+  const hipError_t e2 =
+      unweighted ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, (k_first_csr<true, true>), kBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, (k_first_csr<false, true>), kBlock, 0);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return std::max(1, std::min(n1, n2));
 }
 
 }  // namespace lm

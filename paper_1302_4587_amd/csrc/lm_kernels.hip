@@ -1557,6 +1557,7 @@ static hipError_t launch_stream(const StreamArgs& a, int grid, hipStream_t s, hi
 }
 hipError_t launch_first_argmax(const StreamArgs& a, int grid, hipStream_t s, bool unweighted, hipEvent_t* ev,
                                long long nnz) {
+  if (a.c.graphs > 1 && a.in.csr_rp && !unweighted) return launch_first_csr(a, grid, s, false, ev);  // a batch
   if (a.c.graphs == 1 && a.in.csr_rp) {
     if (unweighted) {
       const bool vec_ok = ((unsigned long long)a.in.col & 15ull) == 0ull && nnz >= first_unw_min_entries();

@@ -316,7 +316,8 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
 
   // resident workgroups per CU of the kernels this solve uses
   const int bs = unweighted ? bpc_stream_u : bpc_stream;
-  const int bf = csr1 ? (unweighted ? bpc_first_unw : bpc_first_csr) : (unweighted ? bpc_first_u : bpc_first);
+  // (the weighted first argmax reads R_1 from the CSR for a batch too)
+  const int bf = unweighted ? (csr1 ? bpc_first_unw : bpc_first_u) : bpc_first_csr;
   const int bl = unweighted ? bpc_late_u : bpc_late;
   const int pcap = std::max(1, std::min(kMaxBlocks, num_cus * std::max(1, std::min(tun.grid_per_cu, bs))));
   // R_1 feeds the first argmax and the first compaction, each split to its
@@ -437,6 +438,10 @@ lm_status Solver::run(const Problem& p, const Work& wk, hipStream_t s, uint32_t 
     std::memset(&sa, 0, sizeof(sa));
     sa.c = c;
     sa.in = live(1);
+    // a weighted batch's first argmax also reads R_1 from the input CSR (the
+    // union of the graphs; the kernel looks up each row's graph), while the
+    // other kernels read its piece records
+    if (!csr1 && !unweighted) sa.in.csr_rp = p.row_ptr;
     sa.parts = wk.parts;
     sa.bstat = wk.bstat;
     sa.cand_phase = 1;
