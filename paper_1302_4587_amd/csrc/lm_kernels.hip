@@ -283,11 +283,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
   const Ctl prev = a.ctl_prev ? *a.ctl_prev : Ctl{0, 0, 0, 0, 0, 0, 0};
   // ranges of the launch being fixed: the first argmax may split R_1 its own way
   const int Pfix = (a.first && prev.Pf > 0) ? prev.Pf : prev.P;
-  // Everything read from the kernels before is loaded here, before the first
-  // barrier, so that the round trips overlap: the lane's first cut-row part,
-  // the run table, the per-run live rows, the per-workgroup matched counts and
-  // skipped entries, and (lane 0) the running totals. None of it is written
-  // by this kernel before it is used.
+  // The run table, the per-run live rows, the per-workgroup matched counts and
+  // skipped entries, and (lane 0) the running totals are loaded here, before
+  // the first barrier, so that the round trips overlap (the cut-row parts
+  // follow in groups). None of it is written by this kernel before it is used.
   constexpr int kPer = kMaxBlocks / kPlanThreads;  // runs per lane in the scan
   const int nr = (a.mode & kPlanPrefix) ? (a.nruns_new >= 0 ? a.nruns_new : prev.P) : 0;
   long long le[kPer];
@@ -306,13 +305,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
     }
   }
   long long mc = 0, ml = 0;
-  if (a.mode & kPlanLog) {
-    for (int b = tid; b < prev.Pm; b += kPlanThreads) mc += a.mcount[b];
-    for (int b = tid; b < prev.P; b += kPlanThreads) ml += a.bstat[b].matched_len;
+  if (a.mode & kPlanLog) {  // (Pm, P <= kMaxBlocks: every load is issued before any is used)
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int b = tid + i * kPlanThreads;
+      if (b < prev.Pm) mc += a.mcount[b];
+      if (b < prev.P) ml += a.bstat[b].matched_len;
+    }
   }
-  Part pl0;
-  pl0.v = -1;
-  if ((a.mode & kPlanFix) && tid < Pfix) pl0 = a.parts[2 * tid + 1];
   Totals tot;  // lane 0: the totals as the kernels before left them
   if (tid == 0) {
     tot = *a.c.totals;
@@ -323,33 +323,56 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(PlanArgs a) {
   __syncthreads();
   if (s_err) return;
   if (a.mode & kPlanFix) {
-    for (int b = tid; b < Pfix; b += kPlanThreads) {
-      const Part pl = b == tid ? pl0 : a.parts[2 * b + 1];
-      if (pl.v < 0) continue;  // block b does not own a cut row
-      Key best;
-      best.w = pl.w;
-      best.hhi = pl.hhi;
-      best.hlo = pl.hlo;
-      best.u = pl.u;
-      int head_row = pl.kept > 0 ? pl.out_row : -1;
-      int pieces = pl.out_row >= 0 ? 1 : 0;
-      for (int b2 = b + 1; b2 < Pfix; ++b2) {
-        const Part pf = a.parts[2 * b2];
-        if (pf.v != pl.v) break;  // defensive: the chain always continues here
-        Key k;
-        k.w = pf.w;
-        k.hhi = pf.hhi;
-        k.hlo = pf.hlo;
-        k.u = pf.u;
-        best = key_max(best, k);
-        if (pf.out_row >= 0) ++pieces;
-        if (head_row < 0 && pf.kept > 0) head_row = pf.out_row;
-        if (!(pf.flags & kPartSingle)) break;
+    // kFixG of the lane's ranges at a time: their parts (the last one of range
+    // b and the first one of range b + 1, where a cut row continues) are all
+    // loaded before any is used, so a chain of one step costs one round trip
+    // per group; longer chains (rows over several ranges) load on.
+    constexpr int kFixG = 4;
+    Part none;
+    none.v = -1;
+    for (int b0 = tid; b0 < Pfix; b0 += kFixG * kPlanThreads) {
+      Part plg[kFixG], pfg[kFixG];
+#pragma unroll
+      for (int g = 0; g < kFixG; ++g) {
+        const int b = b0 + g * kPlanThreads;
+        plg[g] = none;
+        pfg[g] = none;
+        if (b < Pfix) {
+          plg[g] = a.parts[2 * b + 1];
+          if (b + 1 < Pfix) pfg[g] = a.parts[2 * (b + 1)];
+        }
       }
-      if (best.u >= 0) a.c.C[pl.v] = best.u;
-      if (!a.first) {
-        if (head_row >= 0) a.rows_out[head_row].w |= kHeadBit;
-        if (pieces > 1) atomicAdd(&s_extra, pieces - 1);
+#pragma unroll
+      for (int g = 0; g < kFixG; ++g) {
+        const int b = b0 + g * kPlanThreads;
+        const Part pl = plg[g];
+        if (pl.v < 0) continue;  // block b does not own a cut row
+        Key best;
+        best.w = pl.w;
+        best.hhi = pl.hhi;
+        best.hlo = pl.hlo;
+        best.u = pl.u;
+        int head_row = pl.kept > 0 ? pl.out_row : -1;
+        int pieces = pl.out_row >= 0 ? 1 : 0;
+        Part pf = pfg[g];
+        for (int b2 = b + 1; b2 < Pfix; ++b2) {
+          if (b2 > b + 1) pf = a.parts[2 * b2];
+          if (pf.v != pl.v) break;  // defensive: the chain always continues here
+          Key k;
+          k.w = pf.w;
+          k.hhi = pf.hhi;
+          k.hlo = pf.hlo;
+          k.u = pf.u;
+          best = key_max(best, k);
+          if (pf.out_row >= 0) ++pieces;
+          if (head_row < 0 && pf.kept > 0) head_row = pf.out_row;
+          if (!(pf.flags & kPartSingle)) break;
+        }
+        if (best.u >= 0) a.c.C[pl.v] = best.u;
+        if (!a.first) {
+          if (head_row >= 0) atomicOr(&a.rows_out[head_row].w, kHeadBit);  // (no value returned: no wait)
+          if (pieces > 1) atomicAdd(&s_extra, pieces - 1);
+        }
       }
     }
   }

@@ -441,6 +441,54 @@ def test_unweighted_empty_rows(ctx, torch_dev):
         ctx.set_tuning(**base)
 
 
+def test_unweighted_first_compaction(ctx, torch_dev):
+    """With no hand-over to the tail kernel, the compaction of phase 1 of one
+    unweighted graph runs over R_1 read from the CSR (empty rows as pieces of
+    length 0, matched rows skipped unloaded) even for small graphs:
+    power-law, star, geometric and uniform graphs, runs of empty rows, an
+    entry array that is not 16-byte aligned, and range sizes that cut rows at
+    many places. Every solve, phase log included, equals the oracle on the
+    same graph with unit weights."""
+    import torch
+    dense = lmgen.er(3000, 40000, seed=4, weights="unit")
+    lo, hi, _ = ref.undirected_edges(dense)
+    cases = [("rmat 14", lmgen.rmat(14, 16, seed=3)), ("rmat 13 seed 8", lmgen.rmat(13, 16, seed=8)),
+             ("star 5000", _unit(_star(5000, unit=True))), ("rgg 30000", _unit(lmgen.rgg(30000, 10.0, seed=9))),
+             ("er 20000", lmgen.er(20000, 160000, seed=7, weights="unit"))]
+    for k in (2, 100):
+        cases.append((f"ids x{k}", lmgen.from_edges(3000 * k, np.stack([k * lo, k * hi], 1), np.ones(len(lo)))))
+    lo2 = np.concatenate([lo, lo + 200000]).astype(np.int64)
+    hi2 = np.concatenate([hi, hi + 200000]).astype(np.int64)
+    cases.append(("empty stretch", lmgen.from_edges(203000, np.stack([lo2, hi2], 1), np.ones(len(lo2)))))
+    rng = np.random.default_rng(33)
+    for it in range(6):
+        n = int(rng.integers(2, 3000))
+        m = int(rng.integers(0, min(n * (n - 1) // 2, 12 * n) + 1))
+        cases.append((f"er it={it} n={n} m={m}", lmgen.er(n, m, int(rng.integers(1, 2**62)), weights="unit")))
+    base = ctx.tuning()
+    try:
+        for name, g in cases:
+            rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr)).to(torch_dev)
+            col = torch.from_numpy(np.ascontiguousarray(g.col)).to(torch_dev)
+            for be in (None, 2048, 65536):
+                if be is None:
+                    ctx.set_tuning(**{**base, "tail_entries": 0})
+                else:
+                    ctx.set_tuning(**{**base, "tail_entries": 0, "block_entries": be, "grid_per_cu": 1})
+                print(f"case: unweighted first compaction {name} block_entries={be}", flush=True)
+                mate, st = ctx.match(rp, col, None, seed=5)
+                _assert_parity(_unit(g), 5, mate.cpu().numpy(), st, f"first compaction {name} {be}")
+        big = lmgen.rmat(13, 16, seed=6)
+        colx = torch.zeros(big.nnz + 1, dtype=torch.int32, device=torch_dev)
+        colx[1:] = torch.from_numpy(big.col).to(torch_dev)
+        ctx.set_tuning(**{**base, "tail_entries": 0})
+        print("case: unweighted first compaction, unaligned col", flush=True)
+        mate, st = ctx.match(torch.from_numpy(big.row_ptr).to(torch_dev), colx[1:], None, seed=3)
+        _assert_parity(_unit(big), 3, mate.cpu().numpy(), st, "first compaction unaligned col")
+    finally:
+        ctx.set_tuning(**base)
+
+
 def _weight_tol(abs_sum, edges, exact):
     # Any order of 2|M| double additions (each matched edge from both ends,
     # then halved exactly) is within (2|M| - 1) 2^-53 sum|w| of the exact sum;
