@@ -177,6 +177,42 @@ __global__ __launch_bounds__(kCTopThreads) void k_c_scan_top(long long* v, long 
   if (threadIdx.x == 0) *total = carry;
 }
 
+// In-place exclusive scan of a long array in three steps: per-workgroup sums
+// of kSBlock consecutive values (k_c_scan_sums), the one-workgroup scan of
+// those sums (k_c_scan_top), and each workgroup's scan from its prefix
+// (k_c_scan_apply). A lane takes kSI consecutive values.
+constexpr int kSI = 8;
+constexpr int kSBlock = kBlock * kSI;
+
+__global__ __launch_bounds__(kBlock) void k_c_scan_sums(const long long* v, long long m, long long* bs) {
+  __shared__ long long sm[kWaves];
+  const long long i0 = (long long)blockIdx.x * kSBlock + (long long)threadIdx.x * kSI;
+  long long x = 0;
+#pragma unroll
+  for (int j = 0; j < kSI; ++j) x += i0 + j < m ? v[i0 + j] : 0ll;
+  long long tot;
+  (void)block_excl_sum<long long>(x, sm, tot);
+  if (threadIdx.x == 0) bs[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_c_scan_apply(long long* v, long long m, const long long* bs) {
+  __shared__ long long sm[kWaves];
+  const long long i0 = (long long)blockIdx.x * kSBlock + (long long)threadIdx.x * kSI;
+  long long x[kSI], s = 0;
+#pragma unroll
+  for (int j = 0; j < kSI; ++j) {
+    x[j] = i0 + j < m ? v[i0 + j] : 0ll;
+    s += x[j];
+  }
+  long long tot;
+  long long run = bs[blockIdx.x] + block_excl_sum<long long>(s, sm, tot);
+#pragma unroll
+  for (int j = 0; j < kSI; ++j) {
+    if (i0 + j < m) v[i0 + j] = run;
+    run += x[j];
+  }
+}
+
 // Exclusive prefix, in index order, of the kCBlockV values a block staged in
 // val[] (value of index base + i * kBlock + lane at val[i * kBlock + lane]):
 // every lane sums kCV consecutive values, the lanes are scanned, and val[]
@@ -889,46 +925,84 @@ __global__ __launch_bounds__(kBlock) void k_c_copy(CArgs a, long long per_wg) {
   }
 }
 
-// (3a) Offsets of the long rows' entries and tables, one workgroup.
-__global__ __launch_bounds__(kCTopThreads) void k_c_long_prep(CArgs a) {
-  __shared__ long long sm[kCTopThreads / 64];
+// (3a') Sizes of the long rows: entries (their bound), table slots (the
+// power of two at least twice the bound), buckets and chunks, and the
+// offsets of each in row order. Workgroup g sums kLPRows rows
+// (k_c_long_sums), one scan over the workgroup sums per quantity gives the
+// totals (k_c_scan_top), and each workgroup writes its rows' offsets from its
+// prefix (k_c_long_offs). The grid covers the row capacity; workgroups past
+// the long rows counted write zero sums.
+constexpr int kLP = 4;                 // long rows per lane in the prep kernels
+constexpr int kLPRows = kBlock * kLP;  // long rows per workgroup
+
+__device__ __forceinline__ void long_row_sizes(long long ub, int& bits, long long v[4]) {
+  const long long t = 2 * ub;
+  bits = t <= 2 ? 1 : 64 - __clzll((unsigned long long)(t - 1));  // smallest bits >= 1 with 2^bits >= 2 ub
+  v[0] = ub;
+  v[1] = 1ll << bits;
+  v[2] = (ub + kLB - 1) / kLB;
+  v[3] = (ub + kLC - 1) / kLC;
+}
+
+__global__ __launch_bounds__(kBlock) void k_c_long_sums(CArgs a, long long* lsum, long long nblk) {
+  __shared__ long long sm[kWaves];
+  const long long nl = a.tot->err ? 0 : (a.tot->nlong < a.lrow_cap ? a.tot->nlong : a.lrow_cap);
+  long long su[4] = {0, 0, 0, 0};
+  const long long i0 = (long long)blockIdx.x * kLPRows + (long long)threadIdx.x * kLP;
+#pragma unroll
+  for (int j = 0; j < kLP; ++j) {
+    if (i0 + j >= nl) continue;
+    int bits;
+    long long v[4];
+    long_row_sizes(a.lrows[i0 + j].ub, bits, v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) su[q] += v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    long long tot;
+    (void)block_excl_sum<long long>(su[q], sm, tot);
+    if (threadIdx.x == 0) lsum[q * nblk + blockIdx.x] = tot;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_c_long_offs(CArgs a, const long long* lsum, long long nblk) {
+  __shared__ long long sm[kWaves];
   if (a.tot->err) return;
   const long long nl = a.tot->nlong < a.lrow_cap ? a.tot->nlong : a.lrow_cap;
-  long long ce = 0, cs = 0, cb = 0, cc = 0;
-  for (long long base = 0; base < nl; base += kCTopThreads) {
-    const long long i = base + threadIdx.x;
-    long long ub = 0, slots = 0, nb = 0, nc = 0;
-    int bits = 1;
-    if (i < nl) {
-      ub = a.lrows[i].ub;
-      while ((1ll << bits) < 2 * ub) ++bits;
-      slots = 1ll << bits;
-      nb = (ub + kLB - 1) / kLB;
-      nc = (ub + kLC - 1) / kLC;
-    }
-    long long te, ts, tb, tc;
-    const long long ee = top_excl_sum(ub, sm, te);
-    const long long es = top_excl_sum(slots, sm, ts);
-    const long long eb = top_excl_sum(nb, sm, tb);
-    const long long ec = top_excl_sum(nc, sm, tc);
-    if (i < nl) {
-      a.lrows[i].eoff = ce + ee;
-      a.lrows[i].toff = cs + es;
-      a.lrows[i].tbits = bits;
-      a.lrows[i].nb = (int)nb;
-      a.lrows[i].boff = cb + eb;
-      a.lrows[i].coff = cc + ec;
-    }
-    ce += te;
-    cs += ts;
-    cb += tb;
-    cc += tc;
+  if ((long long)blockIdx.x * kLPRows >= nl) return;  // (uniform)
+  const long long i0 = (long long)blockIdx.x * kLPRows + (long long)threadIdx.x * kLP;
+  int bits[kLP];
+  long long v[kLP][4];
+  long long su[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < kLP; ++j) {
+    bits[j] = 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[j][q] = 0;
+    if (i0 + j < nl) long_row_sizes(a.lrows[i0 + j].ub, bits[j], v[j]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) su[q] += v[j][q];
   }
-  if (threadIdx.x == 0) {
-    a.tot->long_entries = ce;
-    a.tot->long_slots = cs;
-    a.tot->long_buckets = cb;
-    a.tot->long_chunks = cc;
+  long long off[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    long long tot;
+    off[q] = lsum[q * nblk + blockIdx.x] + block_excl_sum<long long>(su[q], sm, tot);
+  }
+#pragma unroll
+  for (int j = 0; j < kLP; ++j) {
+    if (i0 + j < nl) {
+      LongRow& L = a.lrows[i0 + j];
+      L.eoff = off[0];
+      L.toff = off[1];
+      L.tbits = bits[j];
+      L.nb = (int)v[j][2];
+      L.boff = off[2];
+      L.coff = off[3];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) off[q] += v[j][q];
   }
 }
 
@@ -1137,20 +1211,18 @@ struct ChunkSmem {
   int hist[kLHist];      // per bucket of the row: entries of the chunk, then their first record
   unsigned erec[kLC];    // per chunk entry: bucket << 13 | rank in the bucket within the chunk
   int row;
+  int lb;
 };
 static_assert(kLC <= (1 << 13) && kLHist <= (1 << 19), "bucket and rank fit the packed word");
 
-// The row of long-row chunk c (largest coff <= c), found by thread 0.
-__device__ __forceinline__ int chunk_row(const CArgs& a, long long nl, long long c) {
-  long long lo = 0, hi = nl;
-  while (hi - lo > 1) {
-    const long long mid = (lo + hi) >> 1;
-    if (a.lrows[mid].coff <= c)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return (int)lo;
+// Workgroup g of G takes the contiguous items [m g / G, m (g + 1) / G) (chunks
+// or buckets, in row order), so the row of each item is found by walking on
+// from the row of the one before (one step at most, mostly none); the first
+// item's row comes from one 256-way search over the long rows. Every lane
+// calls it.
+template <typename Off>
+__device__ __forceinline__ long long first_item_row(long long nl, long long c0, Off off, int* sm) {
+  return block_lower_bound(0, nl, [&](long long i) { return off(i) > c0; }, sm) - 1;  // largest off <= c0
 }
 
 // (3b') Maps every long-row entry (its coarse neighbour into next[k], -1 for
@@ -1166,8 +1238,20 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_count(CArgs a, long long nl, lo
   __shared__ CountSmem sm;
   unsigned err = 0;
   const int tid = threadIdx.x;
+  // chunks taken in strides: those of rows counted in device memory come in
+  // runs, which contiguous ranges would leave to a few workgroups
   for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    if (tid == 0) sm.row = chunk_row(a, nl, c);
+    if (tid == 0) {  // the row: largest coff <= c
+      long long lo = 0, hi = nl;
+      while (hi - lo > 1) {
+        const long long mid = (lo + hi) >> 1;
+        if (a.lrows[mid].coff <= c)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      sm.row = (int)lo;
+    }
     __syncthreads();
     const LongRow L = a.lrows[sm.row];
     const bool lds = L.nb <= kLHist;
@@ -1225,8 +1309,14 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_count(CArgs a, long long nl, lo
 __global__ __launch_bounds__(kBlock) void k_c_lb_scatter(CArgs a, long long nl, long long nchunks) {
   __shared__ ChunkSmem sm;
   const int tid = threadIdx.x;
-  for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    if (tid == 0) sm.row = chunk_row(a, nl, c);
+  const long long c0 = nchunks * blockIdx.x / gridDim.x, c1 = nchunks * (blockIdx.x + 1) / gridDim.x;
+  if (c0 >= c1) return;  // (uniform)
+  long long row = first_item_row(nl, c0, [&](long long i) { return a.lrows[i].coff; }, &sm.lb);
+  for (long long c = c0; c < c1; ++c) {
+    if (tid == 0) {
+      while (row + 1 < nl && a.lrows[row + 1].coff <= c) ++row;
+      sm.row = (int)row;
+    }
     __syncthreads();
     const LongRow L = a.lrows[sm.row];
     const bool lds = L.nb <= kLHist;
@@ -1291,6 +1381,7 @@ struct BucketSmem {
   short eslot[kLBCap];
   int kept[2];
   int row;
+  int lb;
 };
 
 // (3d') Groups every bucket in LDS, one workgroup per bucket at a time: the
@@ -1305,7 +1396,9 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, lo
     sm.shead[i] = -1;
   }
   unsigned err = 0;
-  for (long long b = blockIdx.x; b < nbk; b += gridDim.x) {
+  const long long b0 = nbk * blockIdx.x / gridDim.x, b1 = nbk * (blockIdx.x + 1) / gridDim.x;
+  long long row = b0 < b1 ? first_item_row(nl, b0, [&](long long i) { return a.lrows[i].boff; }, &sm.lb) : 0;
+  for (long long b = b0; b < b1; ++b) {
     const long long s0 = a.bstart[b], s1 = a.bstart[b + 1];
     const int ne = (int)(s1 - s0);
     if (ne == 0) continue;  // uniform
@@ -1313,16 +1406,9 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, lo
       if (tid == 0) atomicOr(&a.tot->overflow, 1u);
       continue;
     }
-    if (tid == 0) {
-      long long lo = 0, hi = nl;  // the row: largest boff <= b
-      while (hi - lo > 1) {
-        const long long mid = (lo + hi) >> 1;
-        if (a.lrows[mid].boff <= b)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      sm.row = (int)lo;
+    if (tid == 0) {  // the row: largest boff <= b
+      while (row + 1 < nl && a.lrows[row + 1].boff <= b) ++row;
+      sm.row = (int)row;
       sm.kept[0] = sm.kept[1] = 0;
     }
     __syncthreads();
@@ -1498,9 +1584,36 @@ size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// The long rows' sizes and offsets (k_c_long_sums, four top scans, k_c_long_offs)
+// over a grid that covers lrow_cap rows; lsum holds 4 * long_prep_blocks(lrow_cap).
+static long long long_prep_blocks(long long lrow_cap) { return std::max<long long>(1, (lrow_cap + kLPRows - 1) / kLPRows); }
+static void launch_long_prep(const CArgs& a, long long* lsum, hipStream_t s) {
+  const long long nblk = long_prep_blocks(a.lrow_cap);
+  hipLaunchKernelGGL(k_c_long_sums, dim3((unsigned)nblk), dim3(kBlock), 0, s, a, lsum, nblk);
+  long long* totals[4] = {&a.tot->long_entries, &a.tot->long_slots, &a.tot->long_buckets, &a.tot->long_chunks};
+  for (int q = 0; q < 4; ++q)
+    hipLaunchKernelGGL(k_c_scan_top, dim3(1), dim3(kCTopThreads), 0, s, lsum + q * nblk, nblk, totals[q]);
+  hipLaunchKernelGGL(k_c_long_offs, dim3((unsigned)nblk), dim3(kBlock), 0, s, a, (const long long*)lsum, nblk);
+}
+
+// Exclusive scan of v[0, m) in place, its total to *total. Arrays above one
+// top-scan round's worth take the three-step scan, with the workgroup sums
+// in tmp (tmp_cap values; the one-workgroup scan when they would not fit).
+static void launch_scan(long long* v, long long m, long long* total, long long* tmp, long long tmp_cap,
+                        hipStream_t s) {
+  const long long nb = (m + kSBlock - 1) / kSBlock;
+  if (m <= 8 * kCTopThreads || nb > tmp_cap) {
+    hipLaunchKernelGGL(k_c_scan_top, dim3(1), dim3(kCTopThreads), 0, s, v, m, total);
+    return;
+  }
+  hipLaunchKernelGGL(k_c_scan_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, (const long long*)v, m, tmp);
+  hipLaunchKernelGGL(k_c_scan_top, dim3(1), dim3(kCTopThreads), 0, s, tmp, nb, total);
+  hipLaunchKernelGGL(k_c_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, v, m, (const long long*)tmp);
+}
+
 // Buffers of the contraction, kept in the context between calls.
 struct ContractState {
-  DevBuf bsum, tot, crep, cnt, scr, next, lrows, table, bstart, bfill, rec;
+  DevBuf bsum, tot, crep, cnt, scr, next, lrows, table, bstart, bfill, rec, lsum;
   DevBuf in_rp, in_col, in_w, in_mate, in_vw, o_cmap, o_crp, o_ccol, o_cw, o_cvw;
   CTot* h_tot = nullptr;
 };
@@ -1510,7 +1623,8 @@ void contract_release(Solver& S) {
   if (!cs) return;
   DevBuf* all[] = {&cs->bsum,  &cs->tot,    &cs->crep,  &cs->cnt,  &cs->scr,     &cs->next,  &cs->lrows,
                    &cs->table, &cs->bstart, &cs->bfill, &cs->rec,  &cs->in_rp,   &cs->in_col, &cs->in_w,
-                   &cs->in_mate, &cs->in_vw, &cs->o_cmap, &cs->o_crp, &cs->o_ccol, &cs->o_cw, &cs->o_cvw};
+                   &cs->in_mate, &cs->in_vw, &cs->o_cmap, &cs->o_crp, &cs->o_ccol, &cs->o_cw, &cs->o_cvw,
+                   &cs->lsum};
   for (DevBuf* b : all) S.pool.release(*b);
   if (cs->h_tot) (void)hipHostFree(cs->h_tot);
   delete cs;
@@ -1538,6 +1652,7 @@ lm_status check_row_duplicates(Solver& S, int64_t n, int64_t nnz, const long lon
   if ((rs = P.reserve(cs.bsum, a256(sizeof(long long) * (size_t)(nb_v + 1)))) != LM_OK) return rs;
   if ((rs = P.reserve(cs.tot, a256(sizeof(CTot)))) != LM_OK) return rs;
   if ((rs = P.reserve(cs.lrows, a256(sizeof(LongRow) * (size_t)lrow_cap))) != LM_OK) return rs;
+  if ((rs = P.reserve(cs.lsum, a256(sizeof(long long) * 4 * (size_t)long_prep_blocks(lrow_cap)))) != LM_OK) return rs;
   CArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = n;
@@ -1557,7 +1672,7 @@ lm_status check_row_duplicates(Solver& S, int64_t n, int64_t nnz, const long lon
   grid = std::max<long long>(1, std::min<long long>(grid, (cost + 2 * kCT - 1) / (2 * kCT)));
   hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)grid), dim3(kBlock), 0, s, a, (cost + grid - 1) / grid);
   hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, (cost + grid - 1) / grid);
-  hipLaunchKernelGGL(k_c_long_prep, dim3(1), dim3(kCTopThreads), 0, s, a);
+  launch_long_prep(a, (long long*)cs.lsum.p, s);
   if (hipGetLastError() != hipSuccess) return LM_EDEVICE;
   if (hipMemcpyAsync(cs.h_tot, a.tot, sizeof(CTot), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -1646,6 +1761,7 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
   LMC_TRY(P.reserve(cs.cnt, a256(sizeof(int) * (size_t)n)));
   LMC_TRY(P.reserve(cs.scr, a256(sizeof(int2) * (size_t)(nnz > 0 ? nnz : 1))));
   LMC_TRY(P.reserve(cs.lrows, a256(sizeof(LongRow) * (size_t)lrow_cap)));
+  LMC_TRY(P.reserve(cs.lsum, a256(sizeof(long long) * 4 * (size_t)long_prep_blocks(lrow_cap))));
 
   CArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -1724,7 +1840,7 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
   const long long per_wg = (cost + grid - 1) / grid;
   hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
   hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
-  hipLaunchKernelGGL(k_c_long_prep, dim3(1), dim3(kCTopThreads), 0, s, a);
+  launch_long_prep(a, (long long*)cs.lsum.p, s);
   LMC_HIP(hipGetLastError());
   LMC_HIP(hipMemcpyAsync(cs.h_tot, a.tot, sizeof(CTot), hipMemcpyDeviceToHost, s));
   LMC_HIP(hipStreamSynchronize(s));
@@ -1753,7 +1869,8 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
     const long long nch = t1.long_chunks;
     const long long cgd = std::max<long long>(1, std::min<long long>(nch, (long long)S.num_cus * 8));
     hipLaunchKernelGGL(k_c_lb_count, dim3((unsigned)cgd), dim3(kBlock), 0, s, a, nl, nch);
-    hipLaunchKernelGGL(k_c_scan_top, dim3(1), dim3(kCTopThreads), 0, s, a.bstart, nbk + 1, &a.tot->long_kept);
+    // (lsum is free again: the long rows' offsets are written)
+    launch_scan(a.bstart, nbk + 1, &a.tot->long_kept, (long long*)cs.lsum.p, 4 * long_prep_blocks(lrow_cap), s);
     hipLaunchKernelGGL(k_c_lb_scatter, dim3((unsigned)cgd), dim3(kBlock), 0, s, a, nl, nch);
     const long long gg = std::max<long long>(1, std::min<long long>(nbk, (long long)S.num_cus * 8));
     hipLaunchKernelGGL(k_c_lb_group, dim3((unsigned)gg), dim3(kBlock), 0, s, a, nl, nbk);
