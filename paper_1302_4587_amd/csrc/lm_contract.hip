@@ -1398,8 +1398,17 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, lo
   unsigned err = 0;
   const long long b0 = nbk * blockIdx.x / gridDim.x, b1 = nbk * (blockIdx.x + 1) / gridDim.x;
   long long row = b0 < b1 ? first_item_row(nl, b0, [&](long long i) { return a.lrows[i].boff; }, &sm.lb) : 0;
+  // Consecutive buckets mostly share a row: its record and row offsets are
+  // reloaded only when the row changes, the next row's first bucket only when
+  // it is passed (thread 0), and a bucket's start is the previous one's end.
+  long long next_boff = row + 1 < nl ? a.lrows[row + 1].boff : nbk;
+  int cur = -1;
+  LongRow L;
+  long long ka = 0, kb = 0;
+  long long s1n = b0 < b1 ? a.bstart[b0] : 0;
   for (long long b = b0; b < b1; ++b) {
-    const long long s0 = a.bstart[b], s1 = a.bstart[b + 1];
+    const long long s0 = s1n, s1 = a.bstart[b + 1];
+    s1n = s1;
     const int ne = (int)(s1 - s0);
     if (ne == 0) continue;  // uniform
     if (ne > kLBCap) {
@@ -1407,14 +1416,20 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, lo
       continue;
     }
     if (tid == 0) {  // the row: largest boff <= b
-      while (row + 1 < nl && a.lrows[row + 1].boff <= b) ++row;
+      while (next_boff <= b) {
+        ++row;
+        next_boff = row + 1 < nl ? a.lrows[row + 1].boff : nbk;
+      }
       sm.row = (int)row;
       sm.kept[0] = sm.kept[1] = 0;
     }
     __syncthreads();
-    const LongRow L = a.lrows[sm.row];
-    const long long ka = a.rp[L.a];
-    const long long kb = L.b >= 0 ? a.rp[L.b] : 0;
+    if (sm.row != cur) {  // (uniform)
+      cur = sm.row;
+      L = a.lrows[cur];
+      ka = a.rp[L.a];
+      kb = L.b >= 0 ? a.rp[L.b] : 0;
+    }
     for (int q = tid; q < ne; q += kBlock) {
       const int k = a.rec[s0 + q];
       const int D = a.next[k];
