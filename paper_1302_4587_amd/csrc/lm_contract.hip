@@ -1371,10 +1371,11 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_scatter(CArgs a, long long nl, 
   }
 }
 
+// (an entry's index is not kept: it follows from its position in the row
+// and the row's two offsets, which keeps five workgroups resident per CU)
 struct BucketSmem {
   int skey[2 * kLBCap];
   int shead[2 * kLBCap];
-  int ek[kLBCap];
   int epos[kLBCap];
   int eD[kLBCap];
   short enext[kLBCap];
@@ -1434,7 +1435,6 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, lo
       const int k = a.rec[s0 + q];
       const int D = a.next[k];
       const bool pa = (long long)k >= ka && (long long)k < ka + L.dega;
-      sm.ek[q] = k;
       sm.epos[q] = pa ? (int)(k - ka) : L.dega + (int)(k - kb);
       sm.eD[q] = D;
       const unsigned h0 = (unsigned)D * 0x85EBCA77u;
@@ -1448,9 +1448,10 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, lo
       sm.enext[q] = (short)atomicExch(&sm.shead[hh], q);
     }
     __syncthreads();
+    auto entry_of = [&](int pos) { return (int)(pos < L.dega ? ka + pos : kb + (pos - L.dega)); };
     for (int q = tid; q < ne; q += kBlock) {
-      const int k = sm.ek[q];
       const int my = sm.epos[q];
+      const int k = entry_of(my);
       int lst[kCMaxDup + 1];
       int nlst = 0;
       int p = sm.shead[sm.eslot[q]];
@@ -1481,7 +1482,7 @@ __global__ __launch_bounds__(kBlock) void k_c_lb_group(CArgs a, long long nl, lo
           wv[t] = 0.f;
           if (t >= nlst) continue;
           const int pp = lst[t];
-          const int kp = sm.ek[pp];
+          const int kp = entry_of(sm.epos[pp]);
           const int sp = sm.epos[pp] < L.dega ? L.a : L.b;
           ord[t] = edge_order(sp, a.col[kp]);
           wv[t] = a.w ? a.w[kp] : 1.0f;
@@ -1584,6 +1585,15 @@ __global__ __launch_bounds__(kBlock) void k_c_long_pack(CArgs a, long long nl) {
       dest += tot;
     }
   }
+}
+
+int lb_group_blocks_per_cu() {
+  static int cached = 0;
+  if (cached) return cached;
+  int nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_c_lb_group, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  cached = nb;
+  return nb;
 }
 
 int tile_blocks_per_cu() {
@@ -1887,7 +1897,8 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
     // (lsum is free again: the long rows' offsets are written)
     launch_scan(a.bstart, nbk + 1, &a.tot->long_kept, (long long*)cs.lsum.p, 4 * long_prep_blocks(lrow_cap), s);
     hipLaunchKernelGGL(k_c_lb_scatter, dim3((unsigned)cgd), dim3(kBlock), 0, s, a, nl, nch);
-    const long long gg = std::max<long long>(1, std::min<long long>(nbk, (long long)S.num_cus * 8));
+    // every workgroup resident: each takes one contiguous range of buckets
+    const long long gg = std::max<long long>(1, std::min<long long>(nbk, (long long)S.num_cus * lb_group_blocks_per_cu()));
     hipLaunchKernelGGL(k_c_lb_group, dim3((unsigned)gg), dim3(kBlock), 0, s, a, nl, nbk);
     LMC_HIP(hipGetLastError());
     LMC_HIP(hipMemcpyAsync(cs.h_tot, a.tot, sizeof(CTot), hipMemcpyDeviceToHost, s));
