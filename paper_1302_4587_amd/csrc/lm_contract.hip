@@ -396,7 +396,7 @@ struct WaveSmem {
   int st[65];  // wave-local start of each lane's row; st[64] = the wave's total
   int ra[64], rb[64], rc[64], rdega[64], rut[64];
   int rrk[64][2];  // kept entries of the tile before the row's a part and b part
-  long long rka[64], rkb[64];
+  int rka[64], rkb[64];  // the row parts' first entries (nnz < 2^31: five workgroups fit a CU)
 };
 
 // Orders the wave's LDS accesses across lanes (a wave's LDS operations are
@@ -470,8 +470,8 @@ __global__ __launch_bounds__(kBlock) void k_c_group_wave(CArgs a, long long per_
     sm.rc[l] = h.c;
     sm.rdega[l] = h.dega;
     sm.rut[l] = ut;
-    sm.rka[l] = h.ka;
-    sm.rkb[l] = h.kb;
+    sm.rka[l] = (int)h.ka;
+    sm.rkb[l] = (int)h.kb;
     wave_sync();
     const int ntile = (U + kWStep - 1) / kWStep;
     for (int j = 0; j < ntile; ++j) {
@@ -1596,6 +1596,15 @@ int lb_group_blocks_per_cu() {
   return nb;
 }
 
+int wave_blocks_per_cu() {
+  static int cached = 0;
+  if (cached) return cached;
+  int nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_c_group_wave, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  cached = nb;
+  return nb;
+}
+
 int tile_blocks_per_cu() {
   static int cached = 0;
   if (cached) return cached;
@@ -1695,7 +1704,10 @@ lm_status check_row_duplicates(Solver& S, int64_t n, int64_t nnz, const long lon
   const long long cost = nnz + (long long)kCCost * n;
   long long grid = (long long)S.num_cus * tile_blocks_per_cu();
   grid = std::max<long long>(1, std::min<long long>(grid, (cost + 2 * kCT - 1) / (2 * kCT)));
-  hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)grid), dim3(kBlock), 0, s, a, (cost + grid - 1) / grid);
+  // (each grouping kernel takes its own resident count of workgroups)
+  const long long gw = std::max<long long>(
+      1, std::min<long long>((long long)S.num_cus * wave_blocks_per_cu(), (cost + 2 * kCT - 1) / (2 * kCT)));
+  hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)gw), dim3(kBlock), 0, s, a, (cost + gw - 1) / gw);
   hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, (cost + grid - 1) / grid);
   launch_long_prep(a, (long long*)cs.lsum.p, s);
   if (hipGetLastError() != hipSuccess) return LM_EDEVICE;
@@ -1863,7 +1875,9 @@ lm_status lm_contract(lm_ctx* ctx, const lm_csr* g, const int32_t* mate, const i
   if (grid > by_cost) grid = by_cost;
   if (grid < 1) grid = 1;
   const long long per_wg = (cost + grid - 1) / grid;
-  hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
+  // (each grouping kernel takes its own resident count of workgroups)
+  const long long gw = std::max<long long>(1, std::min<long long>((long long)S.num_cus * wave_blocks_per_cu(), by_cost));
+  hipLaunchKernelGGL(k_c_group_wave, dim3((unsigned)gw), dim3(kBlock), 0, s, a, (cost + gw - 1) / gw);
   hipLaunchKernelGGL(k_c_group, dim3((unsigned)grid), dim3(kBlock), 0, s, a, per_wg);
   launch_long_prep(a, (long long*)cs.lsum.p, s);
   LMC_HIP(hipGetLastError());
